@@ -1,0 +1,141 @@
+/*
+ * gfp.h -- C ABI of libgfpfft: FFT and polynomial multiplication over Z/pZ
+ * for a Generalized Fermat prime p = r^k + 1 on AMD MI355X (gfx950).
+ *
+ * The operations follow arXiv:1811.01490 ("Putting Furer Algorithm into
+ * Practice with the BPAS Library"):
+ *   - the field and the radix-r element encoding: section 2;
+ *   - the primitive N-th root w with w^(N/2k) = r: section 2.1, Alg. 1;
+ *   - the DFT at w, computed for N = K^e, K = 2k, with base case DFT_K at
+ *     w^(N/K) = r: section 1.1 (eq. CTCT), section 4.1 (eq. sixstepfft),
+ *     section 4.3 (Alg. DFT_general);
+ *   - the inverse transform (1/N) DFT at w^-1 and the product of two
+ *     polynomials by forward transforms, a pointwise product and an inverse
+ *     transform: section 3.3, Alg. Fast Convolution.
+ *
+ * Element encoding (section 2).  An element x of Z/pZ is k digits x_0..x_{k-1}
+ * with x = sum_d x_d r^d, every digit in [0, r), except p - 1 which is written
+ * x_{k-1} = r and all other digits 0.  This makes the encoding unique; every
+ * output of the library is in this canonical form.
+ *
+ * Vector layout.  A vector of n elements is structure-of-arrays: digit d of
+ * element i is the uint64_t at v[d * ld + i], ld >= n (row d is contiguous).
+ *
+ * Memory and streams.  Unless stated otherwise, vector pointers are device
+ * pointers (HIP device memory of the current device) owned by the caller;
+ * the library never frees them.  `stream` is a hipStream_t (NULL = the null
+ * stream).  Transform calls only enqueue work on that stream and return; the
+ * caller synchronises.  The library owns the field object, its host tables
+ * and the per-device twiddle tables (uploaded on the first transform of a
+ * size on a device, which synchronises that device once).
+ *
+ * Errors.  Every call returns GFP_OK or a GFP_E* code and never throws.
+ * Invalid arguments are rejected before any work is enqueued.  Errors of
+ * asynchronous device work surface as GFP_EDEVICE from a later call on the
+ * stream or from the caller's own synchronisation.  Inputs are assumed
+ * canonical; non-canonical digits give unspecified (but memory-safe) results.
+ */
+#ifndef GFP_H
+#define GFP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GFP_OK 0
+#define GFP_EINVAL 1       /* bad argument (null pointer, ld < n, size not allowed) */
+#define GFP_EUNSUPPORTED 2 /* field or size outside what this build implements */
+#define GFP_ENOMEM 3       /* device or host allocation failed */
+#define GFP_EAGAIN 4       /* request loop: no capacity right now */
+#define GFP_EDEVICE 5      /* HIP runtime error */
+#define GFP_ENOTPRIME 6    /* r^k + 1 failed the probable-prime test */
+#define GFP_ECANCELED 7    /* request loop: request cancelled at shutdown */
+#define GFP_EPENDING 8     /* request loop: result not ready yet */
+
+/* Elementwise operations (gfp_elementwise). */
+#define GFP_OP_ADD 0       /* z = x + y */
+#define GFP_OP_SUB 1       /* z = x - y */
+#define GFP_OP_MUL 2       /* z = x * y */
+#define GFP_OP_MUL_POW_R 3 /* z = x * r^s (section 2.3), y unused */
+#define GFP_OP_MUL_CONST 4 /* z = x * c * r^s, c = host digits passed as y_host */
+#define GFP_OP_MUL_SCALE 5 /* z = x * y * c, c = host digits passed as y_host */
+
+typedef struct gfp_field gfp_field;
+
+/* Create the field Z/pZ, p = r^k + 1 (section 2).  Host-only; touches no GPU.
+ * k must be a power of two and r even; this build runs transforms for
+ * k in {8, 16} with r = 2^w + 2^u for (k, w, u) in {(8, 63, 34), (8, 59, 16),
+ * (16, 62, 36), (16, 58, 10)} (Table 1 and Table testprimes).  p is checked
+ * with a Miller-Rabin probable-prime test (12 fixed bases).
+ * Returns GFP_EINVAL (out == NULL, bad k/r), GFP_EUNSUPPORTED (shape not
+ * compiled in), GFP_ENOTPRIME.  On success *out owns the field; release it
+ * with gfp_field_destroy. */
+int gfp_field_create(uint32_t k, uint64_t r, gfp_field** out);
+
+/* Release a field and its device tables.  The caller must ensure no work
+ * using the field is still running.  NULL is accepted. */
+int gfp_field_destroy(gfp_field* f);
+
+/* Field parameters.  log2_max_n: the largest e with 2^e | p - 1 (Table 1).
+ * Any output pointer may be NULL. */
+int gfp_field_info(const gfp_field* f, uint32_t* k, uint64_t* r, uint32_t* log2_max_n);
+
+/* Primitive n-th root of unity w_n (section 2.1, Alg. 1): n a power of two,
+ * 2k <= n <= 2^log2_max_n.  w_n^(n/2k) = r.  g in Alg. 1 is
+ * h^((p-1)/n) for the smallest quadratic non-residue h, which makes the roots
+ * nested: w_n = w_m^(m/n).  inverse != 0 returns w_n^-1.  digits: host array
+ * of k uint64_t, canonical encoding.  Host-only. */
+int gfp_root_of_unity(const gfp_field* f, uint64_t n, int inverse, uint64_t* digits);
+
+/* Transform sizes: n = K^e, K = 2k, e >= 1, n <= 2^log2_max_n and n <= 2^26.
+ * Workspace bytes needed by gfp_fft_forward / gfp_fft_inverse of size n. */
+int gfp_fft_workspace_size(const gfp_field* f, uint64_t n, uint64_t* bytes);
+
+/* Forward DFT at w_n: y_i = sum_j x_j w_n^(ij), natural order (section 1.1).
+ * x: n elements (ld_x >= n), y: n elements (ld_y >= n), device memory.
+ * x == y (same pointer and ld) is allowed.  Other overlap is not.
+ * workspace: device memory of at least gfp_fft_workspace_size bytes, or NULL
+ * to let the library take it from the stream-ordered allocator. */
+int gfp_fft_forward(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t ld_x, uint64_t* y, uint64_t ld_y,
+                    void* workspace, uint64_t ws_bytes, void* stream);
+
+/* Inverse DFT including the 1/n factor: x_j = n^-1 sum_i y_i w_n^(-ij)
+ * (section 3.3, Alg. Fast Convolution).  Same arguments as gfp_fft_forward. */
+int gfp_fft_inverse(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t ld_x, uint64_t* y, uint64_t ld_y,
+                    void* workspace, uint64_t ws_bytes, void* stream);
+
+/* Transform size used by gfp_polymul for la + lb - 1 output coefficients:
+ * the smallest K^e >= la + lb - 1 (and >= K). */
+int gfp_polymul_size(const gfp_field* f, uint64_t la, uint64_t lb, uint64_t* n);
+
+/* Workspace bytes for gfp_polymul(la, lb). */
+int gfp_polymul_workspace_size(const gfp_field* f, uint64_t la, uint64_t lb, uint64_t* bytes);
+
+/* Product c = a * b of polynomials over Z/pZ (section 3.3, Alg. Fast
+ * Convolution with zero padding so the cyclic product does not wrap):
+ * c_m = sum_{i+j=m} a_i b_j, m < la + lb - 1.  a: la coefficients (ld_a >= la),
+ * b: lb coefficients (ld_b >= lb), c: la + lb - 1 coefficients
+ * (ld_c >= la + lb - 1), device memory, c must not overlap a or b.
+ * la, lb >= 1.  Workspace as for the transforms. */
+int gfp_polymul(const gfp_field* f, const uint64_t* a, uint64_t la, uint64_t ld_a, const uint64_t* b, uint64_t lb,
+                uint64_t ld_b, uint64_t* c, uint64_t ld_c, void* workspace, uint64_t ws_bytes, void* stream);
+
+/* Elementwise z = op(x, y) on n elements (section 2: addition, subtraction,
+ * multiplication by a power of r, multiplication).  x, y, z device vectors
+ * (y unused for GFP_OP_MUL_POW_R and GFP_OP_MUL_CONST); z may equal x or y.
+ * s: the exponent for GFP_OP_MUL_POW_R / GFP_OP_MUL_CONST (any integer,
+ * taken mod 2k).  c_host: k host digits of the constant c for
+ * GFP_OP_MUL_CONST and GFP_OP_MUL_SCALE, else ignored. */
+int gfp_elementwise(const gfp_field* f, int op, const uint64_t* x, uint64_t ld_x, const uint64_t* y, uint64_t ld_y,
+                    uint64_t* z, uint64_t ld_z, uint64_t n, int64_t s, const uint64_t* c_host, void* stream);
+
+/* Static description of an error code. */
+const char* gfp_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GFP_H */

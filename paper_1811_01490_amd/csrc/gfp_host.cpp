@@ -1,0 +1,586 @@
+// Host side of libgfpfft: field setup (section 2), roots of unity (Alg. 1),
+// twiddle tables, pass scheduling and the C ABI declared in include/gfp.h.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/gfp.h"
+#include "bigint.hpp"
+#include "gfp_internal.hpp"
+
+using gfp::Big;
+using gfp::Mont;
+
+namespace {
+
+const uint64_t kMaxLog2N = 25;
+
+struct DevTables {
+  uint32_t* fwd = nullptr;  // n/K entries: w^j
+  uint32_t* inv = nullptr;  // n/K entries: w^-j
+  uint32_t* ninv = nullptr; // one entry: 1/n
+};
+
+struct DevConsts {
+  uint32_t* one = nullptr;  // one entry: 1
+};
+
+}  // namespace
+
+struct gfp_field {
+  uint32_t k = 0;
+  uint64_t r = 0;
+  int w = -1, u = -1;  // r = 2^w + 2^u when the shape is compiled in
+  bool gpu_shape = false;
+  Big p, pm1;
+  std::unique_ptr<Mont> mont;
+  uint32_t log2max = 0;
+  Big h_mont;       // smallest quadratic non-residue, Montgomery form
+  uint64_t j1 = 0;  // Alg. 1's exponent (independent of n)
+  std::mutex mu;
+  std::map<std::pair<int, uint64_t>, DevTables> tables;
+  std::map<int, DevConsts> consts;
+};
+
+namespace {
+
+int log2_exact(uint64_t n) {
+  if (n == 0 || (n & (n - 1))) return -1;
+  return __builtin_ctzll(n);
+}
+
+// Miller-Rabin to a fixed base set (host-side sanity check of p).
+bool probable_prime(const Big& n, const Mont& M) {
+  Big nm1 = gfp::sub(n, Big(1));
+  unsigned s = gfp::ctz(nm1);
+  Big d = gfp::shr(nm1, s);
+  Big minus_one = M.to(nm1);
+  static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  for (uint64_t b : bases) {
+    Big x = M.pow(M.to(Big(b)), d);
+    if (gfp::cmp(x, M.one) == 0 || gfp::cmp(x, minus_one) == 0) continue;
+    bool ok = false;
+    for (unsigned i = 1; i < s; ++i) {
+      x = M.mmul(x, x);
+      if (gfp::cmp(x, minus_one) == 0) { ok = true; break; }
+    }
+    if (!ok) return false;
+  }
+  return true;
+}
+
+// canonical radix-r digits of v (0 <= v < p)
+void to_digits(const gfp_field* f, const Big& v, uint64_t* out) {
+  if (gfp::cmp(v, f->pm1) == 0) {
+    for (uint32_t d = 0; d < f->k; ++d) out[d] = 0;
+    out[f->k - 1] = f->r;
+    return;
+  }
+  Big cur = v;
+  for (uint32_t d = 0; d < f->k; ++d) {
+    uint64_t rem;
+    cur = gfp::divmod_small(cur, f->r, &rem);
+    out[d] = rem;
+  }
+}
+
+Big from_digits(const gfp_field* f, const uint64_t* dg) {
+  Big v;
+  for (uint32_t d = f->k; d-- > 0;) v = gfp::add(gfp::mul_small(v, f->r), Big(dg[d]));
+  return gfp::mod(v, f->p);
+}
+
+// Twiddle-entry layout of the kernels: limbs (22, 22, 20 bits) of every
+// digit, then the suffix sums sum_{t >= i} y_t as three 32-bit words.
+void make_entry(uint32_t k, const uint64_t* y, uint32_t* e) {
+  for (uint32_t t = 0; t < k; ++t) {
+    e[3 * t] = (uint32_t)(y[t] & 0x3FFFFFu);
+    e[3 * t + 1] = (uint32_t)((y[t] >> 22) & 0x3FFFFFu);
+    e[3 * t + 2] = (uint32_t)(y[t] >> 44);
+  }
+  for (uint32_t i = 0; i < k; ++i) {
+    gfp::u128 s = 0;
+    for (uint32_t t = i; t < k; ++t) s += y[t];
+    e[3 * k + 3 * i] = (uint32_t)s;
+    e[3 * k + 3 * i + 1] = (uint32_t)(s >> 32);
+    e[3 * k + 3 * i + 2] = (uint32_t)(s >> 64);
+  }
+}
+
+// w_n in Montgomery form (Alg. 1 with g = h^((p-1)/n))
+Big root_mont(const gfp_field* f, uint64_t n, bool inverse) {
+  const int lg = log2_exact(n);
+  Big e = gfp::mul_small(gfp::shr(f->pm1, (unsigned)lg), f->j1);  // j (p-1)/n
+  if (inverse) {
+    // w^-1 = w^(n-1)
+    e = gfp::mul_small(e, n - 1);
+  }
+  return f->mont->pow(f->h_mont, e);
+}
+
+// host table of w^(sign j), j < cnt, in entry layout
+void build_table(const gfp_field* f, const Big& wm, uint64_t cnt, std::vector<uint32_t>& out) {
+  const int words = gfpk::tw_words((int)f->k);
+  out.assign(cnt * words, 0);
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (cnt < 4096) nth = 1;
+  const uint64_t chunk = (cnt + nth - 1) / nth;
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nth; ++t) {
+    const uint64_t lo = t * chunk, hi = std::min(cnt, lo + chunk);
+    if (lo >= hi) break;
+    th.emplace_back([&, lo, hi]() {
+      const Mont& M = *f->mont;
+      Big acc = M.pow(wm, Big(lo));
+      std::vector<uint64_t> dg(f->k);
+      for (uint64_t j = lo; j < hi; ++j) {
+        to_digits(f, M.from(acc), dg.data());
+        make_entry(f->k, dg.data(), &out[j * words]);
+        acc = M.mmul(acc, wm);
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? GFP_OK : (e == hipErrorOutOfMemory ? GFP_ENOMEM : GFP_EDEVICE); }
+
+int upload(const std::vector<uint32_t>& host, uint32_t** dev) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, host.size() * sizeof(uint32_t));
+  if (e != hipSuccess) return hip_status(e);
+  e = hipMemcpy(p, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return hip_status(e);
+  }
+  *dev = (uint32_t*)p;
+  return GFP_OK;
+}
+
+// valid transform size: n = K^e, e >= 1, within the field and the build limit
+int check_size(const gfp_field* f, uint64_t n, int* log2n, int* e) {
+  const int lg = log2_exact(n);
+  const int lk = log2_exact(2ull * f->k);
+  if (lg < 0 || lg < lk || lg % lk != 0) return GFP_EUNSUPPORTED;
+  if ((uint64_t)lg > f->log2max || (uint64_t)lg > kMaxLog2N) return GFP_EUNSUPPORTED;
+  *log2n = lg;
+  *e = lg / lk;
+  return GFP_OK;
+}
+
+int get_tables(gfp_field* f, uint64_t n, const DevTables** out) {
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return hip_status(he);
+  std::lock_guard<std::mutex> g(f->mu);
+  auto key = std::make_pair(dev, n);
+  auto it = f->tables.find(key);
+  if (it != f->tables.end()) {
+    *out = &it->second;
+    return GFP_OK;
+  }
+  const uint64_t cnt = n / (2ull * f->k);
+  DevTables t;
+  std::vector<uint32_t> host;
+  build_table(f, root_mont(f, n, false), cnt, host);
+  int rc = upload(host, &t.fwd);
+  if (rc == GFP_OK) {
+    build_table(f, root_mont(f, n, true), cnt, host);
+    rc = upload(host, &t.inv);
+  }
+  if (rc == GFP_OK) {
+    // 1/n = n^(p-2)
+    const Mont& M = *f->mont;
+    Big ninv = M.from(M.pow(M.to(Big(n)), gfp::sub(f->p, Big(2))));
+    std::vector<uint64_t> dg(f->k);
+    to_digits(f, ninv, dg.data());
+    host.assign(gfpk::tw_words((int)f->k), 0);
+    make_entry(f->k, dg.data(), host.data());
+    rc = upload(host, &t.ninv);
+  }
+  if (rc != GFP_OK) {
+    (void)hipFree(t.fwd);
+    (void)hipFree(t.inv);
+    (void)hipFree(t.ninv);
+    return rc;
+  }
+  auto ins = f->tables.emplace(key, t);
+  *out = &ins.first->second;
+  return GFP_OK;
+}
+
+int get_one(gfp_field* f, const uint32_t** out) {
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return hip_status(he);
+  std::lock_guard<std::mutex> g(f->mu);
+  auto it = f->consts.find(dev);
+  if (it != f->consts.end()) {
+    *out = it->second.one;
+    return GFP_OK;
+  }
+  std::vector<uint64_t> dg(f->k, 0);
+  dg[0] = 1;
+  std::vector<uint32_t> host(gfpk::tw_words((int)f->k));
+  make_entry(f->k, dg.data(), host.data());
+  DevConsts c;
+  int rc = upload(host, &c.one);
+  if (rc != GFP_OK) return rc;
+  f->consts[dev] = c;
+  *out = c.one;
+  return GFP_OK;
+}
+
+// Stream-ordered scratch when the caller passes no workspace.
+struct Scratch {
+  void* p = nullptr;
+  hipStream_t st = nullptr;
+  ~Scratch() {
+    if (p) (void)hipFreeAsync(p, st);
+  }
+};
+
+int get_workspace(void* ws, uint64_t ws_bytes, uint64_t need, hipStream_t st, Scratch& s, uint64_t** out) {
+  if (ws) {
+    if (ws_bytes < need) return GFP_EINVAL;
+    *out = (uint64_t*)ws;
+    return GFP_OK;
+  }
+  if (need == 0) {
+    *out = nullptr;
+    return GFP_OK;
+  }
+  hipError_t e = hipMallocAsync(&s.p, need, st);
+  if (e != hipSuccess) return hip_status(e);
+  s.st = st;
+  *out = (uint64_t*)s.p;
+  return GFP_OK;
+}
+
+// Run the e passes of a transform of size n (log2n) from X to Y.
+// Intermediate passes alternate between W1 and W2 (each n elements, ld n);
+// X is only read by pass 0.  When X == Y and e == 1 the pass writes W1 and
+// the result is copied.
+int run_transform(gfp_field* f, int log2n, int e, bool inverse, const uint64_t* X, uint64_t ldx, uint64_t* Y,
+                  uint64_t ldy, uint64_t* W1, uint64_t* W2, hipStream_t st) {
+  const uint64_t n = 1ull << log2n;
+  const DevTables* t = nullptr;
+  int rc = get_tables(f, n, &t);
+  if (rc != GFP_OK) return rc;
+  const int lk = log2_exact(2ull * f->k);
+  const bool copy_back = (e == 1 && X == Y);
+  const uint64_t* src = X;
+  uint64_t lds = ldx;
+  for (int s = 0; s < e; ++s) {
+    uint64_t* dst;
+    uint64_t ldd;
+    if (s == e - 1 && !copy_back) {
+      dst = Y;
+      ldd = ldy;
+    } else {
+      dst = (((e - 2 - s) % 2) == 0) ? W1 : W2;  // pass e-2 -> W1, e-3 -> W2, ...
+      ldd = n;
+    }
+    gfpk::PassArgs p;
+    p.in = src;
+    p.ld_in = lds;
+    p.out = dst;
+    p.ld_out = ldd;
+    p.log2n = log2n;
+    p.log2ns = s * lk;
+    p.ngroups = n >> lk;
+    p.inverse = inverse;
+    p.scale = inverse && s == 0;
+    p.tw = p.scale ? t->ninv : (inverse ? t->inv : t->fwd);
+    p.last = (s == e - 1);
+    hipError_t he = gfpk::launch_pass((int)f->k, f->w, f->u, p, st);
+    if (he != hipSuccess) return hip_status(he);
+    src = dst;
+    lds = ldd;
+  }
+  if (copy_back) {
+    hipError_t he = hipMemcpy2DAsync(Y, ldy * 8, src, lds * 8, n * 8, f->k, hipMemcpyDeviceToDevice, st);
+    if (he != hipSuccess) return hip_status(he);
+  }
+  return GFP_OK;
+}
+
+int transform_entry(const gfp_field* cf, uint64_t n, const uint64_t* x, uint64_t ldx, uint64_t* y, uint64_t ldy,
+                    void* ws, uint64_t ws_bytes, void* stream, bool inverse) {
+  gfp_field* f = const_cast<gfp_field*>(cf);
+  if (!f || !x || !y) return GFP_EINVAL;
+  if (!f->gpu_shape) return GFP_EUNSUPPORTED;
+  int log2n, e;
+  int rc = check_size(f, n, &log2n, &e);
+  if (rc != GFP_OK) return rc;
+  if (ldx < n || ldy < n) return GFP_EINVAL;
+  if (x == y && ldx != ldy) return GFP_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  Scratch s;
+  uint64_t* w = nullptr;
+  rc = get_workspace(ws, ws_bytes, 2ull * n * f->k * 8, st, s, &w);
+  if (rc != GFP_OK) return rc;
+  return run_transform(f, log2n, e, inverse, x, ldx, y, ldy, w, w + n * f->k, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int gfp_field_create(uint32_t k, uint64_t r, gfp_field** out) {
+  if (!out) return GFP_EINVAL;
+  *out = nullptr;
+  if (k < 2 || (k & (k - 1)) || k > 64 || r < 2 || (r & 1)) return GFP_EINVAL;
+  gfp_field* f = new (std::nothrow) gfp_field();
+  if (!f) return GFP_ENOMEM;
+  f->k = k;
+  f->r = r;
+  // r = 2^w + 2^u ?
+  if (__builtin_popcountll(r) == 2) {
+    f->u = __builtin_ctzll(r);
+    f->w = 63 - __builtin_clzll(r);
+  }
+  f->gpu_shape = f->w >= 0 && gfpk::shape_supported((int)k, f->w, f->u);
+  Big rk(1);
+  for (uint32_t i = 0; i < k; ++i) rk = gfp::mul_small(rk, r);
+  f->pm1 = rk;
+  f->p = gfp::add(rk, Big(1));
+  f->mont.reset(new Mont(f->p));
+  if (!probable_prime(f->p, *f->mont)) {
+    delete f;
+    return GFP_ENOTPRIME;
+  }
+  f->log2max = k * (uint32_t)__builtin_ctzll(r);  // v2(r^k)
+  // smallest quadratic non-residue h (Euler's criterion)
+  const Mont& M = *f->mont;
+  Big half = gfp::shr(f->pm1, 1);
+  Big minus_one = M.to(f->pm1);
+  uint64_t h = 2;
+  for (;; ++h) {
+    Big x = M.pow(M.to(Big(h)), half);
+    if (gfp::cmp(x, minus_one) == 0) break;
+  }
+  f->h_mont = M.to(Big(h));
+  // Alg. 1: a = g^(n/2k) = h^((p-1)/2k) for every n; smallest j with a^j = r
+  Big a = M.pow(f->h_mont, gfp::shr(f->pm1, (unsigned)__builtin_ctz(2 * k)));
+  Big rm = M.to(Big(r));
+  Big b = a;
+  uint64_t j = 1;
+  while (gfp::cmp(b, rm) != 0 && j <= 4 * k) {
+    b = M.mmul(b, a);
+    ++j;
+  }
+  if (j > 4 * k) {  // cannot happen for prime p: a and r are both primitive 2k-th roots
+    delete f;
+    return GFP_EINVAL;
+  }
+  f->j1 = j;
+  *out = f;
+  return GFP_OK;
+}
+
+int gfp_field_destroy(gfp_field* f) {
+  if (!f) return GFP_OK;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  for (auto& kv : f->tables) {
+    (void)hipSetDevice(kv.first.first);
+    (void)hipFree(kv.second.fwd);
+    (void)hipFree(kv.second.inv);
+    (void)hipFree(kv.second.ninv);
+  }
+  for (auto& kv : f->consts) {
+    (void)hipSetDevice(kv.first);
+    (void)hipFree(kv.second.one);
+  }
+  if (!f->tables.empty() || !f->consts.empty()) (void)hipSetDevice(dev);
+  delete f;
+  return GFP_OK;
+}
+
+int gfp_field_info(const gfp_field* f, uint32_t* k, uint64_t* r, uint32_t* log2_max_n) {
+  if (!f) return GFP_EINVAL;
+  if (k) *k = f->k;
+  if (r) *r = f->r;
+  if (log2_max_n) *log2_max_n = f->log2max;
+  return GFP_OK;
+}
+
+int gfp_root_of_unity(const gfp_field* f, uint64_t n, int inverse, uint64_t* digits) {
+  if (!f || !digits) return GFP_EINVAL;
+  const int lg = log2_exact(n);
+  if (lg < 0 || n < 2ull * f->k || (uint64_t)lg > f->log2max) return GFP_EINVAL;
+  Big w = f->mont->from(root_mont(f, n, inverse != 0));
+  to_digits(f, w, digits);
+  return GFP_OK;
+}
+
+int gfp_fft_workspace_size(const gfp_field* f, uint64_t n, uint64_t* bytes) {
+  if (!f || !bytes) return GFP_EINVAL;
+  int log2n, e;
+  int rc = check_size(f, n, &log2n, &e);
+  if (rc != GFP_OK) return rc;
+  *bytes = 2ull * n * f->k * 8;
+  return GFP_OK;
+}
+
+int gfp_fft_forward(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t ld_x, uint64_t* y, uint64_t ld_y,
+                    void* workspace, uint64_t ws_bytes, void* stream) {
+  return transform_entry(f, n, x, ld_x, y, ld_y, workspace, ws_bytes, stream, false);
+}
+
+int gfp_fft_inverse(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t ld_x, uint64_t* y, uint64_t ld_y,
+                    void* workspace, uint64_t ws_bytes, void* stream) {
+  return transform_entry(f, n, x, ld_x, y, ld_y, workspace, ws_bytes, stream, true);
+}
+
+int gfp_polymul_size(const gfp_field* f, uint64_t la, uint64_t lb, uint64_t* n) {
+  if (!f || !n || la == 0 || lb == 0) return GFP_EINVAL;
+  const uint64_t need = la + lb - 1;
+  uint64_t N = 2ull * f->k;
+  while (N < need) {
+    if (N > (1ull << kMaxLog2N)) return GFP_EUNSUPPORTED;
+    N *= 2ull * f->k;
+  }
+  int log2n, e;
+  int rc = check_size(f, N, &log2n, &e);
+  if (rc != GFP_OK) return rc;
+  *n = N;
+  return GFP_OK;
+}
+
+int gfp_polymul_workspace_size(const gfp_field* f, uint64_t la, uint64_t lb, uint64_t* bytes) {
+  if (!bytes) return GFP_EINVAL;
+  uint64_t N;
+  int rc = gfp_polymul_size(f, la, lb, &N);
+  if (rc != GFP_OK) return rc;
+  *bytes = 4ull * N * f->k * 8;
+  return GFP_OK;
+}
+
+int gfp_polymul(const gfp_field* cf, const uint64_t* a, uint64_t la, uint64_t ld_a, const uint64_t* b, uint64_t lb,
+                uint64_t ld_b, uint64_t* c, uint64_t ld_c, void* workspace, uint64_t ws_bytes, void* stream) {
+  gfp_field* f = const_cast<gfp_field*>(cf);
+  if (!f || !a || !b || !c || la == 0 || lb == 0) return GFP_EINVAL;
+  if (!f->gpu_shape) return GFP_EUNSUPPORTED;
+  if (ld_a < la || ld_b < lb || ld_c < la + lb - 1) return GFP_EINVAL;
+  uint64_t N;
+  int rc = gfp_polymul_size(f, la, lb, &N);
+  if (rc != GFP_OK) return rc;
+  int log2n, e;
+  check_size(f, N, &log2n, &e);
+  hipStream_t st = (hipStream_t)stream;
+  Scratch s;
+  uint64_t* w = nullptr;
+  const uint64_t k = f->k;
+  rc = get_workspace(workspace, ws_bytes, 4ull * N * k * 8, st, s, &w);
+  if (rc != GFP_OK) return rc;
+  uint64_t* A = w;
+  uint64_t* B = w + N * k;
+  uint64_t* W1 = w + 2 * N * k;
+  uint64_t* W2 = w + 3 * N * k;
+  hipError_t he = hipMemsetAsync(A, 0, 2 * N * k * 8, st);
+  if (he == hipSuccess) he = hipMemcpy2DAsync(A, N * 8, a, ld_a * 8, la * 8, k, hipMemcpyDeviceToDevice, st);
+  if (he == hipSuccess) he = hipMemcpy2DAsync(B, N * 8, b, ld_b * 8, lb * 8, k, hipMemcpyDeviceToDevice, st);
+  if (he != hipSuccess) return hip_status(he);
+  rc = run_transform(f, log2n, e, false, A, N, A, N, W1, W2, st);
+  if (rc == GFP_OK) rc = run_transform(f, log2n, e, false, B, N, B, N, W1, W2, st);
+  if (rc != GFP_OK) return rc;
+  gfpk::EwArgs ew;
+  ew.op = GFP_OP_MUL;
+  ew.x = A;
+  ew.ldx = N;
+  ew.y = B;
+  ew.ldy = N;
+  ew.z = A;
+  ew.ldz = N;
+  ew.n = N;
+  ew.s = 0;
+  ew.cst = nullptr;
+  he = gfpk::launch_elementwise((int)k, f->w, f->u, ew, st);
+  if (he != hipSuccess) return hip_status(he);
+  // inverse into B (full length), then the first la + lb - 1 coefficients to c
+  rc = run_transform(f, log2n, e, true, A, N, B, N, W1, W2, st);
+  if (rc != GFP_OK) return rc;
+  he = hipMemcpy2DAsync(c, ld_c * 8, B, N * 8, (la + lb - 1) * 8, k, hipMemcpyDeviceToDevice, st);
+  return hip_status(he);
+}
+
+int gfp_elementwise(const gfp_field* cf, int op, const uint64_t* x, uint64_t ld_x, const uint64_t* y, uint64_t ld_y,
+                    uint64_t* z, uint64_t ld_z, uint64_t n, int64_t s, const uint64_t* c_host, void* stream) {
+  gfp_field* f = const_cast<gfp_field*>(cf);
+  if (!f || !x || !z) return GFP_EINVAL;
+  if (!f->gpu_shape) return GFP_EUNSUPPORTED;
+  if (op < GFP_OP_ADD || op > GFP_OP_MUL_SCALE) return GFP_EINVAL;
+  const bool needs_y = (op == GFP_OP_ADD || op == GFP_OP_SUB || op == GFP_OP_MUL || op == GFP_OP_MUL_SCALE);
+  const bool needs_c = (op == GFP_OP_MUL_CONST || op == GFP_OP_MUL_SCALE);
+  if (needs_y && !y) return GFP_EINVAL;
+  if (needs_c && !c_host) return GFP_EINVAL;
+  if (ld_x < n || ld_z < n || (needs_y && ld_y < n)) return GFP_EINVAL;
+  if (n == 0) return GFP_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t* cst = nullptr;
+  Scratch cs;
+  if (needs_c) {
+    // validate and stage the constant (stream-ordered, freed after use)
+    std::vector<uint64_t> dg(c_host, c_host + f->k);
+    bool canon = true;
+    bool top_r = dg[f->k - 1] == f->r;
+    for (uint32_t d = 0; d < f->k; ++d) {
+      if (top_r ? (d + 1 < f->k && dg[d] != 0) : (dg[d] >= f->r)) canon = false;
+    }
+    if (!canon) return GFP_EINVAL;
+    std::vector<uint32_t> host(gfpk::tw_words((int)f->k));
+    make_entry(f->k, dg.data(), host.data());
+    hipError_t he = hipMallocAsync(&cs.p, host.size() * 4, st);
+    if (he != hipSuccess) return hip_status(he);
+    cs.st = st;
+    // the host vector must outlive the copy: copy synchronously with respect to the host
+    he = hipMemcpyAsync(cs.p, host.data(), host.size() * 4, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return hip_status(he);
+    cst = (const uint32_t*)cs.p;
+  } else if (op == GFP_OP_MUL_POW_R) {
+    int rc = get_one(f, &cst);
+    if (rc != GFP_OK) return rc;
+  }
+  gfpk::EwArgs a;
+  a.op = op;
+  a.x = x;
+  a.ldx = ld_x;
+  a.y = needs_y ? y : x;
+  a.ldy = needs_y ? ld_y : ld_x;
+  a.z = z;
+  a.ldz = ld_z;
+  a.n = n;
+  a.s = s;
+  a.cst = cst;
+  hipError_t he = gfpk::launch_elementwise((int)f->k, f->w, f->u, a, st);
+  return hip_status(he);
+}
+
+const char* gfp_strerror(int code) {
+  switch (code) {
+    case GFP_OK: return "ok";
+    case GFP_EINVAL: return "invalid argument";
+    case GFP_EUNSUPPORTED: return "unsupported field or size";
+    case GFP_ENOMEM: return "out of memory";
+    case GFP_EAGAIN: return "no capacity, try again";
+    case GFP_EDEVICE: return "HIP device error";
+    case GFP_ENOTPRIME: return "r^k + 1 is not a probable prime";
+    case GFP_ECANCELED: return "request cancelled";
+    case GFP_EPENDING: return "result not ready";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+// HIP kernels for the Generalized Fermat prime field FFT (gfx950).
+//
+// The transform of size N = K^e (K = 2k) runs as e radix-K passes of an
+// out-of-place, self-sorting (Stockham) decimation-in-time schedule.  Pass s
+// (stride Ns = K^s) takes, for every j < N/K, the K elements
+// x[j + t N/K] (t < K), multiplies element t by the twiddle w_L^(a t)
+// (L = Ns K, a = j mod Ns), runs the base case DFT_K at w^(N/K) = r on them
+// and writes output t to (j - a) K + a + t Ns.  This is the Cooley-Tukey
+// factorisation of section 1.1 (eq. CTCT) unrolled e times, with the stride
+// permutations of section 4.1 folded into the load/store indexing.  The
+// twiddle w_L^(a t) = r^rho w^(c N/L) with rho = floor(a t / Ns) and
+// c = a t mod Ns (section 4.1: w^(i N/K + j) = r^i w^j): only w^j for
+// j < N/K is tabulated and r^rho is a digit rotation.
+#include "gfp_device.hpp"
+#include "gfp_internal.hpp"
+
+namespace gfpk {
+
+// ---------------------------------------------------------------------------
+// one radix-K Stockham pass
+// ---------------------------------------------------------------------------
+// MODE_PLAIN: twiddles from the table (forward or inverse table).
+// MODE_SCALE: every slot multiplied by one constant (inverse pass 0: 1/N).
+enum { MODE_PLAIN = 0, MODE_SCALE = 1 };
+
+template <int KD, int W, int U, bool INV, int MODE, bool LAST>
+__global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, uint64_t ld_in, uint64_t* __restrict__ out,
+                                              uint64_t ld_out, const uint32_t* __restrict__ tw, int log2n, int log2ns,
+                                              uint64_t ngroups) {
+  typedef Geo<KD> Gm;
+  constexpr int KB = Gm::KB;
+  constexpr int LOGKB = ilog2(KB);
+  const int l = Gm::lane();
+  const int m = Gm::digit(l);
+  const uint64_t j = ((uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * Gm::G + Gm::group(l);
+  const bool active = j < ngroups;
+  const uint64_t jj = active ? j : 0;  // inactive groups compute on element 0 and store nothing
+  const uint64_t nk = ngroups;         // N / K
+  const uint64_t ns = 1ull << log2ns;
+  const uint64_t a = jj & (ns - 1);
+
+  uint64_t x[KB];
+  static_for<KB>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    x[t] = in[(uint64_t)m * ld_in + jj + (uint64_t)t * nk];
+  });
+
+  L96 v[KB];
+  if constexpr (MODE == MODE_SCALE) {
+    static_for<KB>([&](auto T) {
+      constexpr int t = decltype(T)::value;
+      v[t] = mul_twiddle<KD, W, U>(x[t], tw, 0, l, m);
+    });
+  } else {
+    v[0] = l96(x[0]);
+    if (log2ns == 0 || __all(a == 0)) {
+      static_for<KB - 1>([&](auto T) {
+        constexpr int t = decltype(T)::value + 1;
+        v[t] = l96(x[t]);
+      });
+    } else {
+      const int shift = log2n - log2ns - LOGKB;  // table stride N / (Ns K)
+      static_for<KB - 1>([&](auto T) {
+        constexpr int t = decltype(T)::value + 1;
+        const uint64_t e = a * (uint64_t)t;
+        const int rho = (int)(e >> log2ns);
+        const uint64_t c = e & (ns - 1);
+        const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
+        const uint32_t* ent = tw + (c << shift) * TwLayout<KD>::WORDS;
+        v[t] = mul_twiddle<KD, W, U>(x[t], ent, rot, l, m);
+      });
+    }
+  }
+
+  dft_base<KD, INV>(v, m);
+
+  const uint64_t obase = (jj - a) * KB + a;
+  static_for<KB>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    uint64_t d;
+    if constexpr (LAST) {
+      d = canonicalize<KD, W, U>(v[t], l, m);
+    } else {
+      d = seminorm<KD, W, U>(v[t], m);
+    }
+    if (active) out[(uint64_t)m * ld_out + obase + (uint64_t)t * ns] = d;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// elementwise operations (one element per k lanes)
+// ---------------------------------------------------------------------------
+template <int KD, int W, int U, int OP>
+__global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict__ x, uint64_t ldx,
+                                                     const uint64_t* __restrict__ y, uint64_t ldy, uint64_t* __restrict__ z,
+                                                     uint64_t ldz, uint64_t n, int64_t s, const uint32_t* __restrict__ cst) {
+  typedef Geo<KD> Gm;
+  const int l = Gm::lane();
+  const int m = Gm::digit(l);
+  const uint64_t e = ((uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * Gm::G + Gm::group(l);
+  const bool active = e < n;
+  const uint64_t ee = active ? e : 0;
+  const uint64_t xm = x[(uint64_t)m * ldx + ee];
+  L96 t;
+  if constexpr (OP == GFP_OP_ADD || OP == GFP_OP_SUB) {
+    const uint64_t ym = y[(uint64_t)m * ldy + ee];
+    t = (OP == GFP_OP_ADD) ? l96_add(l96(xm), l96(ym)) : l96_sub(l96(xm), l96(ym));
+  } else if constexpr (OP == GFP_OP_MUL || OP == GFP_OP_MUL_SCALE) {
+    uint64_t yd[KD];
+    static_for<KD>([&](auto T) {
+      constexpr int tt = decltype(T)::value;
+      yd[tt] = y[(uint64_t)tt * ldy + ee];
+    });
+    t = mul_data<KD, W, U>(xm, yd, m);
+    if constexpr (OP == GFP_OP_MUL_SCALE) {
+      const uint64_t sn = seminorm<KD, W, U>(t, m);
+      t = mul_twiddle<KD, W, U>(sn, cst, 0, l, m);
+    }
+  } else if constexpr (OP == GFP_OP_MUL_CONST) {
+    t = mul_twiddle<KD, W, U>(xm, cst, (int)(((s % (2 * KD)) + 2 * KD) % (2 * KD)), l, m);
+  } else {  // GFP_OP_MUL_POW_R: x * r^s by rotation with the multiply by the constant 1
+    t = mul_twiddle<KD, W, U>(xm, cst, (int)(((s % (2 * KD)) + 2 * KD) % (2 * KD)), l, m);
+  }
+  const uint64_t d = canonicalize<KD, W, U>(t, l, m);
+  if (active) z[(uint64_t)m * ldz + ee] = d;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(uint64_t groups, int G) {
+  const uint64_t per_block = 4ull * G;  // 4 wavefronts of 64 lanes per block
+  return (unsigned)((groups + per_block - 1) / per_block);
+}
+
+template <int KD, int W, int U>
+static hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
+  const unsigned nb = blocks_for(p.ngroups, Geo<KD>::G);
+  if (nb == 0) return hipSuccess;
+#define GFP_LAUNCH(INV, MODE, LAST)                                                                                  \
+  hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST>), dim3(nb), dim3(256), 0, st, p.in, p.ld_in, p.out, p.ld_out, \
+                     p.tw, p.log2n, p.log2ns, p.ngroups)
+  if (p.scale) {
+    if (p.last) GFP_LAUNCH(true, MODE_SCALE, true); else GFP_LAUNCH(true, MODE_SCALE, false);
+  } else if (p.inverse) {
+    if (p.last) GFP_LAUNCH(true, MODE_PLAIN, true); else GFP_LAUNCH(true, MODE_PLAIN, false);
+  } else {
+    if (p.last) GFP_LAUNCH(false, MODE_PLAIN, true); else GFP_LAUNCH(false, MODE_PLAIN, false);
+  }
+#undef GFP_LAUNCH
+  return hipGetLastError();
+}
+
+template <int KD, int W, int U>
+static hipError_t launch_elementwise_t(const EwArgs& a, hipStream_t st) {
+  const unsigned nb = blocks_for(a.n, Geo<KD>::G);
+  if (nb == 0) return hipSuccess;
+#define GFP_LAUNCH_EW(OP)                                                                                        \
+  hipLaunchKernelGGL((k_elementwise<KD, W, U, OP>), dim3(nb), dim3(256), 0, st, a.x, a.ldx, a.y, a.ldy, a.z, a.ldz, \
+                     a.n, a.s, a.cst)
+  switch (a.op) {
+    case GFP_OP_ADD: GFP_LAUNCH_EW(GFP_OP_ADD); break;
+    case GFP_OP_SUB: GFP_LAUNCH_EW(GFP_OP_SUB); break;
+    case GFP_OP_MUL: GFP_LAUNCH_EW(GFP_OP_MUL); break;
+    case GFP_OP_MUL_POW_R: GFP_LAUNCH_EW(GFP_OP_MUL_POW_R); break;
+    case GFP_OP_MUL_CONST: GFP_LAUNCH_EW(GFP_OP_MUL_CONST); break;
+    case GFP_OP_MUL_SCALE: GFP_LAUNCH_EW(GFP_OP_MUL_SCALE); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef GFP_LAUNCH_EW
+  return hipGetLastError();
+}
+
+// Radix shapes compiled in: the two workload primes of Table 1 and the two
+// test primes of section 5.3 (Table testprimes) with k = 8 and 16.
+#define GFP_FOR_EACH_SHAPE(X) \
+  X(8, 63, 34)                \
+  X(8, 59, 16)                \
+  X(16, 62, 36)               \
+  X(16, 58, 10)
+
+bool shape_supported(int k, int w, int u) {
+#define GFP_SHAPE_CASE(K, W, U) \
+  if (k == K && w == W && u == U) return true;
+  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
+#undef GFP_SHAPE_CASE
+  return false;
+}
+
+hipError_t launch_pass(int k, int w, int u, const PassArgs& p, hipStream_t st) {
+#define GFP_SHAPE_CASE(K, W, U) \
+  if (k == K && w == W && u == U) return launch_pass_t<K, W, U>(p, st);
+  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
+#undef GFP_SHAPE_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_elementwise(int k, int w, int u, const EwArgs& a, hipStream_t st) {
+#define GFP_SHAPE_CASE(K, W, U) \
+  if (k == K && w == W && u == U) return launch_elementwise_t<K, W, U>(a, st);
+  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
+#undef GFP_SHAPE_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gfpk

@@ -1,0 +1,208 @@
+"""Python binding of libgfpfft (ctypes).  Argument marshalling only: every
+step of the transforms runs in the HIP library; PyTorch provides device
+memory and streams.
+
+Vectors are torch tensors of shape (k, ld), dtype int64 or uint64 (the bit
+pattern is what matters), on a HIP device, row-major with unit stride along
+the element axis: digit d of element i is t[d, i].  Only the first n
+columns are read or written.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgfpfft.so")
+
+GFP_OK = 0
+GFP_EINVAL = 1
+GFP_EUNSUPPORTED = 2
+GFP_ENOMEM = 3
+GFP_EAGAIN = 4
+GFP_EDEVICE = 5
+GFP_ENOTPRIME = 6
+GFP_ECANCELED = 7
+GFP_EPENDING = 8
+
+OP_ADD, OP_SUB, OP_MUL, OP_MUL_POW_R, OP_MUL_CONST, OP_MUL_SCALE = range(6)
+
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_vp = ctypes.c_void_p
+_pu64 = ctypes.POINTER(ctypes.c_uint64)
+
+# name -> (restype, argtypes); mirrors include/gfp.h
+SIGNATURES = {
+    "gfp_field_create": (_int, [_u32, _u64, ctypes.POINTER(_vp)]),
+    "gfp_field_destroy": (_int, [_vp]),
+    "gfp_field_info": (_int, [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_u32)]),
+    "gfp_root_of_unity": (_int, [_vp, _u64, _int, _pu64]),
+    "gfp_fft_workspace_size": (_int, [_vp, _u64, ctypes.POINTER(_u64)]),
+    "gfp_fft_forward": (_int, [_vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp]),
+    "gfp_fft_inverse": (_int, [_vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp]),
+    "gfp_polymul_size": (_int, [_vp, _u64, _u64, ctypes.POINTER(_u64)]),
+    "gfp_polymul_workspace_size": (_int, [_vp, _u64, _u64, ctypes.POINTER(_u64)]),
+    "gfp_polymul": (_int, [_vp, _vp, _u64, _u64, _vp, _u64, _u64, _vp, _u64, _vp, _u64, _vp]),
+    "gfp_elementwise": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _u64, _i64, _pu64, _vp]),
+    "gfp_strerror": (ctypes.c_char_p, [_int]),
+}
+
+_lib = None
+
+
+class GFPError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s: %s (code %d)" % (what, strerror(code), code))
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library; fails loudly if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgfpfft.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().gfp_strerror(code).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != GFP_OK:
+        raise GFPError(rc, what)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _vec(t: torch.Tensor, k: int, n: int, name: str):
+    if t.dtype not in (torch.int64, torch.uint64) or t.dim() != 2 or t.shape[0] != k:
+        raise ValueError("%s must be a (k, ld) int64/uint64 tensor" % name)
+    if t.stride(1) != 1 or t.shape[1] < n or not t.is_cuda:
+        raise ValueError("%s must be a HIP tensor with unit element stride and >= n columns" % name)
+    return ctypes.c_void_p(t.data_ptr()), t.stride(0)
+
+
+class Field:
+    """Z/pZ with p = r^k + 1 (a handle on gfp_field)."""
+
+    def __init__(self, k: int, r: int):
+        h = _vp()
+        _check(lib().gfp_field_create(k, r, ctypes.byref(h)), "gfp_field_create")
+        self._h = h
+        self.k = k
+        self.r = r
+        lg = _u32()
+        _check(lib().gfp_field_info(h, None, None, ctypes.byref(lg)), "gfp_field_info")
+        self.log2_max_n = lg.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gfp_field_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def root_of_unity(self, n: int, inverse: bool = False) -> list:
+        out = (ctypes.c_uint64 * self.k)()
+        _check(lib().gfp_root_of_unity(self._h, n, int(inverse), out), "gfp_root_of_unity")
+        return [int(v) for v in out]
+
+    def fft_workspace_size(self, n: int) -> int:
+        b = _u64()
+        _check(lib().gfp_fft_workspace_size(self._h, n, ctypes.byref(b)), "gfp_fft_workspace_size")
+        return b.value
+
+    def polymul_size(self, la: int, lb: int) -> int:
+        v = _u64()
+        _check(lib().gfp_polymul_size(self._h, la, lb, ctypes.byref(v)), "gfp_polymul_size")
+        return v.value
+
+    def polymul_workspace_size(self, la: int, lb: int) -> int:
+        v = _u64()
+        _check(lib().gfp_polymul_workspace_size(self._h, la, lb, ctypes.byref(v)), "gfp_polymul_workspace_size")
+        return v.value
+
+    def _transform(self, fn, what, x, n, y, workspace, stream):
+        px, ldx = _vec(x, self.k, n, "x")
+        if y is None:
+            y = torch.empty((self.k, n), dtype=x.dtype, device=x.device)
+        py, ldy = _vec(y, self.k, n, "y")
+        wp, wb = (ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()) \
+            if workspace is not None else (None, 0)
+        _check(fn(self._h, n, px, ldx, py, ldy, wp, wb, _stream(stream)), what)
+        return y
+
+    def fft_forward(self, x, n=None, y=None, workspace=None, stream=None):
+        n = x.shape[1] if n is None else n
+        return self._transform(lib().gfp_fft_forward, "gfp_fft_forward", x, n, y, workspace, stream)
+
+    def fft_inverse(self, x, n=None, y=None, workspace=None, stream=None):
+        n = x.shape[1] if n is None else n
+        return self._transform(lib().gfp_fft_inverse, "gfp_fft_inverse", x, n, y, workspace, stream)
+
+    def polymul(self, a, b, la=None, lb=None, c=None, workspace=None, stream=None):
+        la = a.shape[1] if la is None else la
+        lb = b.shape[1] if lb is None else lb
+        pa, lda = _vec(a, self.k, la, "a")
+        pb, ldb = _vec(b, self.k, lb, "b")
+        if c is None:
+            c = torch.empty((self.k, la + lb - 1), dtype=a.dtype, device=a.device)
+        pc, ldc = _vec(c, self.k, la + lb - 1, "c")
+        wp, wb = (ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()) \
+            if workspace is not None else (None, 0)
+        _check(lib().gfp_polymul(self._h, pa, la, lda, pb, lb, ldb, pc, ldc, wp, wb, _stream(stream)), "gfp_polymul")
+        return c
+
+    def elementwise(self, op, x, y=None, z=None, n=None, s=0, c=None, stream=None):
+        n = x.shape[1] if n is None else n
+        px, ldx = _vec(x, self.k, n, "x")
+        py, ldy = _vec(y, self.k, n, "y") if y is not None else (None, 0)
+        if z is None:
+            z = torch.empty((self.k, n), dtype=x.dtype, device=x.device)
+        pz, ldz = _vec(z, self.k, n, "z")
+        ch = (ctypes.c_uint64 * self.k)(*[int(v) for v in c]) if c is not None else None
+        _check(lib().gfp_elementwise(self._h, op, px, ldx, py, ldy, pz, ldz, n, s, ch, _stream(stream)),
+               "gfp_elementwise")
+        return z
+
+
+# ---- numpy <-> device helpers (marshalling only) --------------------------------
+def to_device(digits_u64, device="cuda") -> torch.Tensor:
+    """(k, n) numpy uint64 -> (k, n) int64 device tensor with the same bits."""
+    import numpy as np
+
+    arr = np.ascontiguousarray(digits_u64, dtype=np.uint64)
+    return torch.from_numpy(arr.view(np.int64)).to(device)
+
+
+def to_host(t: torch.Tensor):
+    """Device tensor -> (k, n) numpy uint64."""
+    import numpy as np
+
+    return t.detach().cpu().contiguous().numpy().view(np.uint64)

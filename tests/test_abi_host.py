@@ -1,0 +1,87 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/gfp.h declares, and its host-side field setup (probable-prime test,
+Alg. 1 root of unity, error codes) agrees with the oracle."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle.field import GFPField, P8, P16
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gfp.h")
+
+gfp = pytest.importorskip("paper_1811_01490_amd.gfp")
+
+
+def _lib():
+    if not os.path.exists(gfp.LIB_PATH):
+        pytest.skip("libgfpfft.so not built")
+    return gfp.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(gfp_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_bound_functions():
+    names = declared_functions()
+    assert names, "no declarations found"
+    assert set(names) == set(gfp.SIGNATURES), (set(names) ^ set(gfp.SIGNATURES))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("params", [P8, P16, dict(k=8, r=2 ** 59 + 2 ** 16), dict(k=16, r=2 ** 58 + 2 ** 10)])
+def test_field_create_info_and_roots(params):
+    _lib()
+    F = GFPField(**params)
+    f = gfp.Field(params["k"], params["r"])
+    assert f.log2_max_n == F.max_log2_n
+    for N in (2 * F.k, 4 * F.k * F.k, 2 ** 12, 2 ** 20):
+        if N < 2 * F.k:
+            continue
+        w = F.paper_root_of_unity(N)
+        assert f.root_of_unity(N) == F.from_int(w)
+        assert f.root_of_unity(N, inverse=True) == F.from_int(F.inv(w))
+    f.close()
+
+
+def test_error_codes():
+    L = _lib()
+    h = ctypes.c_void_p()
+    assert L.gfp_field_create(8, 2 ** 63 + 2 ** 30, ctypes.byref(h)) == gfp.GFP_ENOTPRIME  # composite (s = 30)
+    assert L.gfp_field_create(6, 2 ** 63 + 2 ** 34, ctypes.byref(h)) == gfp.GFP_EINVAL    # k not a power of two
+    assert L.gfp_field_create(8, 2 ** 63 + 2 ** 34 + 1, ctypes.byref(h)) == gfp.GFP_EINVAL  # r odd
+    assert L.gfp_field_create(8, 2 ** 63 + 2 ** 34, None) == gfp.GFP_EINVAL
+    # a prime outside the compiled shapes is accepted by create, rejected by transforms
+    assert L.gfp_field_create(4, 2 ** 64 - 2 ** 50, ctypes.byref(h)) == gfp.GFP_OK  # Table 1 row 2
+    out = (ctypes.c_uint64 * 4)()
+    assert L.gfp_root_of_unity(h, 8, 0, out) == gfp.GFP_OK
+    F = GFPField(4, 2 ** 64 - 2 ** 50)
+    assert [int(v) for v in out] == F.from_int(F.paper_root_of_unity(8))
+    assert L.gfp_fft_forward(h, 8, ctypes.c_void_p(8), 8, ctypes.c_void_p(8), 8, None, 0, None) == gfp.GFP_EUNSUPPORTED
+    L.gfp_field_destroy(h)
+    f = gfp.Field(**P8)
+    b = ctypes.c_uint64()
+    for bad_n in (0, 8, 32, 100, 2 ** 26):
+        assert L.gfp_fft_workspace_size(f.handle, bad_n, ctypes.byref(b)) in (gfp.GFP_EUNSUPPORTED, gfp.GFP_EINVAL)
+    assert L.gfp_fft_workspace_size(f.handle, 4096, ctypes.byref(b)) == gfp.GFP_OK
+    assert b.value == 2 * 4096 * 8 * 8
+    assert f.polymul_size(2048, 2048) == 4096
+    assert f.polymul_size(1, 1) == 16
+    assert f.polymul_size(2 ** 19, 2 ** 19) == 2 ** 20
+    assert f.polymul_size(9, 9) == 256 and f.polymul_size(8, 9) == 16
+    # null / short-ld arguments are rejected before any device work
+    assert L.gfp_fft_forward(f.handle, 4096, None, 4096, ctypes.c_void_p(8), 4096, None, 0, None) == gfp.GFP_EINVAL
+    assert L.gfp_fft_forward(f.handle, 4096, ctypes.c_void_p(8), 4000, ctypes.c_void_p(8), 4096, None, 0, None) == gfp.GFP_EINVAL
+    assert L.gfp_polymul(f.handle, ctypes.c_void_p(8), 0, 1, ctypes.c_void_p(8), 1, 1, ctypes.c_void_p(8), 1, None, 0, None) == gfp.GFP_EINVAL
+    assert L.gfp_elementwise(f.handle, 99, ctypes.c_void_p(8), 1, None, 0, ctypes.c_void_p(8), 1, 1, 0, None, None) == gfp.GFP_EINVAL
+    assert gfp.strerror(gfp.GFP_ENOTPRIME).startswith("r^k + 1")

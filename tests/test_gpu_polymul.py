@@ -1,0 +1,68 @@
+"""Polynomial product (section 3.3, Alg. Fast Convolution) against the
+schoolbook product, bit-exact; at the full workload size (two degree < 2^19
+factors) by Schwartz-Zippel evaluation and sampled coefficients."""
+
+import random
+
+import numpy as np
+import pytest
+
+import gfp_inputs as gi
+from oracle import transform as T
+from oracle.field import GFPField, P8, P16
+from tests.helpers import canonical_mask, to_ints
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _run(params, la, lb, seed, edge=0.02):
+    from paper_1811_01490_amd import Field, to_device, to_host
+
+    F = GFPField(**params)
+    f = Field(params["k"], params["r"])
+    a = gi.operand(F.k, F.r, la, seed, 0, edge_frac=edge)
+    b = gi.operand(F.k, F.r, lb, seed, 1, edge_frac=edge)
+    c = to_host(f.polymul(to_device(a), to_device(b)))
+    assert c.shape == (F.k, la + lb - 1)
+    assert canonical_mask(c, F.r).all()
+    return F, a, b, c
+
+
+def test_config0_schoolbook(torch_mod):
+    """k = 8, la = lb = 2048 (transform size 16^3 = 4096)."""
+    F, a, b, c = _run(P8, 2048, 2048, gi.BASE_SEED + 0)
+    want = T.polymul(to_ints(a, F.r), to_ints(b, F.r), F.p)
+    got = to_ints(c, F.r)
+    bad = [m for m in range(len(want)) if got[m] != want[m]]
+    assert not bad, (bad[:8], len(bad))
+
+
+@pytest.mark.parametrize("params", [P8, P16], ids=["k8", "k16"])
+@pytest.mark.parametrize("la,lb", [(1, 1), (1, 17), (3, 5), (9, 8), (8, 9), (16, 1), (100, 157), (300, 1), (513, 512)])
+def test_ragged_schoolbook(torch_mod, params, la, lb):
+    F, a, b, c = _run(params, la, lb, gi.BASE_SEED + la * 1000 + lb, edge=0.2)
+    assert to_ints(c, F.r) == T.polymul(to_ints(a, F.r), to_ints(b, F.r), F.p)
+
+
+@pytest.mark.parametrize("params,cfg", [(P8, 1), (P16, 2)], ids=["config1-k8", "config2-k16"])
+def test_full_size_sampled(torch_mod, params, cfg):
+    la = lb = 2 ** 19
+    F, a, b, c = _run(params, la, lb, gi.BASE_SEED + cfg, edge=0.0005)
+    ai, bi = to_ints(a, F.r), to_ints(b, F.r)
+    g = random.Random(cfg)
+    cols = gi.sample_indices(la + lb - 1, 6, gi.BASE_SEED + cfg, 3, must=(0, 1, la - 1, la, la + lb - 2))
+    cv = to_ints(c[:, cols], F.r)
+    for m, got in zip(cols, cv):
+        assert got == T.polymul_coeff(ai, bi, m, F.p), m
+    ci = to_ints(c, F.r)
+    for _ in range(3):
+        z = g.randrange(F.p)
+        assert T.horner(ci, z, F.p) == T.horner(ai, z, F.p) * T.horner(bi, z, F.p) % F.p
