@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark: forward FFT over Z/pZ, p = (2^63 + 2^34)^8 + 1 (k = 8), of
+N = 16^5 = 1,048,576 coefficients on one MI355X.
+
+Prints one JSON line.  value = N / (time of one forward transform), inputs
+resident in HBM before the timed region.  The timed region is `steps`
+back-to-back calls of gfp_fft_forward bracketed by synchronisations, timed
+with HIP events on the stream the library launches on.
+
+Extra objects:
+  roofline      the dominant kernel (the slowest radix-16 pass), timed alone
+                with HIP events; ALU-bound, so achieved = algorithmic integer
+                operations per launch / mean launch time against the chip's
+                32-bit VALU peak (256 CU x 64 lanes x 2.4 GHz).
+  hbm           the whole transform against the HBM roofline: algorithmic
+                bytes (read + write the vector once) / transform time.
+  cpu_baseline  the CPU oracle (radix-2 NTT on Python integers) timed on a
+                bounded sample of the same workload on this host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Z/pZ FFT coeffs/s (k=8,N=16^5); batched-vs-plain polymul speedup; p99 latency"
+K_DIG, R = 8, 2 ** 63 + 2 ** 34
+LOG2N = 20
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit integer lane-ops per second (Tops/s)
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1811_01490_amd/csrc/gfp_kernels.hpp", "paper_1811_01490_amd/csrc/gfp_device.hpp"]
+
+
+def pass_counts(N: int, K: int, s: int, k: int):
+    """Per-pass algorithmic work of the radix-K schedule at stage s:
+    general twiddle products (twiddle not a power of r), butterflies, and
+    the integer operations they need at minimum: 4 k^2 32x32-bit limb
+    products per general product (schoolbook on k 64-bit digits) and 4 k
+    32-bit add/sub-with-carry per radix-2 butterfly (one k-digit addition and
+    one subtraction)."""
+    import numpy as np
+
+    ns = K ** s
+    a = np.arange(ns, dtype=np.int64)
+    general = 0
+    for t in range(1, K):
+        general += int(np.count_nonzero((a * t) % ns))
+    general *= (N // K) // ns
+    lgk = K.bit_length() - 1
+    butterflies = (N // K) * (K // 2) * lgk
+    ops = general * 4 * k * k + butterflies * 4 * k
+    return general, butterflies, ops
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_key: str):
+    """HBM traffic per launch from a committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    ent = d.get("kernels", {}).get(kernel_key)
+    return ent.get("bytes_per_launch") if ent else None
+
+
+def cpu_baseline(sample_log2: int):
+    """The oracle's radix-2 NTT (Python integers, one thread) on a 2^sample
+    prefix-sized instance of the workload, scaled to N = 2^20 by N log2 N."""
+    import gfp_inputs as gi
+    from oracle import transform as T
+    from oracle.field import GFPField
+
+    F = GFPField(K_DIG, R)
+    n = 2 ** sample_log2
+    x = gi.uniform_digits(K_DIG, R, n, gi.BASE_SEED + 1, 0)
+    obj = x.astype(object)
+    vals = obj[K_DIG - 1].copy()
+    for d in range(K_DIG - 2, -1, -1):
+        vals = vals * R + obj[d]
+    vals = [int(v) for v in vals]
+    w = F.paper_root_of_unity(n)
+    t0 = time.perf_counter()
+    T.ntt(vals, w, F.p)
+    dt = time.perf_counter() - t0
+    full = dt * (2 ** LOG2N * LOG2N) / (n * sample_log2)
+    return {
+        "value": round(2 ** LOG2N / full, 1),
+        "unit": "coeffs/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "oracle radix-2 NTT (Python integers, 1 thread) of 2^%d uniform coefficients over the same prime, "
+                  "%.2f s; scaled to N = 2^20 by the N log2 N butterfly count" % (sample_log2, dt),
+        "cpu_model": _cpu_model(),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--pass-reps", type=int, default=50)
+    ap.add_argument("--cpu-sample-log2", type=int, default=19)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (one transform does not span GPUs). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gfp_inputs as gi
+    from paper_1811_01490_amd import Field, to_device
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    N = 2 ** LOG2N
+    K = 2 * K_DIG
+    f = Field(K_DIG, R)
+    x = to_device(gi.uniform_digits(K_DIG, R, N, gi.BASE_SEED + 1, 0), dev)
+    y = torch.empty_like(x)
+    ws = torch.empty(f.fft_workspace_size(N) // 8, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        f.fft_forward(x, y=y, workspace=ws)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        f.fft_forward(x, y=y, workspace=ws)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    ms = ev0.elapsed_time(ev1) / args.steps
+
+    # dominant kernel: each pass alone, on the same stream, in the layouts the
+    # transform uses (digit-major in, element-major between passes,
+    # digit-major out)
+    e = LOG2N // (K.bit_length() - 1)
+    em = [ws[: K_DIG * N], ws[K_DIG * N:]]
+    per_pass = []
+    for s in range(e):
+        src = x if s == 0 else em[s % 2]
+        dst = y if s == e - 1 else em[(s + 1) % 2]
+        kw = dict(in_element_major=s > 0, out_element_major=s < e - 1)
+        f.fft_pass(s, src, dst, N, **kw)  # warm
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.pass_reps):
+            f.fft_pass(s, src, dst, N, **kw)
+        b.record(stream)
+        torch.cuda.synchronize()
+        per_pass.append(a.elapsed_time(b) / args.pass_reps)
+    dom = int(np.argmax(per_pass))
+    gen, bfl, ops = pass_counts(N, K, dom, K_DIG)
+    dom_us = per_pass[dom] * 1e3
+    achieved = ops / (dom_us * 1e-6) / 1e12
+    key = "k_pass<8,63,34,fwd,%s>" % ("last" if dom == e - 1 else "mid")
+    traffic = traffic_from_profiles(key)
+    alg_bytes = 2 * N * K_DIG * 8
+    out = {
+        "metric": METRIC,
+        "value": round(N / (ms * 1e-3), 1),
+        "unit": "coeffs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "forward FFT over Z/pZ, p = (2^63+2^34)^8+1 (k=8, radix-16 base case), N = 16^5 = 1048576, "
+                        "uniform random coefficients (seed 1811014901), out-of-place, caller workspace",
+            "passes": e,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": key + " pass %d" % dom,
+            "achieved": round(achieved, 3),
+            "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "Tops/s",
+            "frac": round(achieved / VALU_PEAK_TOPS, 4),
+            "traffic": traffic,
+            "alg_ops_per_launch": ops,
+            "general_products_per_launch": gen,
+            "butterflies_per_launch": bfl,
+            "mean_launch_us": round(dom_us, 2),
+            "pass_us": [round(v * 1e3, 2) for v in per_pass],
+        },
+        "hbm": {
+            "alg_bytes_per_transform": alg_bytes,
+            "achieved_GBs": round(alg_bytes / (ms * 1e-3) / 1e9, 1),
+            "peak_GBs": HBM_PEAK_GBS,
+            "frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        },
+        "timed_wall_s": round(t_wall, 4),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -59,8 +59,8 @@ extern "C" {
 #define GFP_OP_SUB 1       /* z = x - y */
 #define GFP_OP_MUL 2       /* z = x * y */
 #define GFP_OP_MUL_POW_R 3 /* z = x * r^s (section 2.3), y unused */
-#define GFP_OP_MUL_CONST 4 /* z = x * c * r^s, c = host digits passed as y_host */
-#define GFP_OP_MUL_SCALE 5 /* z = x * y * c, c = host digits passed as y_host */
+#define GFP_OP_MUL_CONST 4 /* z = x * c * r^s, c = host digits c_host */
+#define GFP_OP_MUL_SCALE 5 /* z = x * y * c, c = host digits c_host */
 
 typedef struct gfp_field gfp_field;
 
@@ -89,7 +89,7 @@ int gfp_field_info(const gfp_field* f, uint32_t* k, uint64_t* r, uint32_t* log2_
  * of k uint64_t, canonical encoding.  Host-only. */
 int gfp_root_of_unity(const gfp_field* f, uint64_t n, int inverse, uint64_t* digits);
 
-/* Transform sizes: n = K^e, K = 2k, e >= 1, n <= 2^log2_max_n and n <= 2^26.
+/* Transform sizes: n = K^e, K = 2k, e >= 1, n <= 2^log2_max_n and n <= 2^25.
  * Workspace bytes needed by gfp_fft_forward / gfp_fft_inverse of size n. */
 int gfp_fft_workspace_size(const gfp_field* f, uint64_t n, uint64_t* bytes);
 
@@ -105,6 +105,27 @@ int gfp_fft_forward(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t 
  * (section 3.3, Alg. Fast Convolution).  Same arguments as gfp_fft_forward. */
 int gfp_fft_inverse(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t ld_x, uint64_t* y, uint64_t ld_y,
                     void* workspace, uint64_t ws_bytes, void* stream);
+
+/* Layout flags of gfp_fft_pass.  Element-major: digit d of element i at
+ * v[i * k + d] (ld ignored), the layout the transforms use between passes. */
+#define GFP_PASS_IN_ELEMENT_MAJOR 1
+#define GFP_PASS_OUT_ELEMENT_MAJOR 2
+
+/* One radix-K pass (stage s, 0 <= s < e) of the transform schedule used by
+ * gfp_fft_forward / gfp_fft_inverse: for every j < n/K the K elements
+ * x[j + t n/K] are multiplied by the twiddles w_L^(a t) (L = K^(s+1),
+ * a = j mod K^s; for the inverse: the conjugate twiddles, and at s = 0 the
+ * factor 1/n), transformed by DFT_K at r (r^-1) and written to
+ * y[(j - a) K + a + t K^s] (section 1.1, eq. CTCT; section 4.1).  Running
+ * s = 0..e-1 with y of one pass as x of the next is the full transform.
+ * Outputs of s < e-1 are not canonical: every digit is in [0, 2^64) and the
+ * value is congruent mod p (the next pass accepts this); s = e-1 writes the
+ * canonical encoding.  x and y must not overlap.  flags: GFP_PASS_* layout
+ * bits (0 = both digit-major).  gfp_fft_forward runs pass 0 digit-major to
+ * element-major, the middle passes element-major, the last pass
+ * element-major to digit-major.  For instrumentation and custom schedules. */
+int gfp_fft_pass(const gfp_field* f, uint64_t n, int s, int inverse, int flags, const uint64_t* x, uint64_t ld_x,
+                 uint64_t* y, uint64_t ld_y, void* stream);
 
 /* Transform size used by gfp_polymul for la + lb - 1 output coefficients:
  * the smallest K^e >= la + lb - 1 (and >= K). */

@@ -22,7 +22,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["gfp_kernels.hip", "gfp_host.cpp"]
+SOURCES = ["gfp_shape_8_63_34.hip", "gfp_shape_8_59_16.hip", "gfp_shape_16_62_36.hip", "gfp_shape_16_58_10.hip",
+           "gfp_dispatch.cpp", "gfp_host.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -1,0 +1,44 @@
+// Dispatch from a runtime radix shape to the kernels compiled for it.
+#include "gfp_internal.hpp"
+
+namespace gfpk {
+
+// Radix shapes compiled in: the two workload primes of Table 1 and the two
+// test primes of section 5.3 (Table testprimes), k = 8 and 16.
+#define GFP_FOR_EACH_SHAPE(X) \
+  X(8, 63, 34)                \
+  X(8, 59, 16)                \
+  X(16, 62, 36)               \
+  X(16, 58, 10)
+
+#define GFP_DECLARE(K, W, U)                                                \
+  hipError_t launch_pass_##K##_##W##_##U(const PassArgs& p, hipStream_t st); \
+  hipError_t launch_elementwise_##K##_##W##_##U(const EwArgs& a, hipStream_t st);
+GFP_FOR_EACH_SHAPE(GFP_DECLARE)
+#undef GFP_DECLARE
+
+bool shape_supported(int k, int w, int u) {
+#define GFP_SHAPE_CASE(K, W, U) \
+  if (k == K && w == W && u == U) return true;
+  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
+#undef GFP_SHAPE_CASE
+  return false;
+}
+
+hipError_t launch_pass(int k, int w, int u, const PassArgs& p, hipStream_t st) {
+#define GFP_SHAPE_CASE(K, W, U) \
+  if (k == K && w == W && u == U) return launch_pass_##K##_##W##_##U(p, st);
+  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
+#undef GFP_SHAPE_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_elementwise(int k, int w, int u, const EwArgs& a, hipStream_t st) {
+#define GFP_SHAPE_CASE(K, W, U) \
+  if (k == K && w == W && u == U) return launch_elementwise_##K##_##W##_##U(a, st);
+  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
+#undef GFP_SHAPE_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gfpk

@@ -266,35 +266,46 @@ int get_workspace(void* ws, uint64_t ws_bytes, uint64_t need, hipStream_t st, Sc
   return GFP_OK;
 }
 
-// Run the e passes of a transform of size n (log2n) from X to Y.
-// Intermediate passes alternate between W1 and W2 (each n elements, ld n);
-// X is only read by pass 0.  When X == Y and e == 1 the pass writes W1 and
-// the result is copied.
+// Run the e passes of a transform of size n (log2n) from X to Y (both
+// digit-major).  Intermediate passes write element-major vectors (one
+// element = k contiguous digits, so the strided element accesses of the
+// following pass read whole 64- or 128-byte segments), alternating between
+// W1 and W2 (each n elements); X is only read by pass 0.  When X == Y and
+// e == 1 the pass writes W1 and the result is copied.
 int run_transform(gfp_field* f, int log2n, int e, bool inverse, const uint64_t* X, uint64_t ldx, uint64_t* Y,
                   uint64_t ldy, uint64_t* W1, uint64_t* W2, hipStream_t st) {
   const uint64_t n = 1ull << log2n;
+  const uint64_t k = f->k;
   const DevTables* t = nullptr;
   int rc = get_tables(f, n, &t);
   if (rc != GFP_OK) return rc;
   const int lk = log2_exact(2ull * f->k);
   const bool copy_back = (e == 1 && X == Y);
   const uint64_t* src = X;
-  uint64_t lds = ldx;
+  uint64_t se = 1, sd = ldx;
   for (int s = 0; s < e; ++s) {
     uint64_t* dst;
-    uint64_t ldd;
+    uint64_t dse, dsd;
     if (s == e - 1 && !copy_back) {
       dst = Y;
-      ldd = ldy;
+      dse = 1;
+      dsd = ldy;
+    } else if (s == e - 1) {  // copy-back: digit-major into W1
+      dst = W1;
+      dse = 1;
+      dsd = n;
     } else {
       dst = (((e - 2 - s) % 2) == 0) ? W1 : W2;  // pass e-2 -> W1, e-3 -> W2, ...
-      ldd = n;
+      dse = k;
+      dsd = 1;
     }
     gfpk::PassArgs p;
     p.in = src;
-    p.ld_in = lds;
+    p.se_in = se;
+    p.sd_in = sd;
     p.out = dst;
-    p.ld_out = ldd;
+    p.se_out = dse;
+    p.sd_out = dsd;
     p.log2n = log2n;
     p.log2ns = s * lk;
     p.ngroups = n >> lk;
@@ -305,10 +316,11 @@ int run_transform(gfp_field* f, int log2n, int e, bool inverse, const uint64_t* 
     hipError_t he = gfpk::launch_pass((int)f->k, f->w, f->u, p, st);
     if (he != hipSuccess) return hip_status(he);
     src = dst;
-    lds = ldd;
+    se = dse;
+    sd = dsd;
   }
   if (copy_back) {
-    hipError_t he = hipMemcpy2DAsync(Y, ldy * 8, src, lds * 8, n * 8, f->k, hipMemcpyDeviceToDevice, st);
+    hipError_t he = hipMemcpy2DAsync(Y, ldy * 8, src, sd * 8, n * 8, f->k, hipMemcpyDeviceToDevice, st);
     if (he != hipSuccess) return hip_status(he);
   }
   return GFP_OK;
@@ -441,6 +453,39 @@ int gfp_fft_forward(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t 
 int gfp_fft_inverse(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t ld_x, uint64_t* y, uint64_t ld_y,
                     void* workspace, uint64_t ws_bytes, void* stream) {
   return transform_entry(f, n, x, ld_x, y, ld_y, workspace, ws_bytes, stream, true);
+}
+
+int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags, const uint64_t* x, uint64_t ld_x,
+                 uint64_t* y, uint64_t ld_y, void* stream) {
+  gfp_field* f = const_cast<gfp_field*>(cf);
+  if (!f || !x || !y || x == y) return GFP_EINVAL;
+  if (!f->gpu_shape) return GFP_EUNSUPPORTED;
+  int log2n, e;
+  int rc = check_size(f, n, &log2n, &e);
+  if (rc != GFP_OK) return rc;
+  if (s < 0 || s >= e || (flags & ~3)) return GFP_EINVAL;
+  const bool in_em = (flags & GFP_PASS_IN_ELEMENT_MAJOR) != 0;
+  const bool out_em = (flags & GFP_PASS_OUT_ELEMENT_MAJOR) != 0;
+  if ((!in_em && ld_x < n) || (!out_em && ld_y < n)) return GFP_EINVAL;
+  const DevTables* t = nullptr;
+  rc = get_tables(f, n, &t);
+  if (rc != GFP_OK) return rc;
+  const int lk = log2_exact(2ull * f->k);
+  gfpk::PassArgs p;
+  p.in = x;
+  p.se_in = in_em ? f->k : 1;
+  p.sd_in = in_em ? 1 : ld_x;
+  p.out = y;
+  p.se_out = out_em ? f->k : 1;
+  p.sd_out = out_em ? 1 : ld_y;
+  p.log2n = log2n;
+  p.log2ns = s * lk;
+  p.ngroups = n >> lk;
+  p.inverse = inverse != 0;
+  p.scale = p.inverse && s == 0;
+  p.tw = p.scale ? t->ninv : (p.inverse ? t->inv : t->fwd);
+  p.last = (s == e - 1);
+  return hip_status(gfpk::launch_pass((int)f->k, f->w, f->u, p, (hipStream_t)stream));
 }
 
 int gfp_polymul_size(const gfp_field* f, uint64_t la, uint64_t lb, uint64_t* n) {

@@ -9,11 +9,14 @@
 
 namespace gfpk {
 
+// Vector addressing: digit d of element i is at base[i * se + d * sd].
+// Digit-major (the ABI's layout): se = 1, sd = ld.  Element-major (used
+// between passes, one element = k contiguous digits): se = k, sd = 1.
 struct PassArgs {
   const uint64_t* in;
-  uint64_t ld_in;
+  uint64_t se_in, sd_in;
   uint64_t* out;
-  uint64_t ld_out;
+  uint64_t se_out, sd_out;
   const uint32_t* tw;  // twiddle table (or the single scale entry when scale)
   int log2n;
   int log2ns;

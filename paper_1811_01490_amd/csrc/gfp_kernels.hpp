@@ -11,6 +11,8 @@
 // twiddle w_L^(a t) = r^rho w^(c N/L) with rho = floor(a t / Ns) and
 // c = a t mod Ns (section 4.1: w^(i N/K + j) = r^i w^j): only w^j for
 // j < N/K is tabulated and r^rho is a digit rotation.
+#pragma once
+
 #include "gfp_device.hpp"
 #include "gfp_internal.hpp"
 
@@ -24,9 +26,9 @@ namespace gfpk {
 enum { MODE_PLAIN = 0, MODE_SCALE = 1 };
 
 template <int KD, int W, int U, bool INV, int MODE, bool LAST>
-__global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, uint64_t ld_in, uint64_t* __restrict__ out,
-                                              uint64_t ld_out, const uint32_t* __restrict__ tw, int log2n, int log2ns,
-                                              uint64_t ngroups) {
+__global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
+                                              uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
+                                              const uint32_t* __restrict__ tw, int log2n, int log2ns, uint64_t ngroups) {
   typedef Geo<KD> Gm;
   constexpr int KB = Gm::KB;
   constexpr int LOGKB = ilog2(KB);
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
   uint64_t x[KB];
   static_for<KB>([&](auto T) {
     constexpr int t = decltype(T)::value;
-    x[t] = in[(uint64_t)m * ld_in + jj + (uint64_t)t * nk];
+    x[t] = in[(uint64_t)m * sd_in + (jj + (uint64_t)t * nk) * se_in];
   });
 
   L96 v[KB];
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
     } else {
       d = seminorm<KD, W, U>(v[t], m);
     }
-    if (active) out[(uint64_t)m * ld_out + obase + (uint64_t)t * ns] = d;
+    if (active) out[(uint64_t)m * sd_out + (obase + (uint64_t)t * ns) * se_out] = d;
   });
 }
 
@@ -128,18 +130,18 @@ __global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict_
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static inline unsigned blocks_for(uint64_t groups, int G) {
+inline unsigned blocks_for(uint64_t groups, int G) {
   const uint64_t per_block = 4ull * G;  // 4 wavefronts of 64 lanes per block
   return (unsigned)((groups + per_block - 1) / per_block);
 }
 
 template <int KD, int W, int U>
-static hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
+hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
   const unsigned nb = blocks_for(p.ngroups, Geo<KD>::G);
   if (nb == 0) return hipSuccess;
 #define GFP_LAUNCH(INV, MODE, LAST)                                                                                  \
-  hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST>), dim3(nb), dim3(256), 0, st, p.in, p.ld_in, p.out, p.ld_out, \
-                     p.tw, p.log2n, p.log2ns, p.ngroups)
+  hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, p.out, \
+                     p.se_out, p.sd_out, p.tw, p.log2n, p.log2ns, p.ngroups)
   if (p.scale) {
     if (p.last) GFP_LAUNCH(true, MODE_SCALE, true); else GFP_LAUNCH(true, MODE_SCALE, false);
   } else if (p.inverse) {
@@ -152,7 +154,7 @@ static hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
 }
 
 template <int KD, int W, int U>
-static hipError_t launch_elementwise_t(const EwArgs& a, hipStream_t st) {
+hipError_t launch_elementwise_t(const EwArgs& a, hipStream_t st) {
   const unsigned nb = blocks_for(a.n, Geo<KD>::G);
   if (nb == 0) return hipSuccess;
 #define GFP_LAUNCH_EW(OP)                                                                                        \
@@ -169,38 +171,6 @@ static hipError_t launch_elementwise_t(const EwArgs& a, hipStream_t st) {
   }
 #undef GFP_LAUNCH_EW
   return hipGetLastError();
-}
-
-// Radix shapes compiled in: the two workload primes of Table 1 and the two
-// test primes of section 5.3 (Table testprimes) with k = 8 and 16.
-#define GFP_FOR_EACH_SHAPE(X) \
-  X(8, 63, 34)                \
-  X(8, 59, 16)                \
-  X(16, 62, 36)               \
-  X(16, 58, 10)
-
-bool shape_supported(int k, int w, int u) {
-#define GFP_SHAPE_CASE(K, W, U) \
-  if (k == K && w == W && u == U) return true;
-  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
-#undef GFP_SHAPE_CASE
-  return false;
-}
-
-hipError_t launch_pass(int k, int w, int u, const PassArgs& p, hipStream_t st) {
-#define GFP_SHAPE_CASE(K, W, U) \
-  if (k == K && w == W && u == U) return launch_pass_t<K, W, U>(p, st);
-  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
-#undef GFP_SHAPE_CASE
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_elementwise(int k, int w, int u, const EwArgs& a, hipStream_t st) {
-#define GFP_SHAPE_CASE(K, W, U) \
-  if (k == K && w == W && u == U) return launch_elementwise_t<K, W, U>(a, st);
-  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
-#undef GFP_SHAPE_CASE
-  return hipErrorInvalidValue;
 }
 
 }  // namespace gfpk

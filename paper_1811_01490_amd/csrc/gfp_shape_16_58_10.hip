@@ -1,0 +1,11 @@
+// Kernels for k = 16, r = 2^58 + 2^10.
+#include "gfp_kernels.hpp"
+
+namespace gfpk {
+
+hipError_t launch_pass_16_58_10(const PassArgs& p, hipStream_t st) { return launch_pass_t<16, 58, 10>(p, st); }
+hipError_t launch_elementwise_16_58_10(const EwArgs& a, hipStream_t st) {
+  return launch_elementwise_t<16, 58, 10>(a, st);
+}
+
+}  // namespace gfpk

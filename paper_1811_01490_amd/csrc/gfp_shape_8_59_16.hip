@@ -1,0 +1,11 @@
+// Kernels for k = 8, r = 2^59 + 2^16.
+#include "gfp_kernels.hpp"
+
+namespace gfpk {
+
+hipError_t launch_pass_8_59_16(const PassArgs& p, hipStream_t st) { return launch_pass_t<8, 59, 16>(p, st); }
+hipError_t launch_elementwise_8_59_16(const EwArgs& a, hipStream_t st) {
+  return launch_elementwise_t<8, 59, 16>(a, st);
+}
+
+}  // namespace gfpk

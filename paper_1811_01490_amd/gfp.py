@@ -46,6 +46,7 @@ SIGNATURES = {
     "gfp_fft_workspace_size": (_int, [_vp, _u64, ctypes.POINTER(_u64)]),
     "gfp_fft_forward": (_int, [_vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp]),
     "gfp_fft_inverse": (_int, [_vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp]),
+    "gfp_fft_pass": (_int, [_vp, _u64, _int, _int, _int, _vp, _u64, _vp, _u64, _vp]),
     "gfp_polymul_size": (_int, [_vp, _u64, _u64, ctypes.POINTER(_u64)]),
     "gfp_polymul_workspace_size": (_int, [_vp, _u64, _u64, ctypes.POINTER(_u64)]),
     "gfp_polymul": (_int, [_vp, _vp, _u64, _u64, _vp, _u64, _u64, _vp, _u64, _vp, _u64, _vp]),
@@ -165,6 +166,21 @@ class Field:
     def fft_inverse(self, x, n=None, y=None, workspace=None, stream=None):
         n = x.shape[1] if n is None else n
         return self._transform(lib().gfp_fft_inverse, "gfp_fft_inverse", x, n, y, workspace, stream)
+
+    def fft_pass(self, s, x, y, n, inverse=False, in_element_major=False, out_element_major=False, stream=None):
+        """One pass; element-major tensors are flat (n * k,) int64 device tensors."""
+        def ptr(t, em, name):
+            if em:
+                if not t.is_cuda or t.numel() < n * self.k:
+                    raise ValueError("%s: element-major needs n*k words on the device" % name)
+                return ctypes.c_void_p(t.data_ptr()), 0
+            return _vec(t, self.k, n, name)
+        px, ldx = ptr(x, in_element_major, "x")
+        py, ldy = ptr(y, out_element_major, "y")
+        flags = (1 if in_element_major else 0) | (2 if out_element_major else 0)
+        _check(lib().gfp_fft_pass(self._h, n, s, int(inverse), flags, px, ldx, py, ldy, _stream(stream)),
+               "gfp_fft_pass")
+        return y
 
     def polymul(self, a, b, la=None, lb=None, c=None, workspace=None, stream=None):
         la = a.shape[1] if la is None else la
