@@ -170,17 +170,113 @@ __device__ __forceinline__ void dft_base(L96 (&v)[2 * KD], int m) {
 // complement ~x = (2^64 - 1) - x, so every product stays unsigned, and the
 // column is corrected afterwards by -(2^64 - 1) * S_m, S_m = the sum of the
 // y_t met with complemented x.  An extra factor r^rho (twiddle rotation,
-// section 4.1: w^(i N/K + j) = r^i w^j) is applied by first gathering
-// x_{m - rho} into lane m with the same complement rule.
+// section 4.1: w^(i N/K + j) = r^i w^j) is applied by starting lane m with
+// x_{m - rho} under the same complement rule (the caller loads that digit).
 //
 // x is split into two 32-bit limbs and each y_t into three limbs of 22, 22
 // and 20 bits, so every limb product is < 2^54 and k of them fit in a 64-bit
 // accumulator: six v_mad_u64_u32 per digit pair, no carries.
 //
-// The column value (|u_m| < k r^2 plus the correction) is then folded with
-// 2^64 = a r - b (a = 2^(64-W), b = 2^(64-W+U)): u = Q r + T with T a lazy
-// digit (|T| < 2^66) and Q carried to column m+1 (negated into column 0).
+// The column C (|C| < k r^2 + 2^132) is then gathered into 64-bit cells at
+// 32-bit positions and folded three times with 2^64 = a r - b
+// (a = 2^(64-W), b = 2^(64-W+U)) into C = Q r + T: T is this lane's lazy
+// digit (|T| < 2^65) and Q (|Q| < 2^74) is carried to column m+1 (negated
+// into column 0, r^k = -1).  The paper's (l, h, c) split of section 3.1.1 is
+// the same idea with c carried two columns.
 // ------------------------------------------------------------------------
+// ------------------------------------------------------------------------
+// word helpers for the fold
+// ------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+// A constant the compiler cannot see through, so x * c + acc stays one
+// v_mad_u64_u32 with the constant in an SGPR instead of a shift-and-mask.
+__device__ __forceinline__ uint32_t sgpr_const(uint32_t c) {
+  uint32_t v;
+  asm("s_mov_b32 %0, %1" : "=s"(v) : "i"(c));
+  return v;
+}
+__device__ __forceinline__ uint64_t mad32(uint32_t x, uint32_t c, uint64_t acc) { return (uint64_t)x * c + acc; }
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, int sh) {  // (hi:lo) >> sh, 0 < sh < 32
+  return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+// (o0..o3) = (l0, l1) - 2^SB (h0, h1, h2), as a signed 128-bit value
+// truncated to 4 words (the caller knows the result fits).
+template <int SB>
+__device__ __forceinline__ void sub_shifted96(uint32_t l0, uint32_t l1, uint32_t h0, uint32_t h1, uint32_t h2,
+                                              uint32_t& o0, uint32_t& o1, uint32_t& o2, uint32_t& o3) {
+  unsigned b;
+  if constexpr (SB >= 32) {
+    constexpr int s = SB - 32;  // 2^SB H = (0, h0 << s, ...)
+    const uint32_t w1 = s ? (h0 << s) : h0;
+    const uint32_t w2 = s ? funnel(h1, h0, 32 - s) : h1;
+    const uint32_t w3 = s ? funnel(h2, h1, 32 - s) : h2;
+    o0 = l0;
+    o1 = __builtin_subc(l1, w1, 0u, &b);
+    o2 = __builtin_subc(0u, w2, b, &b);
+    o3 = __builtin_subc(0u, w3, b, &b);
+  } else {
+    constexpr int s = SB;
+    const uint32_t w0 = h0 << s;
+    const uint32_t w1 = funnel(h1, h0, 32 - s);
+    const uint32_t w2 = funnel(h2, h1, 32 - s);
+    const uint32_t w3 = (uint32_t)((int32_t)h2 >> (32 - s));
+    o0 = __builtin_subc(l0, w0, 0u, &b);
+    o1 = __builtin_subc(l1, w1, b, &b);
+    o2 = __builtin_subc(0u, w2, b, &b);
+    o3 = __builtin_subc(0u, w3, b, &b);
+  }
+}
+
+// (o0, o1, o2) = (l0, l1) - 2^SB (v2, v3) with (v2, v3) a signed 64-bit
+// value; o2 is the signed high word (the result fits in 96 bits).
+template <int SB>
+__device__ __forceinline__ void sub_shifted64(uint32_t l0, uint32_t l1, uint32_t v2, uint32_t v3, uint32_t& o0,
+                                              uint32_t& o1, uint32_t& o2) {
+  unsigned b;
+  if constexpr (SB >= 32) {
+    constexpr int s = SB - 32;
+    const uint32_t w1 = s ? (v2 << s) : v2;
+    const uint32_t w2 = s ? funnel(v3, v2, 32 - s) : v3;
+    o0 = l0;
+    o1 = __builtin_subc(l1, w1, 0u, &b);
+    o2 = __builtin_subc(0u, w2, b, &b);
+  } else {
+    constexpr int s = SB;
+    const uint32_t w0 = v2 << s;
+    const uint32_t w1 = funnel(v3, v2, 32 - s);
+    const uint32_t w2 = (uint32_t)((int32_t)v3 >> (32 - s));
+    o0 = __builtin_subc(l0, w0, 0u, &b);
+    o1 = __builtin_subc(l1, w1, b, &b);
+    o2 = __builtin_subc(0u, w2, b, &b);
+  }
+}
+
+// (l0, l1) - 2^SB wh for a small signed wh, as a lazy digit.
+template <int SB>
+__device__ __forceinline__ L96 sub_shifted32(uint32_t l0, uint32_t l1, uint32_t wh) {
+  unsigned b;
+  uint32_t o0, o1, o2;
+  if constexpr (SB >= 32) {
+    constexpr int s = SB - 32;
+    const uint32_t w1 = wh << s;
+    const uint32_t w2 = s ? (uint32_t)((int32_t)wh >> (32 - s)) : (uint32_t)((int32_t)wh >> 31);
+    o0 = l0;
+    o1 = __builtin_subc(l1, w1, 0u, &b);
+    o2 = __builtin_subc(0u, w2, b, &b);
+  } else {
+    constexpr int s = SB;
+    const uint32_t w0 = wh << s;
+    const uint32_t w1 = (uint32_t)((int32_t)wh >> (32 - s));
+    const uint32_t w2 = (uint32_t)((int32_t)wh >> 31);
+    o0 = __builtin_subc(l0, w0, 0u, &b);
+    o1 = __builtin_subc(l1, w1, b, &b);
+    o2 = __builtin_subc(0u, w2, b, &b);
+  }
+  return L96{((uint64_t)o1 << 32) | o0, (int32_t)o2};
+}
+
 template <int KD, int W, int U>
 struct Field {
   static constexpr uint64_t R = (1ull << W) + (1ull << U);
@@ -201,14 +297,35 @@ __device__ __forceinline__ void split22(uint64_t y, uint32_t& a, uint32_t& b, ui
   c = (uint32_t)(y >> 44);
 }
 
-// Core: V = (v0, v1) is the lane's starting (possibly complemented) x digit,
-// already rotated by rho.  S = (s_lo, s_hi) the correction sum for this lane.
+// Lane m's share of x * r^rot: which digit of x it starts with and whether
+// that digit is complemented; the correction sum is the suffix sum of y from
+// src + 1, or its complement in the total when `flip`.
+template <int KD>
+struct RotLane {
+  int src;        // digit of x loaded into lane m: (m - rot) mod k
+  uint32_t mask;  // all ones when the digit enters negated
+  bool flip;      // same condition: S = total - suffix(src + 1)
+};
+template <int KD>
+__device__ __forceinline__ RotLane<KD> rot_lane(int rot, int m) {
+  const int rp = rot & (KD - 1);
+  const bool neg = (m < rp) != ((rot & KD) != 0);
+  RotLane<KD> r;
+  r.src = (m - rp) & (KD - 1);
+  r.mask = neg ? 0xFFFFFFFFu : 0u;
+  r.flip = neg;
+  return r;
+}
+
+// Core.  (v0, v1): the lane's starting x digit (rotated, complemented).
+// (s0, s1, s2): the correction sum S_m as three 32-bit words.
 // Returns the lazy product digit T_m + Q_{m-1}.
 template <int KD, int W, int U>
-__device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<KD>& y, uint64_t s_lo, uint32_t s_hi,
-                                        int m) {
+__device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<KD>& y, uint32_t s0, uint32_t s1,
+                                        uint32_t s2, int m) {
   constexpr int GPL = Geo<KD>::GPL;
   typedef Field<KD, W, U> F;
+  constexpr int SA = F::SA, SB = F::SB;
   const uint32_t wrap = (m == 0) ? 0xFFFFFFFFu : 0u;
   uint64_t a00 = 0, a01 = 0, a02 = 0, a10 = 0, a11 = 0, a12 = 0;
   static_for<KD>([&](auto T) {
@@ -225,80 +342,139 @@ __device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<K
       v1 = row_ror<GPL>(v1) ^ wrap;
     }
   });
-  // P0 = sum v0*y, P1 = sum v1*y (each < 2^102); column = P0 + P1 2^32 + S - S 2^64.
-  const u128 P0 = (u128)a00 + ((u128)a01 << 22) + ((u128)a02 << 44);
-  const u128 P1 = (u128)a10 + ((u128)a11 << 22) + ((u128)a12 << 44);
-  const u128 S = ((u128)s_hi << 64) | s_lo;
-  const u128 T2 = P0 + S + ((u128)(uint32_t)P1 << 32);
-  const uint64_t L = (uint64_t)T2;
-  const i128 H = (i128)(T2 >> 64) + (i128)(P1 >> 32) - (i128)S;  // column = L + H 2^64
-  // fold three times with 2^64 = 2^SA r - 2^SB
-  const i128 V = (i128)L - (H << F::SB);
-  const i128 Vh = V >> 64;
-  const uint64_t Vl = (uint64_t)V;
-  const i128 W1 = (i128)Vl - (Vh << F::SB);
-  const i128 W1h = W1 >> 64;
-  const uint64_t W1l = (uint64_t)W1;
-  const i128 Tm = (i128)W1l - (W1h << F::SB);  // |Tm| < 2^65
-  const i128 Q = (H + Vh + W1h) << F::SA;       // |Q| < 2^75
+  // Cells at 32-bit positions, C = c0 + c1 2^32 + c2 2^64 + c3 2^96 - S 2^64:
+  // the accumulators sit at bit 0, 22, 44 (v0 limb) and 32, 54, 76 (v1 limb);
+  // + S enters c0..c2.  Every shifted add is one v_mad_u64_u32 with a
+  // power-of-two multiplier held in an SGPR.  c0, c1 < 2^59, c2 < 2^49,
+  // c3 < 2^38.
+  const uint32_t K22 = sgpr_const(1u << 22), K12 = sgpr_const(1u << 12), ONE = sgpr_const(1u);
+  uint64_t c0 = mad32(lo32(a01), K22, a00);
+  c0 = mad32(s0, ONE, c0);
+  uint64_t c1 = mad32(hi32(a01), K22, a10);
+  c1 = mad32(lo32(a02), K12, c1);
+  c1 = mad32(lo32(a11), K22, c1);
+  c1 = mad32(s1, ONE, c1);
+  uint64_t c2 = mad32(hi32(a02), K12, (uint64_t)s2);
+  c2 = mad32(hi32(a11), K22, c2);
+  c2 = mad32(lo32(a12), K12, c2);
+  const uint64_t c3 = mad32(hi32(a12), K12, 0ull);
+  // C = L + H 2^64, L = (l0, l1), H = (h0, h1, h2) signed 96-bit, |H| < 2^71
+  unsigned cy;
+  const uint32_t l0 = lo32(c0);
+  const uint32_t l1 = __builtin_addc(hi32(c0), lo32(c1), 0u, &cy);
+  uint32_t h0 = __builtin_addc(lo32(c2), hi32(c1), cy, &cy);
+  uint32_t h1 = __builtin_addc(hi32(c2), lo32(c3), cy, &cy);
+  uint32_t h2 = hi32(c3) + cy;
+  h0 = __builtin_subc(h0, s0, 0u, &cy);
+  h1 = __builtin_subc(h1, s1, cy, &cy);
+  h2 = h2 - s2 - cy;
+  // fold 1 (2^64 = a r - b): C = a H r + V, V = L - b H; keep V's low 64
+  // bits (v0w, v1w) and Vh = V >> 64 (|Vh| < 2^45)
+  uint32_t v0w, v1w, v2w, v3w;
+  sub_shifted96<SB>(l0, l1, h0, h1, h2, v0w, v1w, v2w, v3w);
+  // fold 2: V = a Vh r + W, W = Vl - b Vh; Wh = W >> 64 (|Wh| < 2^20)
+  uint32_t w0w, w1w, w2w;
+  sub_shifted64<SB>(v0w, v1w, v2w, v3w, w0w, w1w, w2w);
+  // fold 3: T = Wl - b Wh, |T| < 2^65
+  L96 Tm = sub_shifted32<SB>(w0w, w1w, w2w);
+  // Q = a (H + Vh + Wh)
+  const uint32_t vs = (uint32_t)((int32_t)v3w >> 31), ws = (uint32_t)((int32_t)w2w >> 31);
+  uint32_t g0 = __builtin_addc(h0, v2w, 0u, &cy);
+  uint32_t g1 = __builtin_addc(h1, v3w, cy, &cy);
+  uint32_t g2 = h2 + vs + cy;
+  g0 = __builtin_addc(g0, w2w, 0u, &cy);
+  g1 = __builtin_addc(g1, ws, cy, &cy);
+  g2 = g2 + ws + cy;
+  L96 Q;
+  Q.lo = ((uint64_t)g1 << 32 | g0) << SA;
+  Q.hi = (int32_t)((g2 << SA) | (g1 >> (32 - SA)));
   // Q_{m-1} into lane m; lane 0 takes -Q_{k-1}
-  L96 q = l96_from_i128(Q);
-  L96 qin = l96_ror<GPL>(q);
-  L96 t = l96_from_i128(Tm);
-  return (m == 0) ? l96_sub(t, qin) : l96_add(t, qin);
+  const L96 nq = l96_sub(L96{0, 0}, Q);
+  const L96 qs = (m == KD - 1) ? nq : Q;
+  return l96_add(Tm, l96_ror<GPL>(qs));
 }
 
 // Twiddle entry layout (u32 words): 3k limbs of the digits, then for
-// i = 0..k-1 the suffix sum sum_{t >= i} y_t as (lo, mid, hi) words.
+// i = 0..k the suffix sum sum_{t >= i} y_t as (lo, mid, hi) words
+// (suffix(k) = 0), padded to a multiple of 4 words.
 template <int KD>
 struct TwLayout {
   static constexpr int LIMBS = 0;
   static constexpr int SUF = 3 * KD;
-  static constexpr int WORDS = 6 * KD;
+  static constexpr int WORDS = (6 * KD + 3 + 3) & ~3;
 };
 
-// x * tw * r^rot for a table twiddle; x is this lane's semi-normalised digit.
-template <int KD, int W, int U>
-__device__ __forceinline__ L96 mul_twiddle(uint64_t x, const uint32_t* __restrict__ tw, int rot, int l, int m) {
-  typedef Geo<KD> Gm;
-  const int rp = rot & (KD - 1);
-  const bool sigma = (rot & KD) != 0;
-  const int src = Gm::lane_of(l, (m - rp) & (KD - 1));
-  uint32_t x0 = (uint32_t)__shfl((int)(uint32_t)x, src, 64);
-  uint32_t x1 = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, 64);
-  const uint32_t neg = ((m < rp) != sigma) ? 0xFFFFFFFFu : 0u;
-  x0 ^= neg;
-  x1 ^= neg;
-  YLimbs<KD> y;
+// S_m for lane m from a table entry: suffix(src + 1), or total - it.
+template <int KD>
+__device__ __forceinline__ void tw_correction(const uint32_t* __restrict__ tw, const RotLane<KD>& rl, uint32_t& s0,
+                                              uint32_t& s1, uint32_t& s2) {
+  const uint32_t* suf = tw + TwLayout<KD>::SUF;
+  const int i = rl.src + 1;
+  const uint64_t a = (uint64_t)suf[3 * i] | ((uint64_t)suf[3 * i + 1] << 32);
+  const uint32_t ah = suf[3 * i + 2];
+  const uint64_t t = (uint64_t)suf[0] | ((uint64_t)suf[1] << 32);
+  const uint32_t th = suf[2];
+  const uint64_t d = t - a;
+  const uint32_t dh = th - ah - (uint32_t)(t < a);
+  const uint64_t sl = rl.flip ? d : a;
+  s0 = (uint32_t)sl;
+  s1 = (uint32_t)(sl >> 32);
+  s2 = rl.flip ? dh : ah;
+}
+
+template <int KD>
+__device__ __forceinline__ void tw_limbs(const uint32_t* __restrict__ tw, YLimbs<KD>& y) {
   const uint4* lp = reinterpret_cast<const uint4*>(tw + TwLayout<KD>::LIMBS);
   static_for<3 * KD / 4>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    uint4 q = lp[i];
+    const uint4 q = lp[i];
     y.l[4 * i] = q.x;
     y.l[4 * i + 1] = q.y;
     y.l[4 * i + 2] = q.z;
     y.l[4 * i + 3] = q.w;
   });
-  // correction set: suffix from idx = m - rp + 1 (wrapped into [1, k]), or its
-  // complement when rp > m, complemented again when sigma
-  int idx = m - rp + 1;
-  if (idx <= 0) idx += KD;
-  const bool flip = (rp > m) != sigma;
-  const uint32_t* suf = tw + TwLayout<KD>::SUF;
-  uint64_t s_lo = 0;
-  uint32_t s_hi = 0;
-  if (idx < KD) {
-    s_lo = (uint64_t)suf[3 * idx] | ((uint64_t)suf[3 * idx + 1] << 32);
-    s_hi = suf[3 * idx + 2];
-  }
-  if (flip) {
-    const uint64_t t_lo = (uint64_t)suf[0] | ((uint64_t)suf[1] << 32);
-    const uint32_t t_hi = suf[2];
-    const u128 d = (((u128)t_hi << 64) | t_lo) - (((u128)s_hi << 64) | s_lo);
-    s_lo = (uint64_t)d;
-    s_hi = (uint32_t)(d >> 64);
-  }
-  return mul_core<KD, W, U>(x0, x1, y, s_lo, s_hi, m);
+}
+
+// x * tw * r^rot where lane m already holds digit rl.src of x (xs).
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_twiddle_pre(uint64_t xs, const uint32_t* __restrict__ tw, const RotLane<KD>& rl,
+                                               int m) {
+  YLimbs<KD> y;
+  tw_limbs<KD>(tw, y);
+  uint32_t s0, s1, s2;
+  tw_correction<KD>(tw, rl, s0, s1, s2);
+  return mul_core<KD, W, U>((uint32_t)xs ^ rl.mask, (uint32_t)(xs >> 32) ^ rl.mask, y, s0, s1, s2, m);
+}
+
+// x * tw * r^rot where lane m holds digit m of x (the digit is fetched from
+// the lane holding digit (m - rot) mod k with a cross-lane permute).
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_twiddle(uint64_t x, const uint32_t* __restrict__ tw, int rot, int l, int m) {
+  const RotLane<KD> rl = rot_lane<KD>(rot, m);
+  const int src = Geo<KD>::lane_of(l, rl.src);
+  const uint32_t x0 = (uint32_t)__shfl((int)(uint32_t)x, src, 64);
+  const uint32_t x1 = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, 64);
+  return mul_twiddle_pre<KD, W, U>(((uint64_t)x1 << 32) | x0, tw, rl, m);
+}
+
+// Same with a wavefront-uniform twiddle entry and rotation: the limbs are
+// read with scalar loads (uniform address, read-only table) and stay in
+// SGPRs; only the per-lane correction sum is a vector load.
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_twiddle_uniform(uint64_t x, const uint32_t* __restrict__ tw, int rot, int l,
+                                                   int m) {
+  const RotLane<KD> rl = rot_lane<KD>(rot, m);
+  const int src = Geo<KD>::lane_of(l, rl.src);
+  const uint32_t x0 = (uint32_t)__shfl((int)(uint32_t)x, src, 64) ^ rl.mask;
+  const uint32_t x1 = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, 64) ^ rl.mask;
+  YLimbs<KD> y;
+  static_for<3 * KD>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    y.l[i] = tw[TwLayout<KD>::LIMBS + i];
+  });
+  uint32_t s0, s1, s2;
+  tw_correction<KD>(tw, rl, s0, s1, s2);
+  return mul_core<KD, W, U>(x0, x1, y, s0, s1, s2, m);
 }
 
 // x * y for two data elements: every lane of the element loads all of y's
@@ -307,13 +483,16 @@ __device__ __forceinline__ L96 mul_twiddle(uint64_t x, const uint32_t* __restric
 template <int KD, int W, int U>
 __device__ __forceinline__ L96 mul_data(uint64_t x, const uint64_t (&yd)[KD], int m) {
   YLimbs<KD> y;
-  u128 S = 0;
+  uint64_t sl = 0;
+  uint32_t sh = 0;
   static_for<KD>([&](auto T) {
     constexpr int t = decltype(T)::value;
     split22(yd[t], y.l[3 * t], y.l[3 * t + 1], y.l[3 * t + 2]);
-    if (t > m) S += yd[t];
+    const uint64_t add = (t > m) ? yd[t] : 0ull;
+    sl += add;
+    sh += (uint32_t)(sl < add);
   });
-  return mul_core<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), y, (uint64_t)S, (uint32_t)(S >> 64), m);
+  return mul_core<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), y, (uint32_t)sl, (uint32_t)(sl >> 32), sh, m);
 }
 
 // ------------------------------------------------------------------------

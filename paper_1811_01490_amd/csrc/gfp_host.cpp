@@ -99,20 +99,22 @@ Big from_digits(const gfp_field* f, const uint64_t* dg) {
 }
 
 // Twiddle-entry layout of the kernels: limbs (22, 22, 20 bits) of every
-// digit, then the suffix sums sum_{t >= i} y_t as three 32-bit words.
+// digit, then the suffix sums sum_{t >= i} y_t, i = 0..k (the last is 0), as
+// three 32-bit words each; padded to gfpk::tw_words(k) words.
 void make_entry(uint32_t k, const uint64_t* y, uint32_t* e) {
   for (uint32_t t = 0; t < k; ++t) {
     e[3 * t] = (uint32_t)(y[t] & 0x3FFFFFu);
     e[3 * t + 1] = (uint32_t)((y[t] >> 22) & 0x3FFFFFu);
     e[3 * t + 2] = (uint32_t)(y[t] >> 44);
   }
-  for (uint32_t i = 0; i < k; ++i) {
+  for (uint32_t i = 0; i <= k; ++i) {
     gfp::u128 s = 0;
     for (uint32_t t = i; t < k; ++t) s += y[t];
     e[3 * k + 3 * i] = (uint32_t)s;
     e[3 * k + 3 * i + 1] = (uint32_t)(s >> 32);
     e[3 * k + 3 * i + 2] = (uint32_t)(s >> 64);
   }
+  for (int w = 6 * (int)k + 3; w < gfpk::tw_words((int)k); ++w) e[w] = 0;
 }
 
 // w_n in Montgomery form (Alg. 1 with g = h^((p-1)/n))

@@ -44,6 +44,6 @@ hipError_t launch_pass(int k, int w, int u, const PassArgs& p, hipStream_t st);
 hipError_t launch_elementwise(int k, int w, int u, const EwArgs& a, hipStream_t st);
 
 // words per twiddle-table entry (see TwLayout in gfp_device.hpp)
-inline int tw_words(int k) { return 6 * k; }
+inline int tw_words(int k) { return (6 * k + 6) & ~3; }
 
 }  // namespace gfpk

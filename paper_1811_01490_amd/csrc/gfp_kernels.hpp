@@ -25,7 +25,12 @@ namespace gfpk {
 // MODE_SCALE: every slot multiplied by one constant (inverse pass 0: 1/N).
 enum { MODE_PLAIN = 0, MODE_SCALE = 1 };
 
-template <int KD, int W, int U, bool INV, int MODE, bool LAST>
+// UNIF: the K^(e-1-s) groups sharing one twiddle base a are spread over
+// whole wavefronts (group g of a wavefront is j = a + (qb G + g) Ns), so the
+// twiddles and rotations of a wavefront are uniform: the table entry is read
+// with scalar loads into SGPRs and feeds v_mad_u64_u32 as its SGPR operand.
+// Used when every a has at least G groups (all passes but the last).
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF>
 __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
                                               uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
                                               const uint32_t* __restrict__ tw, int log2n, int log2ns, uint64_t ngroups) {
@@ -34,12 +39,24 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
   constexpr int LOGKB = ilog2(KB);
   const int l = Gm::lane();
   const int m = Gm::digit(l);
-  const uint64_t j = ((uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * Gm::G + Gm::group(l);
-  const bool active = j < ngroups;
-  const uint64_t jj = active ? j : 0;  // inactive groups compute on element 0 and store nothing
-  const uint64_t nk = ngroups;         // N / K
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const uint64_t nk = ngroups;  // N / K
   const uint64_t ns = 1ull << log2ns;
-  const uint64_t a = jj & (ns - 1);
+  uint64_t j, a;
+  if constexpr (UNIF) {
+    const int log2wpa = log2n - LOGKB - log2ns - ilog2(Gm::G);  // wavefronts per twiddle base
+    a = (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave >> log2wpa));
+    const uint64_t qb = wave & ((1ull << log2wpa) - 1);
+    j = a + ((qb * Gm::G + Gm::group(l)) << log2ns);
+  } else {
+    j = wave * Gm::G + Gm::group(l);
+    a = j & (ns - 1);
+  }
+  // inactive groups (only in the last block of small transforms) compute on
+  // element 0 and store nothing; with UNIF the grid covers the groups exactly
+  const bool active = UNIF || j < ngroups;
+  const uint64_t jj = active ? j : 0;
+  if (!active) a = 0;
 
   uint64_t x[KB];
   static_for<KB>([&](auto T) {
@@ -47,6 +64,9 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
     x[t] = in[(uint64_t)m * sd_in + (jj + (uint64_t)t * nk) * se_in];
   });
 
+  // Twiddle of slot t: w_L^(a t) = r^rho w^(c N/L) with rho = (a t) / Ns,
+  // c = (a t) mod Ns.  r^rho is a digit rotation: lane m takes digit
+  // (m - rho) mod k of the element from the lane holding it.
   L96 v[KB];
   if constexpr (MODE == MODE_SCALE) {
     static_for<KB>([&](auto T) {
@@ -68,8 +88,11 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
         const int rho = (int)(e >> log2ns);
         const uint64_t c = e & (ns - 1);
         const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
-        const uint32_t* ent = tw + (c << shift) * TwLayout<KD>::WORDS;
-        v[t] = mul_twiddle<KD, W, U>(x[t], ent, rot, l, m);
+        if constexpr (UNIF) {
+          v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
+        } else {
+          v[t] = mul_twiddle<KD, W, U>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
+        }
       });
     }
   }
@@ -102,12 +125,13 @@ __global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict_
   const uint64_t e = ((uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * Gm::G + Gm::group(l);
   const bool active = e < n;
   const uint64_t ee = active ? e : 0;
-  const uint64_t xm = x[(uint64_t)m * ldx + ee];
   L96 t;
   if constexpr (OP == GFP_OP_ADD || OP == GFP_OP_SUB) {
+    const uint64_t xm = x[(uint64_t)m * ldx + ee];
     const uint64_t ym = y[(uint64_t)m * ldy + ee];
     t = (OP == GFP_OP_ADD) ? l96_add(l96(xm), l96(ym)) : l96_sub(l96(xm), l96(ym));
   } else if constexpr (OP == GFP_OP_MUL || OP == GFP_OP_MUL_SCALE) {
+    const uint64_t xm = x[(uint64_t)m * ldx + ee];
     uint64_t yd[KD];
     static_for<KD>([&](auto T) {
       constexpr int tt = decltype(T)::value;
@@ -116,12 +140,12 @@ __global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict_
     t = mul_data<KD, W, U>(xm, yd, m);
     if constexpr (OP == GFP_OP_MUL_SCALE) {
       const uint64_t sn = seminorm<KD, W, U>(t, m);
-      t = mul_twiddle<KD, W, U>(sn, cst, 0, l, m);
+      t = mul_twiddle_pre<KD, W, U>(sn, cst, rot_lane<KD>(0, m), m);
     }
-  } else if constexpr (OP == GFP_OP_MUL_CONST) {
-    t = mul_twiddle<KD, W, U>(xm, cst, (int)(((s % (2 * KD)) + 2 * KD) % (2 * KD)), l, m);
-  } else {  // GFP_OP_MUL_POW_R: x * r^s by rotation with the multiply by the constant 1
-    t = mul_twiddle<KD, W, U>(xm, cst, (int)(((s % (2 * KD)) + 2 * KD) % (2 * KD)), l, m);
+  } else {  // GFP_OP_MUL_CONST: x * c * r^s; GFP_OP_MUL_POW_R: the same with c = 1
+    const RotLane<KD> rl = rot_lane<KD>((int)(((s % (2 * KD)) + 2 * KD) % (2 * KD)), m);
+    const uint64_t xs = x[(uint64_t)rl.src * ldx + ee];
+    t = mul_twiddle_pre<KD, W, U>(xs, cst, rl, m);
   }
   const uint64_t d = canonicalize<KD, W, U>(t, l, m);
   if (active) z[(uint64_t)m * ldz + ee] = d;
@@ -139,15 +163,22 @@ template <int KD, int W, int U>
 hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
   const unsigned nb = blocks_for(p.ngroups, Geo<KD>::G);
   if (nb == 0) return hipSuccess;
-#define GFP_LAUNCH(INV, MODE, LAST)                                                                                  \
-  hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, p.out, \
-                     p.se_out, p.sd_out, p.tw, p.log2n, p.log2ns, p.ngroups)
+#define GFP_LAUNCH(INV, MODE, LAST, UNIF)                                                                           \
+  hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST, UNIF>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, \
+                     p.out, p.se_out, p.sd_out, p.tw, p.log2n, p.log2ns, p.ngroups)
+  // uniform twiddles when every base a has at least one wavefront of groups
+  const int lk = ilog2(2 * KD);
+  const bool unif = p.log2ns > 0 && (p.log2n - lk - p.log2ns) >= ilog2(Geo<KD>::G);
   if (p.scale) {
-    if (p.last) GFP_LAUNCH(true, MODE_SCALE, true); else GFP_LAUNCH(true, MODE_SCALE, false);
+    if (p.last) GFP_LAUNCH(true, MODE_SCALE, true, false); else GFP_LAUNCH(true, MODE_SCALE, false, false);
   } else if (p.inverse) {
-    if (p.last) GFP_LAUNCH(true, MODE_PLAIN, true); else GFP_LAUNCH(true, MODE_PLAIN, false);
+    if (p.last) GFP_LAUNCH(true, MODE_PLAIN, true, false);
+    else if (unif) GFP_LAUNCH(true, MODE_PLAIN, false, true);
+    else GFP_LAUNCH(true, MODE_PLAIN, false, false);
   } else {
-    if (p.last) GFP_LAUNCH(false, MODE_PLAIN, true); else GFP_LAUNCH(false, MODE_PLAIN, false);
+    if (p.last) GFP_LAUNCH(false, MODE_PLAIN, true, false);
+    else if (unif) GFP_LAUNCH(false, MODE_PLAIN, false, true);
+    else GFP_LAUNCH(false, MODE_PLAIN, false, false);
   }
 #undef GFP_LAUNCH
   return hipGetLastError();
