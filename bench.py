@@ -21,7 +21,6 @@ Extra objects:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -36,7 +35,6 @@ K_DIG, R = 8, 2 ** 63 + 2 ** 34
 LOG2N = 20
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit integer lane-ops per second (Tops/s)
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1811_01490_amd/csrc/gfp_kernels.hpp", "paper_1811_01490_amd/csrc/gfp_device.hpp"]
 
 
 def pass_counts(N: int, K: int, s: int, k: int):
@@ -60,17 +58,12 @@ def pass_counts(N: int, K: int, s: int, k: int):
     return general, butterflies, ops
 
 
-def source_hash() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profiles(kernel_key: str):
-    """HBM traffic per launch from a committed rocprofv3 --pmc summary, if it
-    was taken on the current kernel sources (else None)."""
+    """HBM bytes per launch of a kernel from the committed rocprofv3 --pmc
+    summary (profiles/pmc_traffic.json), if it was taken on the current
+    kernel sources; else None."""
+    from paper_1811_01490_amd.profiling import source_hash
+
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -157,6 +150,11 @@ def main():
     ws = torch.empty(f.fft_workspace_size(N) // 8, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
 
+    # calibration copy of known size (64 MiB read + 64 MiB written), outside the
+    # timed region: rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of this kernel
+    # scales the counters of the FFT kernels to bytes
+    y.copy_(x)
+    torch.cuda.synchronize()
     for _ in range(args.warmup):
         f.fft_forward(x, y=y, workspace=ws)
     torch.cuda.synchronize()
@@ -193,7 +191,10 @@ def main():
     gen, bfl, ops = pass_counts(N, K, dom, K_DIG)
     dom_us = per_pass[dom] * 1e3
     achieved = ops / (dom_us * 1e-6) / 1e12
-    key = "k_pass<8,63,34,fwd,%s>" % ("last" if dom == e - 1 else "mid")
+    # kernel variant the library runs at stage dom (uniform twiddles on the
+    # middle stages, see gfp_kernels.hpp)
+    key = "k_pass<8,63,34,fwd,last>" if dom == e - 1 else ("k_pass<8,63,34,fwd,mid,unif>" if dom > 0
+                                                          else "k_pass<8,63,34,fwd,mid>")
     traffic = traffic_from_profiles(key)
     alg_bytes = 2 * N * K_DIG * 8
     out = {
@@ -216,7 +217,8 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": key + " pass %d" % dom,
+            "kernel": key,
+            "stage": dom,
             "achieved": round(achieved, 3),
             "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "Tops/s",
