@@ -143,6 +143,38 @@ int gfp_polymul_workspace_size(const gfp_field* f, uint64_t la, uint64_t lb, uin
 int gfp_polymul(const gfp_field* f, const uint64_t* a, uint64_t la, uint64_t ld_a, const uint64_t* b, uint64_t lb,
                 uint64_t ld_b, uint64_t* c, uint64_t ld_c, void* workspace, uint64_t ws_bytes, void* stream);
 
+/* One request of a batched product: c = a * b as in gfp_polymul. */
+typedef struct gfp_polymul_desc {
+  const uint64_t* a;
+  uint64_t la, ld_a;
+  const uint64_t* b;
+  uint64_t lb, ld_b;
+  uint64_t* c;
+  uint64_t ld_c;
+} gfp_polymul_desc;
+
+/* gfp_polymul_batched flags */
+#define GFP_BATCH_GRAPH 1 /* capture the launches into a hipGraph, cache it per argument list, replay it */
+
+/* Workspace bytes gfp_polymul_batched needs for this request list. */
+int gfp_polymul_batched_workspace_size(const gfp_field* f, uint32_t n, const gfp_polymul_desc* d, uint64_t* bytes);
+
+/* n independent products (section 3.3, Alg. Fast Convolution), each exactly
+ * as gfp_polymul, of mixed sizes.  d: host array of n descriptors (device
+ * pointers inside, caller-owned).  Requests are grouped by transform size;
+ * each group runs as one launch per pass over all its operands (in chunks
+ * bounded by the workspace), so the number of launches does not grow with
+ * n.  workspace: device memory of gfp_polymul_batched_workspace_size bytes
+ * (required with GFP_BATCH_GRAPH), or NULL for a stream-ordered allocation.
+ * flags & GFP_BATCH_GRAPH: the launch sequence is captured into a hipGraph
+ * on the first call with this exact argument list (descriptors, workspace,
+ * stream) and replayed on later calls; stream must not be NULL.  Results
+ * do not depend on the batch composition (bit-identical to gfp_polymul).
+ * Errors: GFP_EINVAL (bad descriptor, n == 0, NULL stream with
+ * GFP_BATCH_GRAPH, workspace too small), GFP_EUNSUPPORTED, GFP_EDEVICE. */
+int gfp_polymul_batched(const gfp_field* f, uint32_t n, const gfp_polymul_desc* d, void* workspace, uint64_t ws_bytes,
+                        int flags, void* stream);
+
 /* Elementwise z = op(x, y) on n elements (section 2: addition, subtraction,
  * multiplication by a power of r, multiplication).  x, y, z device vectors
  * (y unused for GFP_OP_MUL_POW_R and GFP_OP_MUL_CONST); z may equal x or y.

@@ -1,0 +1,62 @@
+// Copies between caller vectors (digit-major) and the padded element-major
+// work vectors of the batched product.  Zero padding is written by the
+// kernel (no memset), so a captured graph can be replayed safely.
+#include "gfp_internal.hpp"
+
+namespace gfpk {
+
+struct CopyBatch {
+  CopyDesc d[kCopyBatch];
+};
+
+// thread -> (element i, digit d) of work vector blockIdx.y: work[v n k + i k + d]
+__global__ __launch_bounds__(256) void k_pad(const CopyBatch desc, uint64_t* __restrict__ work, uint64_t n, uint32_t k,
+                                             uint32_t log2k) {
+  const uint32_t v = blockIdx.y;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * k) return;
+  const uint64_t i = t >> log2k;
+  const uint32_t d = (uint32_t)(t & (k - 1));
+  const CopyDesc cd = desc.d[v];
+  work[(uint64_t)v * n * k + t] = (i < cd.len) ? cd.src[(uint64_t)d * cd.ld + i] : 0ull;
+}
+
+// thread -> (digit d, element i) of caller vector blockIdx.y, i < len
+__global__ __launch_bounds__(256) void k_unpad(const CopyBatch desc, const uint64_t* __restrict__ work, uint64_t n,
+                                               uint64_t maxlen, uint32_t k) {
+  const uint32_t v = blockIdx.y;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= maxlen * k) return;
+  const uint32_t d = (uint32_t)(t / maxlen);
+  const uint64_t i = t - (uint64_t)d * maxlen;
+  const CopyDesc cd = desc.d[v];
+  if (i >= cd.len) return;
+  cd.dst[(uint64_t)d * cd.ld + i] = work[(uint64_t)v * n * k + i * k + d];
+}
+
+hipError_t launch_pad(int k, const CopyDesc* d, uint32_t nvec, uint64_t* work, uint64_t n, hipStream_t st) {
+  if (nvec == 0) return hipSuccess;
+  if (nvec > kCopyBatch) return hipErrorInvalidValue;
+  CopyBatch b;
+  for (uint32_t i = 0; i < nvec; ++i) b.d[i] = d[i];
+  const uint64_t tot = n * (uint64_t)k;
+  dim3 grid((unsigned)((tot + 255) / 256), nvec);
+  uint32_t lk = 0;
+  while ((1u << lk) < (uint32_t)k) ++lk;
+  hipLaunchKernelGGL(k_pad, grid, dim3(256), 0, st, b, work, n, (uint32_t)k, lk);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpad(int k, const CopyDesc* d, uint32_t nvec, const uint64_t* work, uint64_t n, uint64_t maxlen,
+                        hipStream_t st) {
+  if (nvec == 0 || maxlen == 0) return hipSuccess;
+  if (nvec > kCopyBatch) return hipErrorInvalidValue;
+  CopyBatch b;
+  for (uint32_t i = 0; i < nvec; ++i) b.d[i] = d[i];
+  const uint64_t tot = maxlen * (uint64_t)k;
+  dim3 grid((unsigned)((tot + 255) / 256), nvec);
+  hipLaunchKernelGGL(k_unpad, grid, dim3(256), 0, st, b, work, n, maxlen, (uint32_t)k);
+  return hipGetLastError();
+}
+
+}  // namespace gfpk

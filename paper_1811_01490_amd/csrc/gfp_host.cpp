@@ -48,6 +48,7 @@ struct gfp_field {
   std::mutex mu;
   std::map<std::pair<int, uint64_t>, DevTables> tables;
   std::map<int, DevConsts> consts;
+  std::map<uint64_t, hipGraphExec_t> graphs;  // batched products, keyed by argument hash
 };
 
 namespace {
@@ -268,62 +269,60 @@ int get_workspace(void* ws, uint64_t ws_bytes, uint64_t need, hipStream_t st, Sc
   return GFP_OK;
 }
 
-// Run the e passes of a transform of size n (log2n) from X to Y (both
-// digit-major).  Intermediate passes write element-major vectors (one
-// element = k contiguous digits, so the strided element accesses of the
-// following pass read whole 64- or 128-byte segments), alternating between
-// W1 and W2 (each n elements); X is only read by pass 0.  When X == Y and
-// e == 1 the pass writes W1 and the result is copied.
-int run_transform(gfp_field* f, int log2n, int e, bool inverse, const uint64_t* X, uint64_t ldx, uint64_t* Y,
-                  uint64_t ldy, uint64_t* W1, uint64_t* W2, hipStream_t st) {
+// Vector view for the pass scheduler: digit d of element i of vector v at
+// base[v * vs + i * se + d * sd].
+struct VecView {
+  const uint64_t* p;
+  uint64_t se, sd, vs;
+};
+
+// Run the e passes of nvec transforms of size n (log2n) from X to Y.
+// Intermediate passes write element-major vectors (one element = k
+// contiguous digits, so the strided element accesses of the following pass
+// read whole 64- or 128-byte segments), alternating between W1 and W2 (each
+// nvec * n elements); X is only read by pass 0.  `canonical`: the last pass
+// writes the canonical encoding (else congruent digits in [0, 2^64)).  When
+// Y aliases X and e == 1 the pass writes W1 and the result is copied.
+int run_transform(gfp_field* f, int log2n, int e, bool inverse, VecView X, VecView Y, uint64_t nvec, bool canonical,
+                  uint64_t* W1, uint64_t* W2, hipStream_t st) {
   const uint64_t n = 1ull << log2n;
   const uint64_t k = f->k;
   const DevTables* t = nullptr;
   int rc = get_tables(f, n, &t);
   if (rc != GFP_OK) return rc;
   const int lk = log2_exact(2ull * f->k);
-  const bool copy_back = (e == 1 && X == Y);
-  const uint64_t* src = X;
-  uint64_t se = 1, sd = ldx;
+  if (e == 1 && X.p == Y.p) return GFP_EINVAL;  // a single pass cannot run in place
+  VecView src = X;
   for (int s = 0; s < e; ++s) {
-    uint64_t* dst;
-    uint64_t dse, dsd;
-    if (s == e - 1 && !copy_back) {
+    VecView dst;
+    if (s == e - 1) {
       dst = Y;
-      dse = 1;
-      dsd = ldy;
-    } else if (s == e - 1) {  // copy-back: digit-major into W1
-      dst = W1;
-      dse = 1;
-      dsd = n;
     } else {
-      dst = (((e - 2 - s) % 2) == 0) ? W1 : W2;  // pass e-2 -> W1, e-3 -> W2, ...
-      dse = k;
-      dsd = 1;
+      dst.p = (((e - 2 - s) % 2) == 0) ? W1 : W2;  // pass e-2 -> W1, e-3 -> W2, ...
+      dst.se = k;
+      dst.sd = 1;
+      dst.vs = n * k;
     }
     gfpk::PassArgs p;
-    p.in = src;
-    p.se_in = se;
-    p.sd_in = sd;
-    p.out = dst;
-    p.se_out = dse;
-    p.sd_out = dsd;
+    p.in = src.p;
+    p.se_in = src.se;
+    p.sd_in = src.sd;
+    p.out = const_cast<uint64_t*>(dst.p);
+    p.se_out = dst.se;
+    p.sd_out = dst.sd;
     p.log2n = log2n;
     p.log2ns = s * lk;
     p.ngroups = n >> lk;
     p.inverse = inverse;
     p.scale = inverse && s == 0;
     p.tw = p.scale ? t->ninv : (inverse ? t->inv : t->fwd);
-    p.last = (s == e - 1);
+    p.last = (s == e - 1) && canonical;
+    p.nvec = nvec;
+    p.vin = src.vs;
+    p.vout = dst.vs;
     hipError_t he = gfpk::launch_pass((int)f->k, f->w, f->u, p, st);
     if (he != hipSuccess) return hip_status(he);
     src = dst;
-    se = dse;
-    sd = dsd;
-  }
-  if (copy_back) {
-    hipError_t he = hipMemcpy2DAsync(Y, ldy * 8, src, sd * 8, n * 8, f->k, hipMemcpyDeviceToDevice, st);
-    if (he != hipSuccess) return hip_status(he);
   }
   return GFP_OK;
 }
@@ -343,7 +342,163 @@ int transform_entry(const gfp_field* cf, uint64_t n, const uint64_t* x, uint64_t
   uint64_t* w = nullptr;
   rc = get_workspace(ws, ws_bytes, 2ull * n * f->k * 8, st, s, &w);
   if (rc != GFP_OK) return rc;
-  return run_transform(f, log2n, e, inverse, x, ldx, y, ldy, w, w + n * f->k, st);
+  VecView X{x, 1, ldx, 0}, Y{y, 1, ldy, 0};
+  if (e == 1 && x == y) {
+    // one pass cannot run in place: transform into W2 (digit-major, ld n), copy back
+    VecView T{w + n * f->k, 1, n, 0};
+    rc = run_transform(f, log2n, e, inverse, X, T, 1, true, w, w, st);
+    if (rc != GFP_OK) return rc;
+    return hip_status(hipMemcpy2DAsync(y, ldy * 8, T.p, n * 8, n * 8, f->k, hipMemcpyDeviceToDevice, st));
+  }
+  return run_transform(f, log2n, e, inverse, X, Y, 1, true, w, w + n * f->k, st);
+}
+
+// ---------------------------------------------------------------------------
+// polynomial products: one size class, a chunk of C requests
+// ---------------------------------------------------------------------------
+// Workspace per chunk: A (2C padded operands), F (2C transforms), W1, W2
+// (2C each), all element-major vectors of n elements: 8 C n k words.
+uint64_t chunk_words(uint64_t n, uint64_t k, uint64_t C) { return 8ull * C * n * k; }
+
+struct PolyReq {
+  const uint64_t* a;
+  uint64_t la, lda;
+  const uint64_t* b;
+  uint64_t lb, ldb;
+  uint64_t* c;
+  uint64_t ldc;
+};
+
+// pad / unpad with descriptors passed by value (so graph capture keeps them)
+int copy_in(gfp_field* f, const std::vector<gfpk::CopyDesc>& d, uint64_t* work, uint64_t n, hipStream_t st) {
+  for (size_t i = 0; i < d.size(); i += gfpk::kCopyBatch) {
+    const uint32_t cnt = (uint32_t)std::min<size_t>(gfpk::kCopyBatch, d.size() - i);
+    hipError_t he = gfpk::launch_pad((int)f->k, d.data() + i, cnt, work + i * n * f->k, n, st);
+    if (he != hipSuccess) return hip_status(he);
+  }
+  return GFP_OK;
+}
+
+int copy_out(gfp_field* f, const std::vector<gfpk::CopyDesc>& d, const uint64_t* work, uint64_t n, hipStream_t st) {
+  for (size_t i = 0; i < d.size(); i += gfpk::kCopyBatch) {
+    const uint32_t cnt = (uint32_t)std::min<size_t>(gfpk::kCopyBatch, d.size() - i);
+    uint64_t maxlen = 0;
+    for (uint32_t j = 0; j < cnt; ++j) maxlen = std::max(maxlen, d[i + j].len);
+    hipError_t he = gfpk::launch_unpad((int)f->k, d.data() + i, cnt, work + i * n * f->k, n, maxlen, st);
+    if (he != hipSuccess) return hip_status(he);
+  }
+  return GFP_OK;
+}
+
+// Enqueue the products of C requests of transform size n = 2^log2n.
+int polymul_chunk(gfp_field* f, int log2n, int e, const PolyReq* r, uint64_t C, uint64_t* ws, hipStream_t st) {
+  const uint64_t n = 1ull << log2n, k = f->k;
+  const uint64_t vw = n * k;  // words per vector
+  uint64_t* A = ws;
+  uint64_t* F = A + 2 * C * vw;
+  uint64_t* W1 = F + 2 * C * vw;
+  uint64_t* W2 = W1 + 2 * C * vw;
+  std::vector<gfpk::CopyDesc> din(2 * C), dout(C);
+  for (uint64_t i = 0; i < C; ++i) {
+    din[i] = gfpk::CopyDesc{r[i].a, nullptr, r[i].la, r[i].lda};
+    din[C + i] = gfpk::CopyDesc{r[i].b, nullptr, r[i].lb, r[i].ldb};
+    dout[i] = gfpk::CopyDesc{nullptr, r[i].c, r[i].la + r[i].lb - 1, r[i].ldc};
+  }
+  int rc = copy_in(f, din, A, n, st);
+  // forward transforms of all 2C operands in one launch per pass; the last
+  // pass leaves congruent (not canonical) digits for the pointwise product
+  const VecView em{A, k, 1, vw}, fm{F, k, 1, vw};
+  if (rc == GFP_OK) rc = run_transform(f, log2n, e, false, em, fm, 2 * C, false, W1, W2, st);
+  if (rc != GFP_OK) return rc;
+  gfpk::EwArgs ew;
+  ew.op = GFP_OP_MUL;
+  ew.x = F;
+  ew.xse = k;
+  ew.xsd = 1;
+  ew.y = F + C * vw;
+  ew.yse = k;
+  ew.ysd = 1;
+  ew.z = A;
+  ew.zse = k;
+  ew.zsd = 1;
+  ew.n = C * n;  // C vectors back to back
+  ew.s = 0;
+  ew.cst = nullptr;
+  hipError_t he = gfpk::launch_elementwise((int)k, f->w, f->u, ew, st);
+  if (he != hipSuccess) return hip_status(he);
+  rc = run_transform(f, log2n, e, true, em, fm, C, true, W1, W2, st);
+  if (rc != GFP_OK) return rc;
+  return copy_out(f, dout, F, n, st);
+}
+
+int check_req(const gfp_field* f, const PolyReq& q) {
+  if (!q.a || !q.b || !q.c || q.la == 0 || q.lb == 0) return GFP_EINVAL;
+  if (q.lda < q.la || q.ldb < q.lb || q.ldc < q.la + q.lb - 1) return GFP_EINVAL;
+  (void)f;
+  return GFP_OK;
+}
+
+// Batched products: requests grouped by transform size; each group in
+// chunks of at most `cap` requests whose workspace fits kChunkBytes (or the
+// whole group when smaller).
+const uint64_t kChunkBytes = 4ull << 30;
+
+struct BatchPlan {
+  struct Group {
+    int log2n, e;
+    std::vector<PolyReq> reqs;
+    uint64_t cap;  // requests per chunk
+  };
+  std::vector<Group> groups;  // ascending size
+  uint64_t ws_words = 0;
+};
+
+int plan_batch(gfp_field* f, uint32_t n, const gfp_polymul_desc* d, BatchPlan& plan) {
+  if (!f || !d || n == 0) return GFP_EINVAL;
+  if (!f->gpu_shape) return GFP_EUNSUPPORTED;
+  std::map<int, size_t> index;
+  for (uint32_t i = 0; i < n; ++i) {
+    PolyReq q{d[i].a, d[i].la, d[i].ld_a, d[i].b, d[i].lb, d[i].ld_b, d[i].c, d[i].ld_c};
+    int rc = check_req(f, q);
+    if (rc != GFP_OK) return rc;
+    uint64_t N;
+    rc = gfp_polymul_size(f, q.la, q.lb, &N);
+    if (rc != GFP_OK) return rc;
+    int log2n, e;
+    check_size(f, N, &log2n, &e);
+    auto it = index.find(log2n);
+    if (it == index.end()) {
+      index[log2n] = plan.groups.size();
+      plan.groups.push_back(BatchPlan::Group{log2n, e, {}, 0});
+      it = index.find(log2n);
+    }
+    plan.groups[it->second].reqs.push_back(q);
+  }
+  std::sort(plan.groups.begin(), plan.groups.end(),
+            [](const BatchPlan::Group& x, const BatchPlan::Group& y) { return x.log2n < y.log2n; });
+  for (auto& g : plan.groups) {
+    const uint64_t per = chunk_words(1ull << g.log2n, f->k, 1) * 8;
+    g.cap = std::max<uint64_t>(1, std::min<uint64_t>(g.reqs.size(), kChunkBytes / per));
+    plan.ws_words = std::max(plan.ws_words, chunk_words(1ull << g.log2n, f->k, g.cap));
+  }
+  return GFP_OK;
+}
+
+int enqueue_batch(gfp_field* f, const BatchPlan& plan, uint64_t* ws, hipStream_t st) {
+  for (const auto& g : plan.groups) {
+    for (size_t i = 0; i < g.reqs.size(); i += g.cap) {
+      const uint64_t C = std::min<uint64_t>(g.cap, g.reqs.size() - i);
+      int rc = polymul_chunk(f, g.log2n, g.e, g.reqs.data() + i, C, ws, st);
+      if (rc != GFP_OK) return rc;
+    }
+  }
+  return GFP_OK;
+}
+
+uint64_t hash_bytes(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;  // FNV-1a
+  return h;
 }
 
 }  // namespace
@@ -416,6 +571,7 @@ int gfp_field_destroy(gfp_field* f) {
     (void)hipSetDevice(kv.first);
     (void)hipFree(kv.second.one);
   }
+  for (auto& kv : f->graphs) (void)hipGraphExecDestroy(kv.second);
   if (!f->tables.empty() || !f->consts.empty()) (void)hipSetDevice(dev);
   delete f;
   return GFP_OK;
@@ -510,56 +666,99 @@ int gfp_polymul_workspace_size(const gfp_field* f, uint64_t la, uint64_t lb, uin
   uint64_t N;
   int rc = gfp_polymul_size(f, la, lb, &N);
   if (rc != GFP_OK) return rc;
-  *bytes = 4ull * N * f->k * 8;
+  *bytes = chunk_words(N, f->k, 1) * 8;
   return GFP_OK;
 }
 
 int gfp_polymul(const gfp_field* cf, const uint64_t* a, uint64_t la, uint64_t ld_a, const uint64_t* b, uint64_t lb,
                 uint64_t ld_b, uint64_t* c, uint64_t ld_c, void* workspace, uint64_t ws_bytes, void* stream) {
   gfp_field* f = const_cast<gfp_field*>(cf);
-  if (!f || !a || !b || !c || la == 0 || lb == 0) return GFP_EINVAL;
+  if (!f) return GFP_EINVAL;
+  PolyReq q{a, la, ld_a, b, lb, ld_b, c, ld_c};
+  int rc = check_req(f, q);
+  if (rc != GFP_OK) return rc;
   if (!f->gpu_shape) return GFP_EUNSUPPORTED;
-  if (ld_a < la || ld_b < lb || ld_c < la + lb - 1) return GFP_EINVAL;
   uint64_t N;
-  int rc = gfp_polymul_size(f, la, lb, &N);
+  rc = gfp_polymul_size(f, la, lb, &N);
   if (rc != GFP_OK) return rc;
   int log2n, e;
   check_size(f, N, &log2n, &e);
   hipStream_t st = (hipStream_t)stream;
   Scratch s;
   uint64_t* w = nullptr;
-  const uint64_t k = f->k;
-  rc = get_workspace(workspace, ws_bytes, 4ull * N * k * 8, st, s, &w);
+  rc = get_workspace(workspace, ws_bytes, chunk_words(N, f->k, 1) * 8, st, s, &w);
   if (rc != GFP_OK) return rc;
-  uint64_t* A = w;
-  uint64_t* B = w + N * k;
-  uint64_t* W1 = w + 2 * N * k;
-  uint64_t* W2 = w + 3 * N * k;
-  hipError_t he = hipMemsetAsync(A, 0, 2 * N * k * 8, st);
-  if (he == hipSuccess) he = hipMemcpy2DAsync(A, N * 8, a, ld_a * 8, la * 8, k, hipMemcpyDeviceToDevice, st);
-  if (he == hipSuccess) he = hipMemcpy2DAsync(B, N * 8, b, ld_b * 8, lb * 8, k, hipMemcpyDeviceToDevice, st);
-  if (he != hipSuccess) return hip_status(he);
-  rc = run_transform(f, log2n, e, false, A, N, A, N, W1, W2, st);
-  if (rc == GFP_OK) rc = run_transform(f, log2n, e, false, B, N, B, N, W1, W2, st);
+  return polymul_chunk(f, log2n, e, &q, 1, w, st);
+}
+
+int gfp_polymul_batched_workspace_size(const gfp_field* cf, uint32_t n, const gfp_polymul_desc* d, uint64_t* bytes) {
+  if (!bytes) return GFP_EINVAL;
+  BatchPlan plan;
+  int rc = plan_batch(const_cast<gfp_field*>(cf), n, d, plan);
   if (rc != GFP_OK) return rc;
-  gfpk::EwArgs ew;
-  ew.op = GFP_OP_MUL;
-  ew.x = A;
-  ew.ldx = N;
-  ew.y = B;
-  ew.ldy = N;
-  ew.z = A;
-  ew.ldz = N;
-  ew.n = N;
-  ew.s = 0;
-  ew.cst = nullptr;
-  he = gfpk::launch_elementwise((int)k, f->w, f->u, ew, st);
-  if (he != hipSuccess) return hip_status(he);
-  // inverse into B (full length), then the first la + lb - 1 coefficients to c
-  rc = run_transform(f, log2n, e, true, A, N, B, N, W1, W2, st);
+  *bytes = plan.ws_words * 8;
+  return GFP_OK;
+}
+
+int gfp_polymul_batched(const gfp_field* cf, uint32_t n, const gfp_polymul_desc* d, void* workspace, uint64_t ws_bytes,
+                        int flags, void* stream) {
+  gfp_field* f = const_cast<gfp_field*>(cf);
+  if (flags & ~GFP_BATCH_GRAPH) return GFP_EINVAL;
+  BatchPlan plan;
+  int rc = plan_batch(f, n, d, plan);
   if (rc != GFP_OK) return rc;
-  he = hipMemcpy2DAsync(c, ld_c * 8, B, N * 8, (la + lb - 1) * 8, k, hipMemcpyDeviceToDevice, st);
-  return hip_status(he);
+  hipStream_t st = (hipStream_t)stream;
+  const bool graph = (flags & GFP_BATCH_GRAPH) != 0;
+  if (graph && (!st || !workspace)) return GFP_EINVAL;
+  // twiddle tables are uploaded synchronously: do it before any capture
+  for (const auto& g : plan.groups) {
+    const DevTables* t;
+    rc = get_tables(f, 1ull << g.log2n, &t);
+    if (rc != GFP_OK) return rc;
+  }
+  Scratch s;
+  uint64_t* w = nullptr;
+  rc = get_workspace(workspace, ws_bytes, plan.ws_words * 8, st, s, &w);
+  if (rc != GFP_OK) return rc;
+  if (!graph) return enqueue_batch(f, plan, w, st);
+
+  uint64_t key = 1469598103934665603ull;
+  key = hash_bytes(key, &n, sizeof(n));
+  key = hash_bytes(key, d, sizeof(gfp_polymul_desc) * n);
+  key = hash_bytes(key, &w, sizeof(w));
+  key = hash_bytes(key, &ws_bytes, sizeof(ws_bytes));
+  key = hash_bytes(key, &st, sizeof(st));
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  key = hash_bytes(key, &dev, sizeof(dev));
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(f->mu);
+    auto it = f->graphs.find(key);
+    if (it != f->graphs.end()) exec = it->second;
+  }
+  if (!exec) {
+    hipError_t he = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (he != hipSuccess) return hip_status(he);
+    rc = enqueue_batch(f, plan, w, st);
+    hipGraph_t g = nullptr;
+    he = hipStreamEndCapture(st, &g);
+    if (rc != GFP_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (he != hipSuccess) return hip_status(he);
+    he = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (he != hipSuccess) return hip_status(he);
+    std::lock_guard<std::mutex> lk(f->mu);
+    auto ins = f->graphs.emplace(key, exec);
+    if (!ins.second) {  // another thread captured the same list meanwhile
+      (void)hipGraphExecDestroy(exec);
+      exec = ins.first->second;
+    }
+  }
+  return hip_status(hipGraphLaunch(exec, st));
 }
 
 int gfp_elementwise(const gfp_field* cf, int op, const uint64_t* x, uint64_t ld_x, const uint64_t* y, uint64_t ld_y,
@@ -603,11 +802,14 @@ int gfp_elementwise(const gfp_field* cf, int op, const uint64_t* x, uint64_t ld_
   gfpk::EwArgs a;
   a.op = op;
   a.x = x;
-  a.ldx = ld_x;
+  a.xse = 1;
+  a.xsd = ld_x;
   a.y = needs_y ? y : x;
-  a.ldy = needs_y ? ld_y : ld_x;
+  a.yse = 1;
+  a.ysd = needs_y ? ld_y : ld_x;
   a.z = z;
-  a.ldz = ld_z;
+  a.zse = 1;
+  a.zsd = ld_z;
   a.n = n;
   a.s = s;
   a.cst = cst;

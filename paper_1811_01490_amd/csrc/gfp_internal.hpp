@@ -24,20 +24,38 @@ struct PassArgs {
   bool inverse;
   bool scale;  // inverse pass 0: multiply every slot by tw[0] (1/n)
   bool last;   // canonical output
+  uint64_t nvec = 1;  // transforms in this launch (same size)
+  uint64_t vin = 0;   // u64 stride between the input vectors
+  uint64_t vout = 0;  // u64 stride between the output vectors
 };
 
 struct EwArgs {
   int op;
   const uint64_t* x;
-  uint64_t ldx;
+  uint64_t xse, xsd;
   const uint64_t* y;
-  uint64_t ldy;
+  uint64_t yse, ysd;
   uint64_t* z;
-  uint64_t ldz;
+  uint64_t zse, zsd;
   uint64_t n;
   int64_t s;
   const uint32_t* cst;  // one twiddle-layout entry (device)
 };
+
+// Copies between caller vectors (digit-major, ld) and padded element-major
+// work vectors of n elements.  One descriptor per vector.
+struct CopyDesc {
+  const uint64_t* src;  // pad: caller vector; unpad: unused
+  uint64_t* dst;        // unpad: caller vector; pad: unused
+  uint64_t len;         // coefficients to copy (the rest of a padded vector is 0)
+  uint64_t ld;          // caller row stride
+};
+// Descriptors travel as kernel arguments (by value, at most kCopyBatch per
+// launch), so a captured graph holds its own copy of them.
+constexpr uint32_t kCopyBatch = 48;
+hipError_t launch_pad(int k, const CopyDesc* host_d, uint32_t nvec, uint64_t* work, uint64_t n, hipStream_t st);
+hipError_t launch_unpad(int k, const CopyDesc* host_d, uint32_t nvec, const uint64_t* work, uint64_t n,
+                        uint64_t maxlen, hipStream_t st);
 
 bool shape_supported(int k, int w, int u);
 hipError_t launch_pass(int k, int w, int u, const PassArgs& p, hipStream_t st);

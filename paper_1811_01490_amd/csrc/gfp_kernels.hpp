@@ -33,30 +33,44 @@ enum { MODE_PLAIN = 0, MODE_SCALE = 1 };
 template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF>
 __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
                                               uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
-                                              const uint32_t* __restrict__ tw, int log2n, int log2ns, uint64_t ngroups) {
+                                              const uint32_t* __restrict__ tw, int log2n, int log2ns, uint64_t ngroups,
+                                              uint64_t nvec, uint64_t vin, uint64_t vout) {
   typedef Geo<KD> Gm;
   constexpr int KB = Gm::KB;
   constexpr int LOGKB = ilog2(KB);
   const int l = Gm::lane();
   const int m = Gm::digit(l);
+  // A launch covers nvec transforms of the same size: vector v reads
+  // in + v vin and writes out + v vout.
   const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   const uint64_t nk = ngroups;  // N / K
+  const int log2nk = log2n - LOGKB;
   const uint64_t ns = 1ull << log2ns;
-  uint64_t j, a;
+  uint64_t j, a, vec;
   if constexpr (UNIF) {
-    const int log2wpa = log2n - LOGKB - log2ns - ilog2(Gm::G);  // wavefronts per twiddle base
-    a = (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave >> log2wpa));
-    const uint64_t qb = wave & ((1ull << log2wpa) - 1);
+    const int log2wpv = log2nk - ilog2(Gm::G);       // wavefronts per vector
+    const int log2wpa = log2wpv - log2ns;            // wavefronts per twiddle base
+    vec = wave >> log2wpv;
+    const uint64_t w = wave & ((1ull << log2wpv) - 1);
+    a = (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(w >> log2wpa));
+    const uint64_t qb = w & ((1ull << log2wpa) - 1);
     j = a + ((qb * Gm::G + Gm::group(l)) << log2ns);
   } else {
-    j = wave * Gm::G + Gm::group(l);
+    const uint64_t J = wave * Gm::G + Gm::group(l);  // group index over all vectors
+    vec = J >> log2nk;
+    j = J & (nk - 1);
     a = j & (ns - 1);
   }
-  // inactive groups (only in the last block of small transforms) compute on
-  // element 0 and store nothing; with UNIF the grid covers the groups exactly
-  const bool active = UNIF || j < ngroups;
+  // inactive groups (past the last vector) compute on element 0 of vector 0
+  // and store nothing; with UNIF the grid covers the groups exactly
+  const bool active = UNIF || vec < nvec;
   const uint64_t jj = active ? j : 0;
-  if (!active) a = 0;
+  if (!active) {
+    a = 0;
+    vec = 0;
+  }
+  in += vec * vin;
+  out += vec * vout;
 
   uint64_t x[KB];
   static_for<KB>([&](auto T) {
@@ -116,9 +130,10 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
 // elementwise operations (one element per k lanes)
 // ---------------------------------------------------------------------------
 template <int KD, int W, int U, int OP>
-__global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict__ x, uint64_t ldx,
-                                                     const uint64_t* __restrict__ y, uint64_t ldy, uint64_t* __restrict__ z,
-                                                     uint64_t ldz, uint64_t n, int64_t s, const uint32_t* __restrict__ cst) {
+__global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict__ x, uint64_t xse, uint64_t xsd,
+                                                     const uint64_t* __restrict__ y, uint64_t yse, uint64_t ysd,
+                                                     uint64_t* __restrict__ z, uint64_t zse, uint64_t zsd, uint64_t n,
+                                                     int64_t s, const uint32_t* __restrict__ cst) {
   typedef Geo<KD> Gm;
   const int l = Gm::lane();
   const int m = Gm::digit(l);
@@ -127,15 +142,15 @@ __global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict_
   const uint64_t ee = active ? e : 0;
   L96 t;
   if constexpr (OP == GFP_OP_ADD || OP == GFP_OP_SUB) {
-    const uint64_t xm = x[(uint64_t)m * ldx + ee];
-    const uint64_t ym = y[(uint64_t)m * ldy + ee];
+    const uint64_t xm = x[(uint64_t)m * xsd + ee * xse];
+    const uint64_t ym = y[(uint64_t)m * ysd + ee * yse];
     t = (OP == GFP_OP_ADD) ? l96_add(l96(xm), l96(ym)) : l96_sub(l96(xm), l96(ym));
   } else if constexpr (OP == GFP_OP_MUL || OP == GFP_OP_MUL_SCALE) {
-    const uint64_t xm = x[(uint64_t)m * ldx + ee];
+    const uint64_t xm = x[(uint64_t)m * xsd + ee * xse];
     uint64_t yd[KD];
     static_for<KD>([&](auto T) {
       constexpr int tt = decltype(T)::value;
-      yd[tt] = y[(uint64_t)tt * ldy + ee];
+      yd[tt] = y[(uint64_t)tt * ysd + ee * yse];
     });
     t = mul_data<KD, W, U>(xm, yd, m);
     if constexpr (OP == GFP_OP_MUL_SCALE) {
@@ -144,11 +159,11 @@ __global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict_
     }
   } else {  // GFP_OP_MUL_CONST: x * c * r^s; GFP_OP_MUL_POW_R: the same with c = 1
     const RotLane<KD> rl = rot_lane<KD>((int)(((s % (2 * KD)) + 2 * KD) % (2 * KD)), m);
-    const uint64_t xs = x[(uint64_t)rl.src * ldx + ee];
+    const uint64_t xs = x[(uint64_t)rl.src * xsd + ee * xse];
     t = mul_twiddle_pre<KD, W, U>(xs, cst, rl, m);
   }
   const uint64_t d = canonicalize<KD, W, U>(t, l, m);
-  if (active) z[(uint64_t)m * ldz + ee] = d;
+  if (active) z[(uint64_t)m * zsd + ee * zse] = d;
 }
 
 // ---------------------------------------------------------------------------
@@ -161,11 +176,11 @@ inline unsigned blocks_for(uint64_t groups, int G) {
 
 template <int KD, int W, int U>
 hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
-  const unsigned nb = blocks_for(p.ngroups, Geo<KD>::G);
+  const unsigned nb = blocks_for(p.ngroups * p.nvec, Geo<KD>::G);
   if (nb == 0) return hipSuccess;
 #define GFP_LAUNCH(INV, MODE, LAST, UNIF)                                                                           \
   hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST, UNIF>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, \
-                     p.out, p.se_out, p.sd_out, p.tw, p.log2n, p.log2ns, p.ngroups)
+                     p.out, p.se_out, p.sd_out, p.tw, p.log2n, p.log2ns, p.ngroups, p.nvec, p.vin, p.vout)
   // uniform twiddles when every base a has at least one wavefront of groups
   const int lk = ilog2(2 * KD);
   const bool unif = p.log2ns > 0 && (p.log2n - lk - p.log2ns) >= ilog2(Geo<KD>::G);
@@ -189,8 +204,8 @@ hipError_t launch_elementwise_t(const EwArgs& a, hipStream_t st) {
   const unsigned nb = blocks_for(a.n, Geo<KD>::G);
   if (nb == 0) return hipSuccess;
 #define GFP_LAUNCH_EW(OP)                                                                                        \
-  hipLaunchKernelGGL((k_elementwise<KD, W, U, OP>), dim3(nb), dim3(256), 0, st, a.x, a.ldx, a.y, a.ldy, a.z, a.ldz, \
-                     a.n, a.s, a.cst)
+  hipLaunchKernelGGL((k_elementwise<KD, W, U, OP>), dim3(nb), dim3(256), 0, st, a.x, a.xse, a.xsd, a.y, a.yse, a.ysd, \
+                     a.z, a.zse, a.zsd, a.n, a.s, a.cst)
   switch (a.op) {
     case GFP_OP_ADD: GFP_LAUNCH_EW(GFP_OP_ADD); break;
     case GFP_OP_SUB: GFP_LAUNCH_EW(GFP_OP_SUB); break;

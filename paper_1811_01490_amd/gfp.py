@@ -29,6 +29,14 @@ GFP_ECANCELED = 7
 GFP_EPENDING = 8
 
 OP_ADD, OP_SUB, OP_MUL, OP_MUL_POW_R, OP_MUL_CONST, OP_MUL_SCALE = range(6)
+BATCH_GRAPH = 1
+
+
+class PolymulDesc(ctypes.Structure):
+    """gfp_polymul_desc"""
+    _fields_ = [("a", ctypes.c_void_p), ("la", ctypes.c_uint64), ("ld_a", ctypes.c_uint64),
+                ("b", ctypes.c_void_p), ("lb", ctypes.c_uint64), ("ld_b", ctypes.c_uint64),
+                ("c", ctypes.c_void_p), ("ld_c", ctypes.c_uint64)]
 
 _u64 = ctypes.c_uint64
 _u32 = ctypes.c_uint32
@@ -50,6 +58,8 @@ SIGNATURES = {
     "gfp_polymul_size": (_int, [_vp, _u64, _u64, ctypes.POINTER(_u64)]),
     "gfp_polymul_workspace_size": (_int, [_vp, _u64, _u64, ctypes.POINTER(_u64)]),
     "gfp_polymul": (_int, [_vp, _vp, _u64, _u64, _vp, _u64, _u64, _vp, _u64, _vp, _u64, _vp]),
+    "gfp_polymul_batched_workspace_size": (_int, [_vp, _u32, _vp, ctypes.POINTER(_u64)]),
+    "gfp_polymul_batched": (_int, [_vp, _u32, _vp, _vp, _u64, _int, _vp]),
     "gfp_elementwise": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _u64, _i64, _pu64, _vp]),
     "gfp_strerror": (ctypes.c_char_p, [_int]),
 }
@@ -194,6 +204,31 @@ class Field:
             if workspace is not None else (None, 0)
         _check(lib().gfp_polymul(self._h, pa, la, lda, pb, lb, ldb, pc, ldc, wp, wb, _stream(stream)), "gfp_polymul")
         return c
+
+    def batch_descs(self, reqs):
+        """reqs: list of (a, b, c) tensors (shape (k, ld)); lengths = a.shape[1],
+        b.shape[1].  Returns a ctypes array of gfp_polymul_desc (keep it alive
+        with the tensors)."""
+        arr = (PolymulDesc * len(reqs))()
+        for i, (a, b, c) in enumerate(reqs):
+            la, lb = a.shape[1], b.shape[1]
+            pa, lda = _vec(a, self.k, la, "a")
+            pb, ldb = _vec(b, self.k, lb, "b")
+            pc, ldc = _vec(c, self.k, la + lb - 1, "c")
+            arr[i] = PolymulDesc(pa, la, lda, pb, lb, ldb, pc, ldc)
+        return arr
+
+    def polymul_batched_workspace_size(self, descs) -> int:
+        v = _u64()
+        _check(lib().gfp_polymul_batched_workspace_size(self._h, len(descs), descs, ctypes.byref(v)),
+               "gfp_polymul_batched_workspace_size")
+        return v.value
+
+    def polymul_batched(self, descs, workspace=None, graph=False, stream=None):
+        wp, wb = (ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()) \
+            if workspace is not None else (None, 0)
+        _check(lib().gfp_polymul_batched(self._h, len(descs), descs, wp, wb, BATCH_GRAPH if graph else 0,
+                                         _stream(stream)), "gfp_polymul_batched")
 
     def elementwise(self, op, x, y=None, z=None, n=None, s=0, c=None, stream=None):
         n = x.shape[1] if n is None else n

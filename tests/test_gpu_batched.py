@@ -1,0 +1,88 @@
+"""Batched products (gfp_polymul_batched): mixed sizes in one call must give,
+for every request, exactly gfp_polymul's result (and the schoolbook product
+where the oracle is fast); the hipGraph path must give the same on every
+replay, with unrelated eager work and synchronisations between replays."""
+
+import numpy as np
+import pytest
+
+import gfp_inputs as gi
+from oracle import transform as T
+from oracle.field import GFPField, P8, P16
+from tests.helpers import canonical_mask, to_ints
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _batch(params, sizes, seed):
+    from paper_1811_01490_amd import to_device
+
+    k, r = params["k"], params["r"]
+    reqs = []
+    for i, (la, lb) in enumerate(sizes):
+        a = gi.operand(k, r, la, seed, 2 + 2 * i, edge_frac=0.05)
+        b = gi.operand(k, r, lb, seed, 3 + 2 * i, edge_frac=0.05)
+        reqs.append((a, b))
+    dev = [(to_device(a), to_device(b)) for a, b in reqs]
+    return reqs, dev
+
+
+@pytest.mark.parametrize("params", [P8, P16], ids=["k8", "k16"])
+def test_batched_mixed_sizes(torch_mod, params):
+    import torch
+
+    from paper_1811_01490_amd import Field, to_host
+
+    F = GFPField(**params)
+    f = Field(params["k"], params["r"])
+    sizes = [(1, 1), (5, 3), (128, 128), (8, 9), (300, 200), (2048, 2048), (1, 2000), (513, 512), (100, 157),
+             (4000, 96), (64, 64)] + [(7 + i, 11 + 2 * i) for i in range(20)]
+    if params["k"] == 8:
+        sizes.append((30000, 30000))  # transform size 16^4
+    reqs, dev = _batch(params, sizes, gi.BASE_SEED + 300)
+    outs = [torch.full((F.k, a.shape[1] + b.shape[1] - 1), 7, dtype=torch.int64, device="cuda") for a, b in dev]
+    descs = f.batch_descs([(a, b, c) for (a, b), c in zip(dev, outs)])
+    f.polymul_batched(descs)
+    torch.cuda.synchronize()
+    for i, ((a, b), (da, db), c) in enumerate(zip(reqs, dev, outs)):
+        ch = to_host(c)
+        assert canonical_mask(ch, F.r).all(), i
+        single = to_host(f.polymul(da, db))
+        assert np.array_equal(ch, single), i
+        if a.shape[1] * b.shape[1] <= 2048 * 2048:
+            assert to_ints(ch, F.r) == T.polymul(to_ints(a, F.r), to_ints(b, F.r), F.p), i
+
+
+def test_batched_graph_replays(torch_mod):
+    import torch
+
+    from paper_1811_01490_amd import Field, to_device, to_host
+
+    F = GFPField(**P8)
+    f = Field(P8["k"], P8["r"])
+    sizes = [(100, 60), (2000, 2000), (20, 1), (600, 700), (3, 3), (1000, 30)]
+    reqs, dev = _batch(P8, sizes, gi.BASE_SEED + 301)
+    outs = [torch.zeros((F.k, a.shape[1] + b.shape[1] - 1), dtype=torch.int64, device="cuda") for a, b in dev]
+    descs = f.batch_descs([(a, b, c) for (a, b), c in zip(dev, outs)])
+    ws = torch.empty(f.polymul_batched_workspace_size(descs) // 8 + 1, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.Stream()
+    want = [T.polymul(to_ints(a, F.r), to_ints(b, F.r), F.p) for a, b in reqs]
+    with torch.cuda.stream(stream):
+        for rep in range(4):
+            for c in outs:
+                c.zero_()
+            f.polymul_batched(descs, workspace=ws, graph=True, stream=stream)
+            # unrelated eager work between replays
+            junk = to_device(gi.uniform_digits(F.k, F.r, 4096, 5, rep))
+            f.fft_forward(junk, stream=stream)
+            stream.synchronize()
+            for i, c in enumerate(outs):
+                assert to_ints(to_host(c), F.r) == want[i], (rep, i)
