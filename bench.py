@@ -109,6 +109,70 @@ def cpu_baseline(sample_log2: int):
     }
 
 
+def batched_leg(torch, f, dev, reps: int):
+    """Config 3: 256 products over the k = 8 prime, transform sizes N_i drawn
+    uniformly from {16^2, 16^3, 16^4, 16^5} (log-uniform in N), la = lb = N_i / 2,
+    uniform coefficients.  Times 256 separate gfp_polymul calls against one
+    gfp_polymul_batched call replayed from its hipGraph, on one stream, and
+    checks that both give the same 256 products."""
+    import numpy as np
+
+    import gfp_inputs as gi
+    from paper_1811_01490_amd import to_device
+
+    seed = gi.BASE_SEED + 3
+    g = gi.rng(seed, 1000)
+    sizes = [16 ** int(e) for e in g.integers(2, 6, size=256)]
+    reqs = []
+    for i, n in enumerate(sizes):
+        a = to_device(gi.uniform_digits(K_DIG, R, n // 2, seed, 2 + 2 * i), dev)
+        b = to_device(gi.uniform_digits(K_DIG, R, n // 2, seed, 3 + 2 * i), dev)
+        reqs.append((a, b))
+    c_plain = [torch.empty((K_DIG, a.shape[1] + b.shape[1] - 1), dtype=torch.int64, device=dev) for a, b in reqs]
+    c_batch = [torch.empty_like(c) for c in c_plain]
+    ws1 = torch.empty(f.polymul_workspace_size(2 ** 19, 2 ** 19) // 8, dtype=torch.int64, device=dev)
+    descs = f.batch_descs([(a, b, c) for (a, b), c in zip(reqs, c_batch)])
+    wsb = torch.empty(f.polymul_batched_workspace_size(descs) // 8 + 1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.Stream(device=dev)  # graph capture needs a non-null stream
+
+    def plain():
+        for (a, b), c in zip(reqs, c_plain):
+            f.polymul(a, b, c=c, workspace=ws1, stream=stream)
+
+    def batched():
+        f.polymul_batched(descs, workspace=wsb, graph=True, stream=stream)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_plain = timed(plain)
+    t_batch = timed(batched)
+    same = all(torch.equal(x, y) for x, y in zip(c_plain, c_batch))
+    coefs = sum(a.shape[1] + b.shape[1] - 1 for a, b in reqs)
+    hist = {str(n): sizes.count(n) for n in sorted(set(sizes))}
+    return {
+        "workload": "256 products, p = (2^63+2^34)^8+1, transform sizes log-uniform on {16^2..16^5}, la = lb = N/2, "
+                    "seed 1811014903",
+        "size_histogram": hist,
+        "output_coeffs": coefs,
+        "plain_ms": round(t_plain, 3),
+        "batched_graph_ms": round(t_batch, 3),
+        "speedup": round(t_plain / t_batch, 3),
+        "batched_coeffs_per_s": round(coefs / (t_batch * 1e-3), 1),
+        "plain_coeffs_per_s": round(coefs / (t_plain * 1e-3), 1),
+        "identical_outputs": bool(same),
+    }
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -127,6 +191,8 @@ def main():
     ap.add_argument("--pass-reps", type=int, default=50)
     ap.add_argument("--cpu-sample-log2", type=int, default=19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one transform does not span GPUs). "
@@ -238,6 +304,8 @@ def main():
         },
         "timed_wall_s": round(t_wall, 4),
     }
+    if not args.no_batched:
+        out["batched"] = batched_leg(torch, f, dev, args.batched_reps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
     print(json.dumps(out), flush=True)
