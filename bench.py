@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 
 METRIC = "Z/pZ FFT coeffs/s (k=8,N=16^5); batched-vs-plain polymul speedup; p99 latency"
 K_DIG, R = 8, 2 ** 63 + 2 ** 34
+R16 = 2 ** 62 + 2 ** 36  # the k = 16 prime of the served workload
 LOG2N = 20
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit integer lane-ops per second (Tops/s)
 HBM_PEAK_GBS = 8000.0
@@ -173,6 +174,138 @@ def batched_leg(torch, f, dev, reps: int):
     }
 
 
+def served_leg(torch, dev, n_req: int, loads, workspace_gib: int, slots: int):
+    """Config 4: a stream of n_req product requests, each over the k = 8 or the
+    k = 16 prime (fair coin), la = lb = floor(2^U), U uniform on [8, 19],
+    Poisson arrivals.  The arrival rate is `load` times the saturated request
+    rate of the plain path (all requests back to back, one gfp_polymul each,
+    one stream).  Each stream is served twice: by the request loop (continuous
+    batching over `slots` streams) and by a one-request-per-launch FIFO loop
+    (one slot, batches of one), reporting p50/p99 latency (done - scheduled
+    arrival) and throughput.  Every served result is compared with the plain
+    run's result of the same request through a 64-bit digest."""
+    import numpy as np
+
+    import gfp_inputs as gi
+    from paper_1811_01490_amd import Field, Server, to_device
+
+    seed = gi.BASE_SEED + 4
+    pool_n = 1 << 21
+    fields = {8: Field(K_DIG, R), 16: Field(16, R16)}
+    pools = {k: to_device(gi.uniform_digits(k, fields[k].r, pool_n, seed, i), dev) for i, k in enumerate((8, 16))}
+    g = gi.rng(seed, 1000)
+    ks = np.where(g.integers(0, 2, size=n_req) == 0, 8, 16)
+    ls = np.floor(2.0 ** g.uniform(8, 19, size=n_req)).astype(np.int64)
+    offs = g.integers(0, pool_n - ls[:, None] + 1, size=(n_req, 2))
+    # outputs: one arena per field, request i owns columns [start, start + 2L - 1)
+    starts, tot = np.zeros(n_req, dtype=np.int64), {8: 0, 16: 0}
+    for i in range(n_req):
+        starts[i] = tot[int(ks[i])]
+        tot[int(ks[i])] += 2 * int(ls[i]) - 1
+    arena = {k: torch.empty((k, max(tot[k], 1)), dtype=torch.int64, device=dev) for k in (8, 16)}
+    weights = torch.randint(-2 ** 62, 2 ** 62, (16, 2 ** 20), generator=torch.Generator().manual_seed(seed),
+                            dtype=torch.int64).to(dev)
+
+    def views(i):
+        k, L = int(ks[i]), int(ls[i])
+        a = pools[k][:, int(offs[i, 0]):int(offs[i, 0]) + L]
+        b = pools[k][:, int(offs[i, 1]):int(offs[i, 1]) + L]
+        c = arena[k][:, int(starts[i]):int(starts[i]) + 2 * L - 1]
+        return fields[k], a, b, c
+
+    reqs = [Server.request(*views(i)) for i in range(n_req)]
+
+    def digests():
+        out = []
+        for i in range(n_req):
+            c = views(i)[3]
+            out.append((c * weights[:c.shape[0], :c.shape[1]]).sum())
+        return torch.stack(out).cpu().numpy()
+
+    # plain path, saturated: every request alone, back to back on one stream
+    stream = torch.cuda.Stream(device=dev)
+    ws = torch.empty(fields[16].polymul_workspace_size(2 ** 19, 2 ** 19) // 8, dtype=torch.int64, device=dev)
+    for i in range(min(n_req, 64)):  # warm-up: twiddle tables of every size, code paths
+        f, a, b, c = views(i)
+        f.polymul(a, b, c=c, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(n_req):
+        f, a, b, c = views(i)
+        f.polymul(a, b, c=c, workspace=ws, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_plain = e0.elapsed_time(e1) * 1e-3
+    ref = digests()
+    del ws
+    print("served: plain saturated run %.3f s" % t_plain, file=sys.stderr, flush=True)
+    coefs = int((2 * ls - 1).sum())
+    mu = n_req / t_plain
+
+    def serve(srv, lam, stream_id):
+        gaps = gi.rng(seed, 1001 + stream_id).exponential(1.0 / lam, size=n_req)
+        arrive = np.cumsum(gaps) - gaps[0]
+        for k in arena:
+            arena[k].fill_(-1)
+        torch.cuda.synchronize()
+        tickets = [0] * n_req
+        t0 = time.monotonic_ns() + 2_000_000
+        sched = (t0 + arrive * 1e9).astype(np.int64)
+        for i in range(n_req):
+            while time.monotonic_ns() < sched[i]:
+                pass
+            tickets[i] = srv.submit_request(reqs[i])
+        srv.drain()
+        res = [srv.poll(t) for t in tickets]
+        st = srv.stats()
+        done = np.array([r["t_done_ns"] for r in res], dtype=np.int64)
+        sub = np.array([r["t_submit_ns"] for r in res], dtype=np.int64)
+        lat = (done - sched) * 1e-6
+        lag = (sub - sched) * 1e-6
+        ok = all(r["status"] == 0 for r in res)
+        same = bool(ok and np.array_equal(digests(), ref))
+        span = (done.max() - sched[0]) * 1e-9
+        return {
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3),
+            "max_submit_lag_ms": round(float(lag.max()), 3),
+            "makespan_s": round(float(span), 3),
+            "coeffs_per_s": round(coefs / span, 1),
+            "requests_per_s": round(n_req / span, 1),
+            "batches": st["batches"],
+            "max_batch_size": st["max_batch_size"],
+            "overlapped_batches": st["overlapped_batches"],
+            "identical_to_alone": same,
+        }
+
+    runs = {}
+    for j, load in enumerate(loads):
+        lam = load * mu
+        with Server(workspace_bytes=workspace_gib << 30, slots=slots, max_batch=256, max_pending=n_req) as srv:
+            cb = serve(srv, lam, j)
+        print("served: load %.2f continuous batching p99 %.3f ms" % (load, cb["p99_ms"]), file=sys.stderr, flush=True)
+        with Server(workspace_bytes=2 << 30, slots=1, max_batch=1, max_pending=n_req) as srv:
+            fifo = serve(srv, lam, j)
+        print("served: load %.2f plain FIFO p99 %.3f ms" % (load, fifo["p99_ms"]), file=sys.stderr, flush=True)
+        runs[str(load)] = {"arrival_rate_per_s": round(lam, 1), "continuous_batching": cb,
+                           "plain_fifo": fifo, "p99_speedup": round(fifo["p99_ms"] / cb["p99_ms"], 3)}
+    for f in fields.values():
+        f.close()
+    return {
+        "workload": "%d product requests, p = (2^63+2^34)^8+1 or (2^62+2^36)^16+1 by a fair coin, la = lb = "
+                    "floor(2^U), U uniform on [8, 19], Poisson arrivals, seed 1811014904" % n_req,
+        "output_coeffs": coefs,
+        "plain_saturated_s": round(t_plain, 3),
+        "plain_saturated_requests_per_s": round(mu, 1),
+        "plain_saturated_coeffs_per_s": round(coefs / t_plain, 1),
+        "slots": slots,
+        "workspace_gib": workspace_gib,
+        "loads": runs,
+    }
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -193,6 +326,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=10000)
+    ap.add_argument("--served-loads", default="0.7", help="comma-separated fractions of the plain saturated rate")
+    ap.add_argument("--served-workspace-gib", type=int, default=16)
+    ap.add_argument("--served-slots", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one transform does not span GPUs). "
@@ -306,6 +444,9 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_leg(torch, f, dev, args.batched_reps)
+    if not args.no_served:
+        out["served"] = served_leg(torch, dev, args.served_requests, [float(x) for x in args.served_loads.split(",")],
+                                   args.served_workspace_gib, args.served_slots)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
     print(json.dumps(out), flush=True)

@@ -184,6 +184,99 @@ int gfp_polymul_batched(const gfp_field* f, uint32_t n, const gfp_polymul_desc* 
 int gfp_elementwise(const gfp_field* f, int op, const uint64_t* x, uint64_t ld_x, const uint64_t* y, uint64_t ld_y,
                     uint64_t* z, uint64_t ld_z, uint64_t n, int64_t s, const uint64_t* c_host, void* stream);
 
+/* ---- Request loop (serving) ------------------------------------------------
+ *
+ * A server takes polynomial-product requests (section 3.3, Alg. Fast
+ * Convolution, exactly as gfp_polymul) of any size and any of the compiled
+ * fields as they arrive, and runs them in batches on the GPU with continuous
+ * batching: it owns `slots` HIP streams, each with its own share of the
+ * workspace budget; a slot that is free takes the requests waiting at that
+ * moment (first come, first served, up to max_batch, as long as their
+ * transform workspace fits the slot's share) and runs them as one
+ * gfp_polymul_batched call per field.  Requests that arrive while slots are
+ * busy wait until a slot frees, and batches of different slots run
+ * concurrently on the device.  Each result is bit-identical to gfp_polymul of
+ * the same request alone: the arithmetic is exact and does not depend on the
+ * batch.  All calls are thread-safe, except that gfp_server_destroy must not
+ * overlap any other call on the same server.  Timestamps are CLOCK_MONOTONIC
+ * nanoseconds (comparable with the host clock of the caller). */
+typedef struct gfp_server gfp_server;
+
+typedef struct gfp_server_config {
+  uint64_t workspace_bytes; /* device memory budget for transform workspace, split evenly over the slots */
+  uint32_t slots;           /* batches in flight at once (0 = 2) */
+  uint32_t max_batch;       /* requests per batch (0 = 256) */
+  uint32_t max_pending;     /* submitted, not yet admitted requests before submit returns GFP_EAGAIN (0 = 65536) */
+  uint32_t max_wait_us;     /* a free slot waits up to this long for more requests before launching (0 = launch at once) */
+  int32_t device;           /* HIP device ordinal, -1 = the current device */
+  uint32_t reserved;        /* must be 0 */
+} gfp_server_config;
+
+typedef struct gfp_request {
+  const gfp_field* field; /* must outlive the request */
+  const uint64_t* a;      /* device, la coefficients, row stride ld_a */
+  uint64_t la, ld_a;
+  const uint64_t* b;
+  uint64_t lb, ld_b;
+  uint64_t* c;            /* device, la + lb - 1 coefficients, row stride ld_c; written when the request is done */
+  uint64_t ld_c;
+  void* ready_event;      /* hipEvent_t the batch waits for before reading a and b (recorded by the caller after
+                             writing them), or NULL: the operands are ready when submit is called */
+} gfp_request;
+
+typedef struct gfp_result {
+  int32_t status;       /* GFP_OK, or the error of this request (GFP_EDEVICE, GFP_ECANCELED, ...) */
+  uint32_t batch_size;  /* requests in the batch that carried it */
+  uint64_t batch_id;    /* 1, 2, ... in launch order */
+  uint64_t t_submit_ns; /* submit returned the ticket */
+  uint64_t t_admit_ns;  /* taken into a batch */
+  uint64_t t_launch_ns; /* its batch started enqueueing */
+  uint64_t t_done_ns;   /* its batch finished on the device */
+} gfp_result;
+
+typedef struct gfp_server_stats {
+  uint64_t submitted, completed, rejected; /* rejected: submit calls that returned GFP_EAGAIN */
+  uint64_t batches;
+  uint64_t max_batch_size;
+  uint64_t max_batch_workspace;            /* largest workspace a batch needed, bytes */
+  uint64_t overlapped_batches;             /* batches launched while another slot's batch was in flight */
+  uint64_t slot_bytes;                     /* workspace per slot */
+} gfp_server_stats;
+
+/* Start a server on cfg->device: allocates the workspace (cfg->workspace_bytes)
+ * and creates the slot streams and threads.  Errors: GFP_EINVAL (NULL
+ * argument, reserved != 0, workspace_bytes / slots of 0), GFP_ENOMEM,
+ * GFP_EDEVICE. */
+int gfp_server_create(const gfp_server_config* cfg, gfp_server** out);
+
+/* Queue one request; returns at once with a ticket (1, 2, ...).  The request
+ * is copied; the buffers it names stay the caller's and must not be touched
+ * until the ticket is done.  Errors: GFP_EINVAL (bad pointers or lengths),
+ * GFP_EUNSUPPORTED (field or size), GFP_ENOMEM (its workspace exceeds one
+ * slot's share, so it could never run), GFP_EAGAIN (max_pending requests are
+ * waiting; try again later), GFP_ECANCELED (the server is shutting down). */
+int gfp_server_submit(gfp_server* s, const gfp_request* req, uint64_t* ticket);
+
+/* If the request is done, write its result, forget the ticket and return
+ * GFP_OK (the output is then complete and visible to every stream); else
+ * GFP_EPENDING.  GFP_EINVAL for an unknown ticket. */
+int gfp_server_poll(gfp_server* s, uint64_t ticket, gfp_result* out);
+
+/* As gfp_server_poll, but blocks until the request is done or timeout_us
+ * microseconds passed (timeout_us < 0: no limit); GFP_EPENDING on time-out. */
+int gfp_server_wait(gfp_server* s, uint64_t ticket, int64_t timeout_us, gfp_result* out);
+
+/* Block until every submitted request is done (results stay available). */
+int gfp_server_drain(gfp_server* s);
+
+/* Counters since create. */
+int gfp_server_get_stats(gfp_server* s, gfp_server_stats* out);
+
+/* Stop the server: requests not yet admitted are cancelled (GFP_ECANCELED),
+ * admitted ones run to completion; then the threads, streams and workspace
+ * are released and every ticket becomes invalid.  NULL is accepted. */
+int gfp_server_destroy(gfp_server* s);
+
 /* Static description of an error code. */
 const char* gfp_strerror(int code);
 

@@ -439,9 +439,8 @@ int check_req(const gfp_field* f, const PolyReq& q) {
 }
 
 // Batched products: requests grouped by transform size; each group in
-// chunks of at most `cap` requests whose workspace fits kChunkBytes (or the
-// whole group when smaller).
-const uint64_t kChunkBytes = 4ull << 30;
+// chunks of at most `cap` requests whose workspace fits gfpk::kChunkBytes
+// (or the whole group when smaller).
 
 struct BatchPlan {
   struct Group {
@@ -478,7 +477,7 @@ int plan_batch(gfp_field* f, uint32_t n, const gfp_polymul_desc* d, BatchPlan& p
             [](const BatchPlan::Group& x, const BatchPlan::Group& y) { return x.log2n < y.log2n; });
   for (auto& g : plan.groups) {
     const uint64_t per = chunk_words(1ull << g.log2n, f->k, 1) * 8;
-    g.cap = std::max<uint64_t>(1, std::min<uint64_t>(g.reqs.size(), kChunkBytes / per));
+    g.cap = std::min<uint64_t>(g.reqs.size(), gfpk::chunk_cap(per));
     plan.ws_words = std::max(plan.ws_words, chunk_words(1ull << g.log2n, f->k, g.cap));
   }
   return GFP_OK;

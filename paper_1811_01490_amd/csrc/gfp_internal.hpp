@@ -61,6 +61,15 @@ bool shape_supported(int k, int w, int u);
 hipError_t launch_pass(int k, int w, int u, const PassArgs& p, hipStream_t st);
 hipError_t launch_elementwise(int k, int w, int u, const EwArgs& a, hipStream_t st);
 
+// Batched products run each transform size in chunks of requests whose
+// workspace fits kChunkBytes (at least one request per chunk); the request
+// loop sizes its batches with the same rule.
+constexpr uint64_t kChunkBytes = 4ull << 30;
+inline uint64_t chunk_cap(uint64_t per_request_bytes) {
+  const uint64_t c = kChunkBytes / per_request_bytes;
+  return c ? c : 1;
+}
+
 // words per twiddle-table entry (see TwLayout in gfp_device.hpp)
 inline int tw_words(int k) { return (6 * k + 6) & ~3; }
 

@@ -1,0 +1,358 @@
+// Request loop of libgfpfft: continuous batching of polynomial products
+// (section 3.3, Alg. Fast Convolution) over a fixed workspace budget.
+//
+// Structure: one queue of submitted requests (FIFO) and `slots` worker
+// threads.  Each worker owns a HIP stream, an event and an equal share of the
+// workspace.  A free worker takes the requests waiting at the head of the
+// queue while their combined workspace fits its share (the same chunk rule as
+// gfp_polymul_batched), enqueues one gfp_polymul_batched call per field on its
+// stream, waits for its event and marks the requests done.  Workers run
+// independently, so a batch that arrives while another is on the device is
+// launched at once on another stream and the two overlap.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <time.h>
+
+#include <algorithm>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/gfp.h"
+#include "gfp_internal.hpp"
+
+namespace {
+
+uint64_t now_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
+struct Request {
+  gfp_request q;
+  uint64_t n = 0;    // transform size
+  uint64_t per = 0;  // workspace bytes of this request alone
+  uint64_t cap = 1;  // requests of its size per workspace chunk
+  bool done = false;
+  gfp_result res{};
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  uint64_t* ws = nullptr;
+  std::thread thread;
+};
+
+}  // namespace
+
+struct gfp_server {
+  gfp_server_config cfg{};
+  uint64_t slot_bytes = 0;
+  void* ws_base = nullptr;
+  std::vector<Slot> slots;
+
+  std::mutex mu;
+  std::condition_variable cv_work;  // queue or stop changed
+  std::condition_variable cv_done;  // a request finished
+  std::deque<uint64_t> queue;       // tickets not yet admitted, arrival order
+  std::unordered_map<uint64_t, Request> reqs;
+  uint64_t next_ticket = 1;
+  uint64_t next_batch = 1;
+  uint64_t unfinished = 0;  // submitted and not done
+  uint32_t in_flight = 0;   // batches on the device
+  bool stopping = false;
+  gfp_server_stats st{};
+};
+
+namespace {
+
+// Workspace a batch needs: per (field, size) class, min(count, cap) requests'
+// worth (its chunks run one after another), and the classes run one after
+// another too, so the maximum over classes.
+struct Need {
+  std::map<std::pair<const gfp_field*, uint64_t>, uint64_t> count;
+  uint64_t bytes = 0;
+  uint64_t with(const Request& r) const {
+    auto it = count.find({r.q.field, r.n});
+    const uint64_t c = (it == count.end() ? 0 : it->second) + 1;
+    return std::max(bytes, std::min(c, r.cap) * r.per);
+  }
+  void add(const Request& r) {
+    bytes = with(r);
+    ++count[{r.q.field, r.n}];
+  }
+};
+
+void finish(gfp_server* s, const std::vector<uint64_t>& tickets, int status, uint64_t t_done) {
+  for (uint64_t t : tickets) {
+    Request& r = s->reqs[t];
+    r.res.status = status;
+    r.res.t_done_ns = t_done;
+    r.done = true;
+  }
+  s->unfinished -= tickets.size();
+  s->st.completed += tickets.size();
+}
+
+// Enqueue the batch on the slot's stream and wait for it.  Runs without the
+// lock; `batch` is a private copy of the requests.
+int run_batch(Slot& sl, uint64_t ws_bytes, const std::vector<gfp_request>& batch) {
+  for (const auto& q : batch) {
+    if (q.ready_event) {
+      hipError_t he = hipStreamWaitEvent(sl.stream, (hipEvent_t)q.ready_event, 0);
+      if (he != hipSuccess) return GFP_EDEVICE;
+    }
+  }
+  // one batched call per field, fields in order of first appearance
+  std::vector<const gfp_field*> fields;
+  for (const auto& q : batch)
+    if (std::find(fields.begin(), fields.end(), q.field) == fields.end()) fields.push_back(q.field);
+  int rc = GFP_OK;
+  for (const gfp_field* f : fields) {
+    std::vector<gfp_polymul_desc> d;
+    for (const auto& q : batch)
+      if (q.field == f) d.push_back(gfp_polymul_desc{q.a, q.la, q.ld_a, q.b, q.lb, q.ld_b, q.c, q.ld_c});
+    rc = gfp_polymul_batched(f, (uint32_t)d.size(), d.data(), sl.ws, ws_bytes, 0, sl.stream);
+    if (rc != GFP_OK) break;
+  }
+  // the event is recorded even after an error so the stream drains before the
+  // requests are released to the caller
+  hipError_t he = hipEventRecord(sl.done, sl.stream);
+  if (he == hipSuccess) he = hipEventSynchronize(sl.done);
+  if (rc == GFP_OK && he != hipSuccess) rc = GFP_EDEVICE;
+  return rc;
+}
+
+void worker(gfp_server* s, size_t idx) {
+  Slot& sl = s->slots[idx];
+  (void)hipSetDevice(s->cfg.device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
+    if (s->queue.empty()) {
+      if (s->stopping) return;
+      continue;
+    }
+    if (s->cfg.max_wait_us && !s->stopping && s->queue.size() < s->cfg.max_batch) {
+      // wait for more requests, up to max_wait_us after the oldest one arrived
+      const uint64_t deadline = s->reqs[s->queue.front()].res.t_submit_ns + 1000ull * s->cfg.max_wait_us;
+      while (!s->stopping && !s->queue.empty() && s->queue.size() < s->cfg.max_batch) {
+        const uint64_t t = now_ns();
+        if (t >= deadline) break;
+        s->cv_work.wait_for(lk, std::chrono::nanoseconds(deadline - t));
+      }
+      if (s->queue.empty()) continue;  // another slot took them
+    }
+    // admission: head of the queue, in order, while the workspace fits
+    Need need;
+    std::vector<uint64_t> tickets;
+    std::vector<gfp_request> batch;
+    const uint64_t t_admit = now_ns();
+    while (!s->queue.empty() && tickets.size() < s->cfg.max_batch) {
+      Request& r = s->reqs[s->queue.front()];
+      if (need.with(r) > s->slot_bytes) break;
+      need.add(r);
+      r.res.t_admit_ns = t_admit;
+      tickets.push_back(s->queue.front());
+      batch.push_back(r.q);
+      s->queue.pop_front();
+    }
+    const uint64_t bid = s->next_batch++;
+    if (s->in_flight > 0) ++s->st.overlapped_batches;
+    ++s->in_flight;
+    ++s->st.batches;
+    s->st.max_batch_size = std::max<uint64_t>(s->st.max_batch_size, tickets.size());
+    s->st.max_batch_workspace = std::max(s->st.max_batch_workspace, need.bytes);
+    const uint64_t t_launch = now_ns();
+    for (uint64_t t : tickets) {
+      Request& r = s->reqs[t];
+      r.res.batch_id = bid;
+      r.res.batch_size = (uint32_t)tickets.size();
+      r.res.t_launch_ns = t_launch;
+    }
+    if (!s->queue.empty()) s->cv_work.notify_one();  // let another free slot take the rest
+    lk.unlock();
+
+    const int rc = run_batch(sl, s->slot_bytes, batch);
+    const uint64_t t_done = now_ns();
+
+    lk.lock();
+    --s->in_flight;
+    finish(s, tickets, rc, t_done);
+    s->cv_done.notify_all();
+  }
+}
+
+bool valid_request(const gfp_request* q) {
+  if (!q || !q->field || !q->a || !q->b || !q->c || q->la == 0 || q->lb == 0) return false;
+  if (q->ld_a < q->la || q->ld_b < q->lb || q->ld_c < q->la + q->lb - 1) return false;
+  return true;
+}
+
+void release(gfp_server* s) {
+  for (auto& sl : s->slots) {
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  if (s->ws_base) (void)hipFree(s->ws_base);
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gfp_server_create(const gfp_server_config* cfg, gfp_server** out) {
+  if (!out) return GFP_EINVAL;
+  *out = nullptr;
+  if (!cfg || cfg->reserved != 0) return GFP_EINVAL;
+  gfp_server_config c = *cfg;
+  if (c.slots == 0) c.slots = 2;
+  if (c.max_batch == 0) c.max_batch = 256;
+  if (c.max_pending == 0) c.max_pending = 65536;
+  if (c.slots > 64) return GFP_EINVAL;
+  // slot shares are multiples of 256 bytes
+  const uint64_t slot_bytes = (c.workspace_bytes / c.slots) & ~255ull;
+  if (slot_bytes == 0) return GFP_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return GFP_EDEVICE;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return GFP_EDEVICE;
+  if (c.device < 0) c.device = prev;
+  if (c.device >= ndev) return GFP_EINVAL;
+
+  gfp_server* s = new (std::nothrow) gfp_server();
+  if (!s) return GFP_ENOMEM;
+  s->cfg = c;
+  s->slot_bytes = slot_bytes;
+  s->st.slot_bytes = slot_bytes;
+  int rc = GFP_OK;
+  if (hipSetDevice(c.device) != hipSuccess) rc = GFP_EDEVICE;
+  if (rc == GFP_OK && hipMalloc(&s->ws_base, slot_bytes * c.slots) != hipSuccess) {
+    s->ws_base = nullptr;
+    rc = GFP_ENOMEM;
+  }
+  s->slots.resize(c.slots);
+  for (uint32_t i = 0; rc == GFP_OK && i < c.slots; ++i) {
+    Slot& sl = s->slots[i];
+    sl.ws = (uint64_t*)((char*)s->ws_base + i * slot_bytes);
+    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
+      sl.stream = nullptr;
+      rc = GFP_EDEVICE;
+    } else if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+      sl.done = nullptr;
+      rc = GFP_EDEVICE;
+    }
+  }
+  (void)hipSetDevice(prev);
+  if (rc != GFP_OK) {
+    release(s);
+    return rc;
+  }
+  for (uint32_t i = 0; i < c.slots; ++i) s->slots[i].thread = std::thread(worker, s, (size_t)i);
+  *out = s;
+  return GFP_OK;
+}
+
+int gfp_server_submit(gfp_server* s, const gfp_request* req, uint64_t* ticket) {
+  if (!s || !ticket || !valid_request(req)) return GFP_EINVAL;
+  Request r;
+  r.q = *req;
+  int rc = gfp_polymul_size(req->field, req->la, req->lb, &r.n);
+  if (rc == GFP_OK) rc = gfp_polymul_workspace_size(req->field, req->la, req->lb, &r.per);
+  if (rc != GFP_OK) return rc;
+  r.cap = gfpk::chunk_cap(r.per);
+  if (r.per > s->slot_bytes) return GFP_ENOMEM;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stopping) return GFP_ECANCELED;
+  if (s->queue.size() >= s->cfg.max_pending) {
+    ++s->st.rejected;
+    return GFP_EAGAIN;
+  }
+  const uint64_t t = s->next_ticket++;
+  r.res.t_submit_ns = now_ns();
+  s->reqs.emplace(t, r);
+  s->queue.push_back(t);
+  ++s->unfinished;
+  ++s->st.submitted;
+  *ticket = t;
+  s->cv_work.notify_one();
+  return GFP_OK;
+}
+
+int gfp_server_poll(gfp_server* s, uint64_t ticket, gfp_result* out) {
+  if (!s || !out) return GFP_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return GFP_EINVAL;
+  if (!it->second.done) return GFP_EPENDING;
+  *out = it->second.res;
+  s->reqs.erase(it);
+  return GFP_OK;
+}
+
+int gfp_server_wait(gfp_server* s, uint64_t ticket, int64_t timeout_us, gfp_result* out) {
+  if (!s || !out) return GFP_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->reqs.find(ticket) == s->reqs.end()) return GFP_EINVAL;
+  // look the ticket up again after every wake-up: another thread may have
+  // polled it meanwhile
+  auto ready = [&] {
+    auto it = s->reqs.find(ticket);
+    return it == s->reqs.end() || it->second.done;
+  };
+  if (timeout_us < 0) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+    return GFP_EPENDING;
+  }
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return GFP_EINVAL;
+  *out = it->second.res;
+  s->reqs.erase(it);
+  return GFP_OK;
+}
+
+int gfp_server_drain(gfp_server* s) {
+  if (!s) return GFP_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->unfinished == 0; });
+  return GFP_OK;
+}
+
+int gfp_server_get_stats(gfp_server* s, gfp_server_stats* out) {
+  if (!s || !out) return GFP_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->st;
+  return GFP_OK;
+}
+
+int gfp_server_destroy(gfp_server* s) {
+  if (!s) return GFP_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+    std::vector<uint64_t> cancelled(s->queue.begin(), s->queue.end());
+    s->queue.clear();
+    finish(s, cancelled, GFP_ECANCELED, now_ns());
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+  }
+  for (auto& sl : s->slots)
+    if (sl.thread.joinable()) sl.thread.join();
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(s->cfg.device);
+  release(s);
+  (void)hipSetDevice(prev);
+  return GFP_OK;
+}
+
+}  // extern "C"

@@ -38,6 +38,41 @@ class PolymulDesc(ctypes.Structure):
                 ("b", ctypes.c_void_p), ("lb", ctypes.c_uint64), ("ld_b", ctypes.c_uint64),
                 ("c", ctypes.c_void_p), ("ld_c", ctypes.c_uint64)]
 
+class ServerConfig(ctypes.Structure):
+    """gfp_server_config"""
+    _fields_ = [("workspace_bytes", ctypes.c_uint64), ("slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("max_pending", ctypes.c_uint32), ("max_wait_us", ctypes.c_uint32), ("device", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Request(ctypes.Structure):
+    """gfp_request"""
+    _fields_ = [("field", ctypes.c_void_p), ("a", ctypes.c_void_p), ("la", ctypes.c_uint64), ("ld_a", ctypes.c_uint64),
+                ("b", ctypes.c_void_p), ("lb", ctypes.c_uint64), ("ld_b", ctypes.c_uint64),
+                ("c", ctypes.c_void_p), ("ld_c", ctypes.c_uint64), ("ready_event", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    """gfp_result"""
+    _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_uint32), ("batch_id", ctypes.c_uint64),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64), ("t_launch_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    """gfp_server_stats"""
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("max_batch_size", ctypes.c_uint64),
+                ("max_batch_workspace", ctypes.c_uint64), ("overlapped_batches", ctypes.c_uint64),
+                ("slot_bytes", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _u64 = ctypes.c_uint64
 _u32 = ctypes.c_uint32
 _i64 = ctypes.c_int64
@@ -61,6 +96,13 @@ SIGNATURES = {
     "gfp_polymul_batched_workspace_size": (_int, [_vp, _u32, _vp, ctypes.POINTER(_u64)]),
     "gfp_polymul_batched": (_int, [_vp, _u32, _vp, _vp, _u64, _int, _vp]),
     "gfp_elementwise": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _u64, _i64, _pu64, _vp]),
+    "gfp_server_create": (_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]),
+    "gfp_server_submit": (_int, [_vp, ctypes.POINTER(Request), ctypes.POINTER(_u64)]),
+    "gfp_server_poll": (_int, [_vp, _u64, ctypes.POINTER(Result)]),
+    "gfp_server_wait": (_int, [_vp, _u64, _i64, ctypes.POINTER(Result)]),
+    "gfp_server_drain": (_int, [_vp]),
+    "gfp_server_get_stats": (_int, [_vp, ctypes.POINTER(ServerStats)]),
+    "gfp_server_destroy": (_int, [_vp]),
     "gfp_strerror": (ctypes.c_char_p, [_int]),
 }
 
@@ -241,6 +283,83 @@ class Field:
         _check(lib().gfp_elementwise(self._h, op, px, ldx, py, ldy, pz, ldz, n, s, ch, _stream(stream)),
                "gfp_elementwise")
         return z
+
+
+class Server:
+    """Request loop (gfp_server): continuous batching of polynomial products.
+
+    Operands and results are caller-owned (k, ld) device tensors; keep them
+    alive until the ticket is done.  Pass ``ready`` (a recorded
+    torch.cuda.Event) when the operands are still being written on some
+    stream; otherwise they must be ready when submit is called."""
+
+    def __init__(self, workspace_bytes: int, slots: int = 2, max_batch: int = 256, max_pending: int = 65536,
+                 max_wait_us: int = 0, device: int = -1):
+        cfg = ServerConfig(workspace_bytes, slots, max_batch, max_pending, max_wait_us, device, 0)
+        h = _vp()
+        _check(lib().gfp_server_create(ctypes.byref(cfg), ctypes.byref(h)), "gfp_server_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gfp_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def request(field: "Field", a, b, c, la=None, lb=None, ready=None) -> Request:
+        la = a.shape[1] if la is None else la
+        lb = b.shape[1] if lb is None else lb
+        pa, lda = _vec(a, field.k, la, "a")
+        pb, ldb = _vec(b, field.k, lb, "b")
+        pc, ldc = _vec(c, field.k, la + lb - 1, "c")
+        ev = ready.cuda_event if ready is not None else None
+        return Request(field.handle, pa, la, lda, pb, lb, ldb, pc, ldc, ev)
+
+    def submit_request(self, req: Request) -> int:
+        """Returns the ticket; raises GFPError (code GFP_EAGAIN when full)."""
+        t = _u64()
+        _check(lib().gfp_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "gfp_server_submit")
+        return t.value
+
+    def submit(self, field: "Field", a, b, c, la=None, lb=None, ready=None) -> int:
+        return self.submit_request(self.request(field, a, b, c, la, lb, ready))
+
+    def poll(self, ticket: int):
+        """Result dict when done, None while pending."""
+        r = Result()
+        rc = lib().gfp_server_poll(self._h, ticket, ctypes.byref(r))
+        if rc == GFP_EPENDING:
+            return None
+        _check(rc, "gfp_server_poll")
+        return r.as_dict()
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        r = Result()
+        rc = lib().gfp_server_wait(self._h, ticket, timeout_us, ctypes.byref(r))
+        if rc == GFP_EPENDING:
+            return None
+        _check(rc, "gfp_server_wait")
+        return r.as_dict()
+
+    def drain(self):
+        _check(lib().gfp_server_drain(self._h), "gfp_server_drain")
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().gfp_server_get_stats(self._h, ctypes.byref(s)), "gfp_server_get_stats")
+        return s.as_dict()
 
 
 # ---- numpy <-> device helpers (marshalling only) --------------------------------

@@ -85,3 +85,54 @@ def test_error_codes():
     assert L.gfp_polymul(f.handle, ctypes.c_void_p(8), 0, 1, ctypes.c_void_p(8), 1, 1, ctypes.c_void_p(8), 1, None, 0, None) == gfp.GFP_EINVAL
     assert L.gfp_elementwise(f.handle, 99, ctypes.c_void_p(8), 1, None, 0, ctypes.c_void_p(8), 1, 1, 0, None, None) == gfp.GFP_EINVAL
     assert gfp.strerror(gfp.GFP_ENOTPRIME).startswith("r^k + 1")
+
+
+def test_server_argument_errors():
+    """Argument checks of the request loop run before any device call."""
+    L = _lib()
+    h = ctypes.c_void_p()
+    cfg = gfp.ServerConfig(1 << 30, 2, 16, 64, 0, -1, 0)
+    assert L.gfp_server_create(None, ctypes.byref(h)) == gfp.GFP_EINVAL
+    assert L.gfp_server_create(ctypes.byref(cfg), None) == gfp.GFP_EINVAL
+    bad = gfp.ServerConfig(1 << 30, 2, 16, 64, 0, -1, 1)  # reserved must be 0
+    assert L.gfp_server_create(ctypes.byref(bad), ctypes.byref(h)) == gfp.GFP_EINVAL
+    tiny = gfp.ServerConfig(100, 2, 16, 64, 0, -1, 0)  # under 256 bytes per slot
+    assert L.gfp_server_create(ctypes.byref(tiny), ctypes.byref(h)) == gfp.GFP_EINVAL
+    many = gfp.ServerConfig(1 << 30, 65, 16, 64, 0, -1, 0)
+    assert L.gfp_server_create(ctypes.byref(many), ctypes.byref(h)) == gfp.GFP_EINVAL
+    t = ctypes.c_uint64()
+    r = gfp.Result()
+    assert L.gfp_server_submit(None, None, ctypes.byref(t)) == gfp.GFP_EINVAL
+    assert L.gfp_server_poll(None, 1, ctypes.byref(r)) == gfp.GFP_EINVAL
+    assert L.gfp_server_wait(None, 1, 0, ctypes.byref(r)) == gfp.GFP_EINVAL
+    assert L.gfp_server_drain(None) == gfp.GFP_EINVAL
+    assert L.gfp_server_destroy(None) == gfp.GFP_OK
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes mirror has the size and field offsets that a C compiler
+    gives the header's struct."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        pytest.skip("no C compiler")
+    mirrors = {"gfp_server_config": gfp.ServerConfig, "gfp_request": gfp.Request, "gfp_result": gfp.Result,
+               "gfp_server_stats": gfp.ServerStats, "gfp_polymul_desc": gfp.PolymulDesc}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gfp.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append('printf("%%s %%zu\\n", "%s", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%%s.%%s %%zu\\n", "%s", "%s", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                                check=True).stdout.split("\n") if line)
+    for cname, py in mirrors.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, fname)]) == getattr(py, fname).offset, (cname, fname)
