@@ -174,7 +174,7 @@ def batched_leg(torch, f, dev, reps: int):
     }
 
 
-def served_leg(torch, dev, n_req: int, loads, workspace_gib: int, slots: int):
+def served_leg(torch, dev, n_req: int, loads, workspace_gib: int, slots: int, express_log2n: int):
     """Config 4: a stream of n_req product requests, each over the k = 8 or the
     k = 16 prime (fair coin), la = lb = floor(2^U), U uniform on [8, 19],
     Poisson arrivals.  The arrival rate is `load` times the saturated request
@@ -283,7 +283,8 @@ def served_leg(torch, dev, n_req: int, loads, workspace_gib: int, slots: int):
     runs = {}
     for j, load in enumerate(loads):
         lam = load * mu
-        with Server(workspace_bytes=workspace_gib << 30, slots=slots, max_batch=256, max_pending=n_req) as srv:
+        with Server(workspace_bytes=workspace_gib << 30, slots=slots, max_batch=256, max_pending=n_req,
+                    express_log2n=express_log2n) as srv:
             cb = serve(srv, lam, j)
         print("served: load %.2f continuous batching p99 %.3f ms" % (load, cb["p99_ms"]), file=sys.stderr, flush=True)
         with Server(workspace_bytes=2 << 30, slots=1, max_batch=1, max_pending=n_req) as srv:
@@ -301,6 +302,7 @@ def served_leg(torch, dev, n_req: int, loads, workspace_gib: int, slots: int):
         "plain_saturated_requests_per_s": round(mu, 1),
         "plain_saturated_coeffs_per_s": round(coefs / t_plain, 1),
         "slots": slots,
+        "express_log2n": express_log2n,
         "workspace_gib": workspace_gib,
         "loads": runs,
     }
@@ -331,6 +333,8 @@ def main():
     ap.add_argument("--served-loads", default="0.7", help="comma-separated fractions of the plain saturated rate")
     ap.add_argument("--served-workspace-gib", type=int, default=16)
     ap.add_argument("--served-slots", type=int, default=2)
+    ap.add_argument("--served-express-log2n", type=int, default=16,
+                    help="the last slot serves only transform sizes up to 2^this (0: no express slot)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one transform does not span GPUs). "
@@ -446,7 +450,7 @@ def main():
         out["batched"] = batched_leg(torch, f, dev, args.batched_reps)
     if not args.no_served:
         out["served"] = served_leg(torch, dev, args.served_requests, [float(x) for x in args.served_loads.split(",")],
-                                   args.served_workspace_gib, args.served_slots)
+                                   args.served_workspace_gib, args.served_slots, args.served_express_log2n)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
     print(json.dumps(out), flush=True)

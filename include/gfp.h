@@ -193,9 +193,11 @@ int gfp_elementwise(const gfp_field* f, int op, const uint64_t* x, uint64_t ld_x
  * workspace budget; a slot that is free takes the requests waiting at that
  * moment (first come, first served, up to max_batch, as long as their
  * transform workspace fits the slot's share) and runs them as one
- * gfp_polymul_batched call per field.  Requests that arrive while slots are
- * busy wait until a slot frees, and batches of different slots run
- * concurrently on the device.  Each result is bit-identical to gfp_polymul of
+ * gfp_polymul_batched call per (field, transform size) class, smallest first;
+ * each class is done as soon as its own work is.  Requests that arrive while
+ * slots are busy wait until a slot frees, and batches of different slots run
+ * concurrently on the device.  An express slot (express_log2n) serves only
+ * small requests, taken from anywhere in the queue in arrival order.  Each result is bit-identical to gfp_polymul of
  * the same request alone: the arithmetic is exact and does not depend on the
  * batch.  All calls are thread-safe, except that gfp_server_destroy must not
  * overlap any other call on the same server.  Timestamps are CLOCK_MONOTONIC
@@ -209,7 +211,8 @@ typedef struct gfp_server_config {
   uint32_t max_pending;     /* submitted, not yet admitted requests before submit returns GFP_EAGAIN (0 = 65536) */
   uint32_t max_wait_us;     /* a free slot waits up to this long for more requests before launching (0 = launch at once) */
   int32_t device;           /* HIP device ordinal, -1 = the current device */
-  uint32_t reserved;        /* must be 0 */
+  uint32_t express_log2n;   /* 0, or: the last slot only takes requests of transform size <= 2^express_log2n
+                               (needs slots >= 2) */
 } gfp_server_config;
 
 typedef struct gfp_request {
@@ -245,8 +248,8 @@ typedef struct gfp_server_stats {
 
 /* Start a server on cfg->device: allocates the workspace (cfg->workspace_bytes)
  * and creates the slot streams and threads.  Errors: GFP_EINVAL (NULL
- * argument, reserved != 0, workspace_bytes / slots of 0), GFP_ENOMEM,
- * GFP_EDEVICE. */
+ * argument, slots > 64, workspace_bytes / slots under 256 bytes,
+ * express_log2n > 40 or with fewer than 2 slots), GFP_ENOMEM, GFP_EDEVICE. */
 int gfp_server_create(const gfp_server_config* cfg, gfp_server** out);
 
 /* Queue one request; returns at once with a ticket (1, 2, ...).  The request

@@ -2,13 +2,18 @@
 // (section 3.3, Alg. Fast Convolution) over a fixed workspace budget.
 //
 // Structure: one queue of submitted requests (FIFO) and `slots` worker
-// threads.  Each worker owns a HIP stream, an event and an equal share of the
+// threads.  Each worker owns a HIP stream, events and an equal share of the
 // workspace.  A free worker takes the requests waiting at the head of the
 // queue while their combined workspace fits its share (the same chunk rule as
-// gfp_polymul_batched), enqueues one gfp_polymul_batched call per field on its
-// stream, waits for its event and marks the requests done.  Workers run
+// gfp_polymul_batched) and enqueues one gfp_polymul_batched call per (field,
+// transform size) class, smallest size first, with an event after each; it
+// marks each class done as soon as its event completes, so the small requests
+// of a mixed batch do not wait for its large ones.  Workers run
 // independently, so a batch that arrives while another is on the device is
-// launched at once on another stream and the two overlap.
+// launched at once on another stream and the two overlap.  With an express
+// slot configured, the last worker only takes requests of small transform
+// size (the earliest ones waiting, wherever they are in the queue), so those
+// never queue behind large ones.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <time.h>
@@ -45,9 +50,18 @@ struct Request {
 
 struct Slot {
   hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
+  std::vector<hipEvent_t> events;  // one per class of a batch, created on demand
   uint64_t* ws = nullptr;
+  bool express = false;  // takes only requests with n <= express_n
   std::thread thread;
+};
+
+// Requests of one (field, transform size) class within a batch.
+struct Class {
+  const gfp_field* field;
+  uint64_t n;
+  std::vector<uint64_t> tickets;
+  std::vector<gfp_polymul_desc> descs;
 };
 
 }  // namespace
@@ -55,6 +69,7 @@ struct Slot {
 struct gfp_server {
   gfp_server_config cfg{};
   uint64_t slot_bytes = 0;
+  uint64_t express_n = 0;  // 0: no express slot
   void* ws_base = nullptr;
   std::vector<Slot> slots;
 
@@ -101,33 +116,51 @@ void finish(gfp_server* s, const std::vector<uint64_t>& tickets, int status, uin
   s->st.completed += tickets.size();
 }
 
-// Enqueue the batch on the slot's stream and wait for it.  Runs without the
-// lock; `batch` is a private copy of the requests.
-int run_batch(Slot& sl, uint64_t ws_bytes, const std::vector<gfp_request>& batch) {
-  for (const auto& q : batch) {
-    if (q.ready_event) {
-      hipError_t he = hipStreamWaitEvent(sl.stream, (hipEvent_t)q.ready_event, 0);
-      if (he != hipSuccess) return GFP_EDEVICE;
+// Enqueue the batch's classes on the slot's stream (smallest transform size
+// first), each followed by an event, then wait for the events in order and
+// mark each class done when its event completes.  Enqueueing runs without
+// the lock on private copies of the requests.
+void run_batch(gfp_server* s, Slot& sl, std::vector<Class>& classes, const std::vector<void*>& ready) {
+  std::sort(classes.begin(), classes.end(), [](const Class& x, const Class& y) { return x.n < y.n; });
+  std::vector<int> rc(classes.size(), GFP_OK);
+  size_t enq = 0;  // classes with an event recorded after them
+  int err = GFP_OK;
+  for (void* ev : ready) {
+    if (hipStreamWaitEvent(sl.stream, (hipEvent_t)ev, 0) != hipSuccess) err = GFP_EDEVICE;
+  }
+  for (size_t i = 0; i < classes.size(); ++i) {
+    if (err == GFP_OK) {
+      Class& c = classes[i];
+      err = gfp_polymul_batched(c.field, (uint32_t)c.descs.size(), c.descs.data(), sl.ws, s->slot_bytes, 0, sl.stream);
+    }
+    rc[i] = err;
+    while (sl.events.size() <= i) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) break;
+      sl.events.push_back(e);
+    }
+    // an event is recorded even after an error, so the stream has drained
+    // before the requests go back to the caller
+    if (sl.events.size() > i && hipEventRecord(sl.events[i], sl.stream) == hipSuccess) {
+      enq = i + 1;
+    } else {
+      if (err == GFP_OK) err = GFP_EDEVICE;
+      rc[i] = err;
+      break;
     }
   }
-  // one batched call per field, fields in order of first appearance
-  std::vector<const gfp_field*> fields;
-  for (const auto& q : batch)
-    if (std::find(fields.begin(), fields.end(), q.field) == fields.end()) fields.push_back(q.field);
-  int rc = GFP_OK;
-  for (const gfp_field* f : fields) {
-    std::vector<gfp_polymul_desc> d;
-    for (const auto& q : batch)
-      if (q.field == f) d.push_back(gfp_polymul_desc{q.a, q.la, q.ld_a, q.b, q.lb, q.ld_b, q.c, q.ld_c});
-    rc = gfp_polymul_batched(f, (uint32_t)d.size(), d.data(), sl.ws, ws_bytes, 0, sl.stream);
-    if (rc != GFP_OK) break;
+  if (enq < classes.size()) {  // no event for the rest: wait for the whole stream
+    if (hipStreamSynchronize(sl.stream) != hipSuccess && err == GFP_OK) err = GFP_EDEVICE;
   }
-  // the event is recorded even after an error so the stream drains before the
-  // requests are released to the caller
-  hipError_t he = hipEventRecord(sl.done, sl.stream);
-  if (he == hipSuccess) he = hipEventSynchronize(sl.done);
-  if (rc == GFP_OK && he != hipSuccess) rc = GFP_EDEVICE;
-  return rc;
+  for (size_t i = 0; i < classes.size(); ++i) {
+    int st = i < enq ? rc[i] : err;
+    if (i < enq && hipEventSynchronize(sl.events[i]) != hipSuccess && st == GFP_OK) st = GFP_EDEVICE;
+    if (i >= enq && st == GFP_OK) st = GFP_EDEVICE;
+    const uint64_t t_done = now_ns();
+    std::lock_guard<std::mutex> lk(s->mu);
+    finish(s, classes[i].tickets, st, t_done);
+    s->cv_done.notify_all();
+  }
 }
 
 void worker(gfp_server* s, size_t idx) {
@@ -135,8 +168,15 @@ void worker(gfp_server* s, size_t idx) {
   (void)hipSetDevice(s->cfg.device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
-    s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
-    if (s->queue.empty()) {
+    // an express slot only wakes for work it can take
+    auto eligible = [&]() -> bool {
+      if (!sl.express) return !s->queue.empty();
+      for (uint64_t t : s->queue)
+        if (s->reqs[t].n <= s->express_n) return true;
+      return false;
+    };
+    s->cv_work.wait(lk, [&] { return s->stopping || eligible(); });
+    if (!eligible()) {
       if (s->stopping) return;
       continue;
     }
@@ -148,21 +188,36 @@ void worker(gfp_server* s, size_t idx) {
         if (t >= deadline) break;
         s->cv_work.wait_for(lk, std::chrono::nanoseconds(deadline - t));
       }
-      if (s->queue.empty()) continue;  // another slot took them
+      if (!eligible()) continue;  // another slot took them
     }
-    // admission: head of the queue, in order, while the workspace fits
+    // admission in arrival order while the workspace fits: from the head of
+    // the queue (stopping at the first request that does not fit), or for
+    // the express slot the small requests wherever they are
     Need need;
     std::vector<uint64_t> tickets;
-    std::vector<gfp_request> batch;
+    std::vector<Class> classes;
+    std::vector<void*> ready;
     const uint64_t t_admit = now_ns();
-    while (!s->queue.empty() && tickets.size() < s->cfg.max_batch) {
-      Request& r = s->reqs[s->queue.front()];
+    for (auto it = s->queue.begin(); it != s->queue.end() && tickets.size() < s->cfg.max_batch;) {
+      Request& r = s->reqs[*it];
+      if (sl.express && r.n > s->express_n) {
+        ++it;
+        continue;
+      }
       if (need.with(r) > s->slot_bytes) break;
       need.add(r);
       r.res.t_admit_ns = t_admit;
-      tickets.push_back(s->queue.front());
-      batch.push_back(r.q);
-      s->queue.pop_front();
+      tickets.push_back(*it);
+      auto c = std::find_if(classes.begin(), classes.end(),
+                            [&](const Class& x) { return x.field == r.q.field && x.n == r.n; });
+      if (c == classes.end()) {
+        classes.push_back(Class{r.q.field, r.n, {}, {}});
+        c = classes.end() - 1;
+      }
+      c->tickets.push_back(*it);
+      c->descs.push_back(gfp_polymul_desc{r.q.a, r.q.la, r.q.ld_a, r.q.b, r.q.lb, r.q.ld_b, r.q.c, r.q.ld_c});
+      if (r.q.ready_event) ready.push_back(r.q.ready_event);
+      it = s->queue.erase(it);
     }
     const uint64_t bid = s->next_batch++;
     if (s->in_flight > 0) ++s->st.overlapped_batches;
@@ -177,16 +232,13 @@ void worker(gfp_server* s, size_t idx) {
       r.res.batch_size = (uint32_t)tickets.size();
       r.res.t_launch_ns = t_launch;
     }
-    if (!s->queue.empty()) s->cv_work.notify_one();  // let another free slot take the rest
+    if (!s->queue.empty()) s->cv_work.notify_all();  // let other free slots take the rest
     lk.unlock();
 
-    const int rc = run_batch(sl, s->slot_bytes, batch);
-    const uint64_t t_done = now_ns();
+    run_batch(s, sl, classes, ready);
 
     lk.lock();
     --s->in_flight;
-    finish(s, tickets, rc, t_done);
-    s->cv_done.notify_all();
   }
 }
 
@@ -198,7 +250,7 @@ bool valid_request(const gfp_request* q) {
 
 void release(gfp_server* s) {
   for (auto& sl : s->slots) {
-    if (sl.done) (void)hipEventDestroy(sl.done);
+    for (hipEvent_t e : sl.events) (void)hipEventDestroy(e);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   if (s->ws_base) (void)hipFree(s->ws_base);
@@ -212,12 +264,12 @@ extern "C" {
 int gfp_server_create(const gfp_server_config* cfg, gfp_server** out) {
   if (!out) return GFP_EINVAL;
   *out = nullptr;
-  if (!cfg || cfg->reserved != 0) return GFP_EINVAL;
+  if (!cfg) return GFP_EINVAL;
   gfp_server_config c = *cfg;
   if (c.slots == 0) c.slots = 2;
   if (c.max_batch == 0) c.max_batch = 256;
   if (c.max_pending == 0) c.max_pending = 65536;
-  if (c.slots > 64) return GFP_EINVAL;
+  if (c.slots > 64 || c.express_log2n > 40 || (c.express_log2n && c.slots < 2)) return GFP_EINVAL;
   // slot shares are multiples of 256 bytes
   const uint64_t slot_bytes = (c.workspace_bytes / c.slots) & ~255ull;
   if (slot_bytes == 0) return GFP_EINVAL;
@@ -239,15 +291,14 @@ int gfp_server_create(const gfp_server_config* cfg, gfp_server** out) {
     s->ws_base = nullptr;
     rc = GFP_ENOMEM;
   }
+  s->express_n = c.express_log2n ? (1ull << c.express_log2n) : 0;
   s->slots.resize(c.slots);
   for (uint32_t i = 0; rc == GFP_OK && i < c.slots; ++i) {
     Slot& sl = s->slots[i];
     sl.ws = (uint64_t*)((char*)s->ws_base + i * slot_bytes);
+    sl.express = c.express_log2n && i + 1 == c.slots;
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
       sl.stream = nullptr;
-      rc = GFP_EDEVICE;
-    } else if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
-      sl.done = nullptr;
       rc = GFP_EDEVICE;
     }
   }
@@ -283,7 +334,7 @@ int gfp_server_submit(gfp_server* s, const gfp_request* req, uint64_t* ticket) {
   ++s->unfinished;
   ++s->st.submitted;
   *ticket = t;
-  s->cv_work.notify_one();
+  s->cv_work.notify_all();  // an express slot may not be able to take it
   return GFP_OK;
 }
 

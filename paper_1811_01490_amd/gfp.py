@@ -42,7 +42,7 @@ class ServerConfig(ctypes.Structure):
     """gfp_server_config"""
     _fields_ = [("workspace_bytes", ctypes.c_uint64), ("slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
                 ("max_pending", ctypes.c_uint32), ("max_wait_us", ctypes.c_uint32), ("device", ctypes.c_int32),
-                ("reserved", ctypes.c_uint32)]
+                ("express_log2n", ctypes.c_uint32)]
 
 
 class Request(ctypes.Structure):
@@ -294,8 +294,8 @@ class Server:
     stream; otherwise they must be ready when submit is called."""
 
     def __init__(self, workspace_bytes: int, slots: int = 2, max_batch: int = 256, max_pending: int = 65536,
-                 max_wait_us: int = 0, device: int = -1):
-        cfg = ServerConfig(workspace_bytes, slots, max_batch, max_pending, max_wait_us, device, 0)
+                 max_wait_us: int = 0, device: int = -1, express_log2n: int = 0):
+        cfg = ServerConfig(workspace_bytes, slots, max_batch, max_pending, max_wait_us, device, express_log2n)
         h = _vp()
         _check(lib().gfp_server_create(ctypes.byref(cfg), ctypes.byref(h)), "gfp_server_create")
         self._h = h

@@ -94,7 +94,9 @@ def test_server_argument_errors():
     cfg = gfp.ServerConfig(1 << 30, 2, 16, 64, 0, -1, 0)
     assert L.gfp_server_create(None, ctypes.byref(h)) == gfp.GFP_EINVAL
     assert L.gfp_server_create(ctypes.byref(cfg), None) == gfp.GFP_EINVAL
-    bad = gfp.ServerConfig(1 << 30, 2, 16, 64, 0, -1, 1)  # reserved must be 0
+    bad = gfp.ServerConfig(1 << 30, 1, 16, 64, 0, -1, 12)  # an express slot needs a second slot
+    assert L.gfp_server_create(ctypes.byref(bad), ctypes.byref(h)) == gfp.GFP_EINVAL
+    bad = gfp.ServerConfig(1 << 30, 2, 16, 64, 0, -1, 41)
     assert L.gfp_server_create(ctypes.byref(bad), ctypes.byref(h)) == gfp.GFP_EINVAL
     tiny = gfp.ServerConfig(100, 2, 16, 64, 0, -1, 0)  # under 256 bytes per slot
     assert L.gfp_server_create(ctypes.byref(tiny), ctypes.byref(h)) == gfp.GFP_EINVAL

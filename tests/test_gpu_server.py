@@ -6,7 +6,10 @@ must answer GFP_EAGAIN, and shutdown must cancel what was not admitted.
 
 To make the timing-dependent cases deterministic, a batch is held on the
 device by giving its request a ready event recorded after a bounded spin
-kernel (torch.cuda._sleep) on another stream."""
+kernel (torch.cuda._sleep) on another stream.  The scheduling assertions use
+the host-side admission and launch times: HIP maps streams onto a few
+hardware queues, so the spin kernel may share a queue with another slot's
+stream and delay its device work, but never its admission."""
 
 import time
 
@@ -137,7 +140,7 @@ def test_arrivals_during_a_batch_use_another_slot(torch_mod, fields, sleep_cycle
     side.synchronize()
     assert r_big["status"] == 0 and all(r["status"] == 0 for r in rs)
     assert all(r["batch_id"] != r_big["batch_id"] for r in rs)
-    assert all(r["t_done_ns"] < r_big["t_done_ns"] for r in rs)  # served while the big batch was held
+    assert all(r["t_launch_ns"] < r_big["t_done_ns"] for r in rs)  # launched while the big batch was held
     assert st["overlapped_batches"] >= 1
     _check_alone(f, da, db, c)
     for x, cc in zip(small, cs):
@@ -207,3 +210,64 @@ def test_full_queue_and_shutdown(torch_mod, fields, sleep_cycles):
     for c in outs:
         assert bool((c == -1).all())  # never written
     assert t0 not in ts
+
+
+def test_express_slot_serves_small_requests_past_large_ones(torch_mod, fields, sleep_cycles):
+    """With an express slot, a small request submitted behind queued large
+    ones is served while they wait; the large ones keep their order."""
+    import torch
+
+    from paper_1811_01490_amd import Server
+
+    f = fields[8]
+    big = [_operands(P8, 3000, 3000, 500 + i) for i in range(3)]  # transform size 16^4
+    small = _operands(P8, 100, 100, 510)  # transform size 16^3
+    cb = [_out(torch, 8, 5999) for _ in big]
+    cs = _out(torch, 8, 199)
+    torch.cuda.synchronize()
+    with Server(workspace_bytes=2 * f.polymul_workspace_size(3000, 3000), slots=2, max_batch=1,
+                express_log2n=12) as srv:
+        ev, side = _held_event(torch, sleep_cycles)
+        tb = [srv.submit(f, big[0][2], big[0][3], cb[0], ready=ev)]
+        time.sleep(0.005)
+        tb += [srv.submit(f, x[2], x[3], c) for x, c in zip(big[1:], cb[1:])]
+        ts = srv.submit(f, small[2], small[3], cs)
+        r_small = srv.wait(ts)
+        rb = [srv.wait(t) for t in tb]
+    side.synchronize()
+    assert r_small["status"] == 0 and all(r["status"] == 0 for r in rb)
+    assert r_small["t_launch_ns"] < rb[0]["t_done_ns"]  # launched while the held large batch ran
+    assert r_small["t_launch_ns"] < rb[1]["t_admit_ns"]  # ahead of the large ones queued before it
+    assert rb[0]["t_done_ns"] <= rb[1]["t_launch_ns"] <= rb[2]["t_launch_ns"]  # one general slot, FIFO
+    _check_alone(f, small[2], small[3], cs)
+    for x, c in zip(big, cb):
+        _check_alone(f, x[2], x[3], c)
+
+
+def test_mixed_batch_completes_small_class_first(torch_mod, fields, sleep_cycles):
+    """One batch with a small and a large class: the small class is done
+    before the large one."""
+    import torch
+
+    from paper_1811_01490_amd import Server
+
+    f = fields[16]
+    hold = _operands(P16, 10, 10, 600)
+    ch = _out(torch, 16, 19)
+    large = _operands(P16, 2 ** 14, 2 ** 14, 601)  # transform size 32^3
+    small = _operands(P16, 30, 20, 602)
+    cl, cs = _out(torch, 16, 2 ** 15 - 1), _out(torch, 16, 49)
+    torch.cuda.synchronize()
+    with Server(workspace_bytes=4 << 30, slots=1, max_batch=64) as srv:
+        ev, side = _held_event(torch, sleep_cycles)
+        t0 = srv.submit(f, hold[2], hold[3], ch, ready=ev)
+        time.sleep(0.005)
+        tl = srv.submit(f, large[2], large[3], cl)  # queued in arrival order, large first
+        ts = srv.submit(f, small[2], small[3], cs)
+        rl, rs = srv.wait(tl), srv.wait(ts)
+        srv.wait(t0)
+    side.synchronize()
+    assert rl["batch_id"] == rs["batch_id"] and rl["batch_size"] == 2
+    assert rs["t_done_ns"] <= rl["t_done_ns"]
+    _check_alone(f, large[2], large[3], cl)
+    _check_alone(f, small[2], small[3], cs)
