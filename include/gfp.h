@@ -184,6 +184,44 @@ int gfp_polymul_batched(const gfp_field* f, uint32_t n, const gfp_polymul_desc* 
 int gfp_elementwise(const gfp_field* f, int op, const uint64_t* x, uint64_t ld_x, const uint64_t* y, uint64_t ld_y,
                     uint64_t* z, uint64_t ld_z, uint64_t n, int64_t s, const uint64_t* c_host, void* stream);
 
+/* ---- Stage groupings and the autotuner -------------------------------------
+ *
+ * A transform of size n = K^e runs as a sequence of launches, each covering
+ * one radix-K pass or (k = 8) two consecutive passes fused in one launch,
+ * with the stride permutation between them (section 4.1, eq. sixstepfft)
+ * staged through LDS so the intermediate never goes to HBM.  A plan is a
+ * string with one character per launch: '1' one pass, '2' two fused passes
+ * (two K^2-element blocks per workgroup; the second pass reads its twiddles
+ * per element group), 'w' two fused passes over eight blocks per workgroup
+ * (wavefront-uniform twiddles in both passes; needs n / (K^2 K^s) >= 8 at
+ * its first pass s).  Example: "1211" for e = 5.  Plans are kept per
+ * (n, batch class, layout): the batch class is the number of same-size
+ * transforms one launch covers (1, 2-7, 8-63, 64 and more: gfp_polymul runs
+ * 2 forward and 1 inverse, gfp_polymul_batched 2C and C); the layout is that
+ * of the transform's ends (digit-major for gfp_fft_forward/inverse,
+ * element-major inside the products).  Keys without a plan use a built-in
+ * default.  Results never depend on the plan.  Plans live in the field
+ * object; a caller that wants them to persist stores the strings. */
+#define GFP_LAYOUT_DIGIT_MAJOR 0
+#define GFP_LAYOUT_ELEMENT_MAJOR 1
+
+/* The plan in use for nvec transforms of size n with the given layout, as a
+ * NUL-terminated string in buf (len >= e + 1). */
+int gfp_plan_get(const gfp_field* f, uint64_t n, uint64_t nvec, int layout, char* buf, uint32_t len);
+
+/* Set the plan for (n, batch class of nvec, layout); plan NULL or "" restores
+ * the default.  GFP_EINVAL for an unknown character, passes that do not sum
+ * to e, a fused pair for a k without one, or 'w' where it does not fit. */
+int gfp_plan_set(gfp_field* f, uint64_t n, uint64_t nvec, int layout, const char* plan);
+
+/* Autotuner: times every valid plan on nvec forward transforms of size n with
+ * the given layout, on `stream`, and keeps the fastest for (n, batch class,
+ * layout).  Allocates and frees its own device buffers (4 nvec n k words, at
+ * most 8 GiB each) and synchronises the stream; must not be called during
+ * stream capture.  best: the chosen plan (len >= e + 1) or NULL; us: its mean
+ * time in microseconds or NULL. */
+int gfp_tune(gfp_field* f, uint64_t n, uint64_t nvec, int layout, void* stream, char* best, uint32_t len, double* us);
+
 /* ---- Request loop (serving) ------------------------------------------------
  *
  * A server takes polynomial-product requests (section 3.3, Alg. Fast

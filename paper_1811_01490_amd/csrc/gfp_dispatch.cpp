@@ -25,6 +25,8 @@ bool shape_supported(int k, int w, int u) {
   return false;
 }
 
+bool span2_supported(int k) { return k == 8; }
+
 hipError_t launch_pass(int k, int w, int u, const PassArgs& p, hipStream_t st) {
 #define GFP_SHAPE_CASE(K, W, U) \
   if (k == K && w == W && u == U) return launch_pass_##K##_##W##_##U(p, st);

@@ -5,7 +5,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
+#include <string>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -49,6 +52,10 @@ struct gfp_field {
   std::map<std::pair<int, uint64_t>, DevTables> tables;
   std::map<int, DevConsts> consts;
   std::map<uint64_t, hipGraphExec_t> graphs;  // batched products, keyed by argument hash
+  // stage groupings: (log2 n, batch class, layout) -> launch codes (1: one
+  // pass, 2: fused pair, 3: wide fused pair), set by gfp_plan_set /
+  // gfp_tune; keys without an entry use default_plan
+  std::map<std::tuple<int, int, int>, std::vector<int>> plans;
 };
 
 namespace {
@@ -283,22 +290,89 @@ struct VecView {
 // nvec * n elements); X is only read by pass 0.  `canonical`: the last pass
 // writes the canonical encoding (else congruent digits in [0, 2^64)).  When
 // Y aliases X and e == 1 the pass writes W1 and the result is copied.
-int run_transform(gfp_field* f, int log2n, int e, bool inverse, VecView X, VecView Y, uint64_t nvec, bool canonical,
-                  uint64_t* W1, uint64_t* W2, hipStream_t st) {
+// ---------------------------------------------------------------------------
+// stage groupings (which passes share a launch)
+// ---------------------------------------------------------------------------
+// Batch class of a launch over nvec transforms: 0 (1), 1 (2..7), 2 (8..63), 3.
+int batch_class(uint64_t nvec) { return nvec <= 1 ? 0 : nvec < 8 ? 1 : nvec < 64 ? 2 : 3; }
+
+// Launch codes: 1 = one pass, 2 = two passes fused (two blocks per
+// workgroup), 3 = two passes fused, eight blocks per workgroup ("wide").
+enum { LC_ONE = 1, LC_PAIR = 2, LC_WIDE = 3 };
+int code_passes(int c) { return c == LC_ONE ? 1 : 2; }
+char code_char(int c) { return c == LC_WIDE ? 'w' : (char)('0' + c); }
+int char_code(char c) { return c == '1' ? LC_ONE : c == '2' ? LC_PAIR : c == 'w' ? LC_WIDE : 0; }
+
+bool plan_valid(const gfp_field* f, int log2n, int e, const std::vector<int>& plan) {
+  const int lk = log2_exact(2ull * f->k);
+  int s = 0;
+  for (int c : plan) {
+    if (c < LC_ONE || c > LC_WIDE) return false;
+    if (c != LC_ONE && !gfpk::span2_supported((int)f->k)) return false;
+    if (s + code_passes(c) > e) return false;
+    if (c == LC_WIDE && log2n - 2 * lk - s * lk < 3) return false;  // 8 blocks per twiddle base
+    s += code_passes(c);
+  }
+  return s == e;
+}
+
+std::string plan_text(const std::vector<int>& plan) {
+  std::string t;
+  for (int c : plan) t += code_char(c);
+  return t;
+}
+
+// Untuned choice (k = 8), the fastest plans measured on MI355X for one
+// transform (digit-major ends) and for the two forward transforms of a
+// product (element-major); k = 16 runs one pass per launch.
+std::vector<int> default_plan(const gfp_field* f, int e, int layout) {
+  std::vector<int> plan;
+  if (!gfpk::span2_supported((int)f->k)) return std::vector<int>(e, LC_ONE);
+  static const char* dm[] = {"", "1", "2", "12", "121", "w21"};
+  static const char* em[] = {"", "1", "2", "12", "22", "w12"};
+  if (e <= 5) {
+    for (const char* c = (layout == GFP_LAYOUT_ELEMENT_MAJOR ? em : dm)[e]; *c; ++c) plan.push_back(char_code(*c));
+    return plan;
+  }
+  int left = e;
+  while (left > 0) {
+    const int c = left >= 2 ? LC_PAIR : LC_ONE;
+    plan.push_back(c);
+    left -= code_passes(c);
+  }
+  return plan;
+}
+
+std::vector<int> plan_for(gfp_field* f, int log2n, int e, uint64_t nvec, int layout) {
+  std::lock_guard<std::mutex> g(f->mu);
+  auto it = f->plans.find(std::make_tuple(log2n, batch_class(nvec), layout));
+  if (it != f->plans.end()) return it->second;
+  return default_plan(f, e, layout);
+}
+
+int view_layout(const VecView& X, const VecView& Y) {
+  return (X.se == 1 || Y.se == 1) ? GFP_LAYOUT_DIGIT_MAJOR : GFP_LAYOUT_ELEMENT_MAJOR;
+}
+
+int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& plan, bool inverse, VecView X,
+                       VecView Y, uint64_t nvec, bool canonical, uint64_t* W1, uint64_t* W2, hipStream_t st) {
   const uint64_t n = 1ull << log2n;
   const uint64_t k = f->k;
   const DevTables* t = nullptr;
   int rc = get_tables(f, n, &t);
   if (rc != GFP_OK) return rc;
+  if (!plan_valid(f, log2n, e, plan)) return GFP_EINVAL;
   const int lk = log2_exact(2ull * f->k);
-  if (e == 1 && X.p == Y.p) return GFP_EINVAL;  // a single pass cannot run in place
+  const int nl = (int)plan.size();
+  if (nl == 1 && X.p == Y.p) return GFP_EINVAL;  // a single launch cannot run in place
   VecView src = X;
-  for (int s = 0; s < e; ++s) {
+  int s = 0;
+  for (int i = 0; i < nl; ++i) {
     VecView dst;
-    if (s == e - 1) {
+    if (i == nl - 1) {
       dst = Y;
     } else {
-      dst.p = (((e - 2 - s) % 2) == 0) ? W1 : W2;  // pass e-2 -> W1, e-3 -> W2, ...
+      dst.p = (((nl - 2 - i) % 2) == 0) ? W1 : W2;  // launch nl-2 -> W1, nl-3 -> W2, ...
       dst.se = k;
       dst.sd = 1;
       dst.vs = n * k;
@@ -316,15 +390,25 @@ int run_transform(gfp_field* f, int log2n, int e, bool inverse, VecView X, VecVi
     p.inverse = inverse;
     p.scale = inverse && s == 0;
     p.tw = p.scale ? t->ninv : (inverse ? t->inv : t->fwd);
-    p.last = (s == e - 1) && canonical;
+    p.tw1 = inverse ? t->inv : t->fwd;
+    p.span = code_passes(plan[i]);
+    p.wide = plan[i] == LC_WIDE;
+    p.last = (i == nl - 1) && canonical;
     p.nvec = nvec;
     p.vin = src.vs;
     p.vout = dst.vs;
     hipError_t he = gfpk::launch_pass((int)f->k, f->w, f->u, p, st);
     if (he != hipSuccess) return hip_status(he);
     src = dst;
+    s += code_passes(plan[i]);
   }
   return GFP_OK;
+}
+
+int run_transform(gfp_field* f, int log2n, int e, bool inverse, VecView X, VecView Y, uint64_t nvec, bool canonical,
+                  uint64_t* W1, uint64_t* W2, hipStream_t st) {
+  return run_transform_plan(f, log2n, e, plan_for(f, log2n, e, nvec, view_layout(X, Y)), inverse, X, Y, nvec,
+                            canonical, W1, W2, st);
 }
 
 int transform_entry(const gfp_field* cf, uint64_t n, const uint64_t* x, uint64_t ldx, uint64_t* y, uint64_t ldy,
@@ -343,14 +427,15 @@ int transform_entry(const gfp_field* cf, uint64_t n, const uint64_t* x, uint64_t
   rc = get_workspace(ws, ws_bytes, 2ull * n * f->k * 8, st, s, &w);
   if (rc != GFP_OK) return rc;
   VecView X{x, 1, ldx, 0}, Y{y, 1, ldy, 0};
-  if (e == 1 && x == y) {
-    // one pass cannot run in place: transform into W2 (digit-major, ld n), copy back
+  const std::vector<int> plan = plan_for(f, log2n, e, 1, GFP_LAYOUT_DIGIT_MAJOR);
+  if (plan.size() == 1 && x == y) {
+    // one launch cannot run in place: transform into W2 (digit-major, ld n), copy back
     VecView T{w + n * f->k, 1, n, 0};
-    rc = run_transform(f, log2n, e, inverse, X, T, 1, true, w, w, st);
+    rc = run_transform_plan(f, log2n, e, plan, inverse, X, T, 1, true, w, w, st);
     if (rc != GFP_OK) return rc;
     return hip_status(hipMemcpy2DAsync(y, ldy * 8, T.p, n * 8, n * 8, f->k, hipMemcpyDeviceToDevice, st));
   }
-  return run_transform(f, log2n, e, inverse, X, Y, 1, true, w, w + n * f->k, st);
+  return run_transform_plan(f, log2n, e, plan, inverse, X, Y, 1, true, w, w + n * f->k, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -814,6 +899,122 @@ int gfp_elementwise(const gfp_field* cf, int op, const uint64_t* x, uint64_t ld_
   a.cst = cst;
   hipError_t he = gfpk::launch_elementwise((int)f->k, f->w, f->u, a, st);
   return hip_status(he);
+}
+
+int gfp_plan_get(const gfp_field* cf, uint64_t n, uint64_t nvec, int layout, char* buf, uint32_t len) {
+  gfp_field* f = const_cast<gfp_field*>(cf);
+  if (!f || !buf || nvec == 0 || (layout != GFP_LAYOUT_DIGIT_MAJOR && layout != GFP_LAYOUT_ELEMENT_MAJOR))
+    return GFP_EINVAL;
+  int log2n, e;
+  int rc = check_size(f, n, &log2n, &e);
+  if (rc != GFP_OK) return rc;
+  const std::string t = plan_text(plan_for(f, log2n, e, nvec, layout));
+  if (len < t.size() + 1) return GFP_EINVAL;
+  memcpy(buf, t.c_str(), t.size() + 1);
+  return GFP_OK;
+}
+
+int gfp_plan_set(gfp_field* f, uint64_t n, uint64_t nvec, int layout, const char* text) {
+  if (!f || nvec == 0 || (layout != GFP_LAYOUT_DIGIT_MAJOR && layout != GFP_LAYOUT_ELEMENT_MAJOR)) return GFP_EINVAL;
+  int log2n, e;
+  int rc = check_size(f, n, &log2n, &e);
+  if (rc != GFP_OK) return rc;
+  const auto key = std::make_tuple(log2n, batch_class(nvec), layout);
+  if (!text || !*text) {
+    std::lock_guard<std::mutex> g(f->mu);
+    f->plans.erase(key);
+    return GFP_OK;
+  }
+  std::vector<int> plan;
+  for (const char* c = text; *c; ++c) {
+    const int code = char_code(*c);
+    if (!code) return GFP_EINVAL;
+    plan.push_back(code);
+  }
+  if (!plan_valid(f, log2n, e, plan)) return GFP_EINVAL;
+  std::lock_guard<std::mutex> g(f->mu);
+  f->plans[key] = plan;
+  return GFP_OK;
+}
+
+int gfp_tune(gfp_field* f, uint64_t n, uint64_t nvec, int layout, void* stream, char* best, uint32_t len,
+             double* us) {
+  if (!f || nvec == 0 || (layout != GFP_LAYOUT_DIGIT_MAJOR && layout != GFP_LAYOUT_ELEMENT_MAJOR)) return GFP_EINVAL;
+  if (!f->gpu_shape) return GFP_EUNSUPPORTED;
+  int log2n, e;
+  int rc = check_size(f, n, &log2n, &e);
+  if (rc != GFP_OK) return rc;
+  const uint64_t words = nvec * n * f->k;
+  if (words > (1ull << 30)) return GFP_EINVAL;  // 8 GiB per buffer
+  // every sequence of launch codes the kernels support for this size
+  std::vector<std::vector<int>> cands;
+  std::vector<int> cur;
+  std::function<void(int)> gen = [&](int s) {
+    if (s == e) {
+      if (plan_valid(f, log2n, e, cur)) cands.push_back(cur);
+      return;
+    }
+    for (int c = LC_ONE; c <= LC_WIDE; ++c) {
+      if (s + code_passes(c) > e) continue;
+      cur.push_back(c);
+      gen(s + code_passes(c));
+      cur.pop_back();
+    }
+  };
+  gen(0);
+  hipStream_t st = (hipStream_t)stream;
+  const DevTables* t = nullptr;
+  rc = get_tables(f, n, &t);
+  if (rc != GFP_OK) return rc;
+  uint64_t* buf = nullptr;
+  if (hipMalloc((void**)&buf, 4 * words * 8) != hipSuccess) return GFP_ENOMEM;
+  // canonical digits (every digit 0x5a5a5a5a5a5a5a5a < r) as input
+  hipError_t he = hipMemsetD32Async(buf, 0x5a5a5a5au, 2 * words * 2, st);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  // digit-major: vector v's digit d at v n k + d n; element-major: v n k + i k + d
+  const bool dm = layout == GFP_LAYOUT_DIGIT_MAJOR;
+  const VecView X{buf, dm ? 1 : f->k, dm ? n : 1, n * f->k}, Y{buf + words, dm ? 1 : f->k, dm ? n : 1, n * f->k};
+  uint64_t* W1 = buf + 2 * words;
+  uint64_t* W2 = buf + 3 * words;
+  double best_us = 0;
+  std::vector<int> best_plan;
+  for (const auto& plan : cands) {
+    if (he != hipSuccess || rc != GFP_OK) break;
+    for (int i = 0; i < 2 && rc == GFP_OK; ++i)
+      rc = run_transform_plan(f, log2n, e, plan, false, X, Y, nvec, true, W1, W2, st);
+    const int reps = 5;
+    if (rc == GFP_OK) he = hipEventRecord(e0, st);
+    for (int i = 0; i < reps && rc == GFP_OK && he == hipSuccess; ++i)
+      rc = run_transform_plan(f, log2n, e, plan, false, X, Y, nvec, true, W1, W2, st);
+    if (rc == GFP_OK && he == hipSuccess) he = hipEventRecord(e1, st);
+    if (rc == GFP_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0;
+    if (rc == GFP_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    const double t_us = 1000.0 * ms / reps;
+    if (rc == GFP_OK && he == hipSuccess && (best_plan.empty() || t_us < best_us)) {
+      best_us = t_us;
+      best_plan = plan;
+    }
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  if (rc != GFP_OK) return rc;
+  if (he != hipSuccess) return hip_status(he);
+  {
+    std::lock_guard<std::mutex> g(f->mu);
+    f->plans[std::make_tuple(log2n, batch_class(nvec), layout)] = best_plan;
+  }
+  if (us) *us = best_us;
+  if (best) {
+    const std::string t = plan_text(best_plan);
+    if (len < t.size() + 1) return GFP_EINVAL;
+    memcpy(best, t.c_str(), t.size() + 1);
+  }
+  return GFP_OK;
 }
 
 const char* gfp_strerror(int code) {

@@ -27,7 +27,16 @@ struct PassArgs {
   uint64_t nvec = 1;  // transforms in this launch (same size)
   uint64_t vin = 0;   // u64 stride between the input vectors
   uint64_t vout = 0;  // u64 stride between the output vectors
+  // span 2: passes log2ns / LOGK and the next one fused in one launch, the
+  // stride permutation between them staged in LDS; tw1 is the table of the
+  // second pass (tw the first pass's, or its scale entry), `last` applies
+  // to the second pass.
+  int span = 1;
+  bool wide = false;  // span 2 over 8 blocks per workgroup (needs N / (K^2 Ns) >= 8)
+  const uint32_t* tw1 = nullptr;
 };
+// Largest span a launch supports for k (0 if none beyond 1).
+bool span2_supported(int k);
 
 struct EwArgs {
   int op;

@@ -127,6 +127,259 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
 }
 
 // ---------------------------------------------------------------------------
+// two radix-K passes s, s+1 in one launch (a stage group of two)
+// ---------------------------------------------------------------------------
+// Block q of a vector (q < N/K^2): a = q mod Ns, c = q / Ns.  Its K^2
+// elements are x[a + Ns c + (N/K^2) t2 + (N/K) t1], t1, t2 < K, and no other
+// block reads or writes them in either pass.  Pass s: group t2 (slots t1,
+// twiddles w_{K Ns}^(a t1), uniform over the block); DFT output t1' of group
+// t2 is stored in LDS at (t1', t2).  Pass s+1 reads the transposed grid:
+// group t1' (slots t2, twiddles w_{K^2 Ns}^((a + Ns t1') t2)) and writes
+// output t2' to a + Ns t1' + K Ns t2' + K^2 Ns c -- the same element
+// operations, in the same order, as the two passes run one after the other
+// (section 4.1: the stride permutation L between the two tensor factors is
+// the LDS transpose).  Two blocks per 256-thread workgroup for k = 8.
+template <int KD>
+struct Span2Geo {
+  static constexpr int KB = Geo<KD>::KB;
+  static constexpr int WPB = KB / Geo<KD>::G;  // wavefronts per block
+  static constexpr int BPW = 4 / WPB;          // blocks per 256-thread workgroup
+  static constexpr int ROW = KB * KD + 8;      // u64 words per LDS row, padded by 64 bytes
+};
+
+template <int KD, int W, int U, bool INV, int MODE, bool LAST>
+__global__ __launch_bounds__(256) void k_pass2(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
+                                               uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
+                                               const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
+                                               int log2n, int log2ns, uint64_t nvec, uint64_t vin, uint64_t vout) {
+  static_assert(KD == 8, "the fused pass pair is built for k = 8");
+  typedef Geo<KD> Gm;
+  typedef Span2Geo<KD> SG;
+  constexpr int KB = Gm::KB;
+  constexpr int LOGKB = ilog2(KB);
+  __shared__ uint64_t lds[SG::BPW * KB * SG::ROW];
+  const int l = Gm::lane();
+  const int m = Gm::digit(l);
+  const int g = Gm::group(l);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int bw = wv / SG::WPB, h = wv % SG::WPB;
+  const int log2nb = log2n - 2 * LOGKB;  // blocks per vector
+  uint64_t gq = (uint64_t)blockIdx.x * SG::BPW + bw;
+  uint64_t vec = gq >> log2nb;
+  const bool active = vec < nvec;
+  if (!active) {
+    gq = 0;
+    vec = 0;
+  }
+  const uint64_t q = gq & ((1ull << log2nb) - 1);
+  in += vec * vin;
+  out += vec * vout;
+  const uint64_t ns = 1ull << log2ns;
+  const uint64_t a = q & (ns - 1);  // uniform over the wavefront
+  const uint64_t c = q >> log2ns;
+  const uint64_t n1 = 1ull << (log2n - LOGKB);
+  const uint64_t n2 = 1ull << log2nb;
+
+  // ---- pass s: group t2, slots t1
+  const uint64_t t2 = (uint64_t)(h * Gm::G + g);
+  const uint64_t base = a + (c << log2ns) + t2 * n2;
+  uint64_t x[KB];
+  static_for<KB>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    x[t] = in[(uint64_t)m * sd_in + (base + (uint64_t)t * n1) * se_in];
+  });
+  L96 v[KB];
+  if constexpr (MODE == MODE_SCALE) {
+    static_for<KB>([&](auto T) {
+      constexpr int t = decltype(T)::value;
+      v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw0, 0, l, m);
+    });
+  } else {
+    v[0] = l96(x[0]);
+    if (a == 0) {
+      static_for<KB - 1>([&](auto T) {
+        constexpr int t = decltype(T)::value + 1;
+        v[t] = l96(x[t]);
+      });
+    } else {
+      const int shift = log2n - log2ns - LOGKB;
+      static_for<KB - 1>([&](auto T) {
+        constexpr int t = decltype(T)::value + 1;
+        const uint64_t e = a * (uint64_t)t;
+        const int rho = (int)(e >> log2ns);
+        const uint64_t cc = e & (ns - 1);
+        const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
+        v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw0 + (cc << shift) * TwLayout<KD>::WORDS, rot, l, m);
+      });
+    }
+  }
+  dft_base<KD, INV>(v, m);
+  uint64_t* L = lds + bw * (KB * SG::ROW);
+  static_for<KB>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    L[t * SG::ROW + (int)t2 * KD + m] = seminorm<KD, W, U>(v[t], m);
+  });
+  __syncthreads();
+
+  // ---- pass s+1: group t1 = h G + g, slots t2
+  const uint64_t t1 = (uint64_t)(h * Gm::G + g);
+  static_for<KB>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    x[t] = L[(int)t1 * SG::ROW + t * KD + m];
+  });
+  const int log2ns1 = log2ns + LOGKB;
+  const uint64_t ns1 = ns << LOGKB;
+  const uint64_t a1 = a + (t1 << log2ns);
+  const int shift1 = log2n - log2ns1 - LOGKB;
+  v[0] = l96(x[0]);
+  static_for<KB - 1>([&](auto T) {
+    constexpr int t = decltype(T)::value + 1;
+    const uint64_t e = a1 * (uint64_t)t;
+    const int rho = (int)(e >> log2ns1);
+    const uint64_t cc = e & (ns1 - 1);
+    const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
+    v[t] = mul_twiddle<KD, W, U>(x[t], tw1 + (cc << shift1) * TwLayout<KD>::WORDS, rot, l, m);
+  });
+  dft_base<KD, INV>(v, m);
+  const uint64_t obase = a + (t1 << log2ns) + (c << (log2ns + 2 * LOGKB));
+  static_for<KB>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    uint64_t d;
+    if constexpr (LAST) {
+      d = canonicalize<KD, W, U>(v[t], l, m);
+    } else {
+      d = seminorm<KD, W, U>(v[t], m);
+    }
+    if (active) out[(uint64_t)m * sd_out + (obase + (uint64_t)t * ns1) * se_out] = d;
+  });
+}
+
+// The same pass pair with uniform twiddles in both halves ("wide"): a
+// 1024-thread workgroup takes the 8 blocks q = a + Ns (8 cb + i), i < 8,
+// which share a.  Pass s: wavefront w handles t2 = w, group g being block g
+// (for s = 0 the 8 groups are consecutive elements, so digit-major loads
+// coalesce).  Pass s+1: wavefront w handles t1' = w, group g being block g,
+// so the twiddle base a + Ns t1' is the same for the whole wavefront.  Needs
+// at least 8 blocks per twiddle base: N / (K^2 Ns) >= 8.
+template <int KD>
+struct Span2UGeo {
+  static constexpr int KB = Geo<KD>::KB;
+  static constexpr int NBLK = 8;                      // blocks per workgroup
+  static constexpr int ROW = KB * KD;                 // u64 words per (block, t1) row
+  static constexpr int BLK = KB * ROW + 8;            // words per block, padded by 64 bytes
+  static constexpr int THREADS = 64 * NBLK * KB / Geo<KD>::G;
+};
+
+template <int KD, int W, int U, bool INV, int MODE, bool LAST>
+__global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
+                                                 uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
+                                                 const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
+                                                 int log2n, int log2ns, uint64_t nvec, uint64_t vin, uint64_t vout) {
+  static_assert(KD == 8, "the fused pass pair is built for k = 8");
+  typedef Geo<KD> Gm;
+  typedef Span2UGeo<KD> SG;
+  static_assert(SG::THREADS == 1024, "one 1024-thread workgroup per 8 blocks");
+  constexpr int KB = Gm::KB;
+  constexpr int LOGKB = ilog2(KB);
+  __shared__ uint64_t lds[SG::NBLK * SG::BLK];
+  const int l = Gm::lane();
+  const int m = Gm::digit(l);
+  const int g = Gm::group(l);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int log2nb = log2n - 2 * LOGKB;      // blocks per vector
+  const int log2wpv = log2nb - 3;            // workgroups per vector
+  const uint64_t wg = blockIdx.x;
+  const uint64_t vec = wg >> log2wpv;
+  const uint64_t r = wg & ((1ull << log2wpv) - 1);
+  in += vec * vin;
+  out += vec * vout;
+  const uint64_t ns = 1ull << log2ns;
+  const uint64_t a = r & (ns - 1);         // uniform over the workgroup
+  const uint64_t c0 = (r >> log2ns) << 3;  // first of the 8 blocks' c
+  const uint64_t n1 = 1ull << (log2n - LOGKB);
+  const uint64_t n2 = 1ull << log2nb;
+
+  // ---- pass s: t2 = wv for the whole wavefront, group g = block g, slots t1
+  const uint64_t t2 = (uint64_t)wv;
+  const uint64_t base = a + ((c0 + (uint64_t)g) << log2ns) + t2 * n2;
+  uint64_t x[KB];
+  static_for<KB>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    x[t] = in[(uint64_t)m * sd_in + (base + (uint64_t)t * n1) * se_in];
+  });
+  L96 v[KB];
+  if constexpr (MODE == MODE_SCALE) {
+    static_for<KB>([&](auto T) {
+      constexpr int t = decltype(T)::value;
+      v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw0, 0, l, m);
+    });
+  } else {
+    v[0] = l96(x[0]);
+    if (a == 0) {
+      static_for<KB - 1>([&](auto T) {
+        constexpr int t = decltype(T)::value + 1;
+        v[t] = l96(x[t]);
+      });
+    } else {
+      const int shift = log2n - log2ns - LOGKB;
+      static_for<KB - 1>([&](auto T) {
+        constexpr int t = decltype(T)::value + 1;
+        const uint64_t e = a * (uint64_t)t;
+        const int rho = (int)(e >> log2ns);
+        const uint64_t cc = e & (ns - 1);
+        const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
+        v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw0 + (cc << shift) * TwLayout<KD>::WORDS, rot, l, m);
+      });
+    }
+  }
+  dft_base<KD, INV>(v, m);
+  static_for<KB>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    lds[g * SG::BLK + t * SG::ROW + wv * KD + m] = seminorm<KD, W, U>(v[t], m);
+  });
+  __syncthreads();
+
+  // ---- pass s+1: t1 = wv for the whole wavefront, group g = block g, slots t2
+  const uint64_t t1 = (uint64_t)wv;
+  static_for<KB>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    x[t] = lds[g * SG::BLK + wv * SG::ROW + t * KD + m];
+  });
+  const int log2ns1 = log2ns + LOGKB;
+  const uint64_t ns1 = ns << LOGKB;
+  const uint64_t a1 = a + (t1 << log2ns);  // uniform over the wavefront
+  v[0] = l96(x[0]);
+  if (a1 == 0) {
+    static_for<KB - 1>([&](auto T) {
+      constexpr int t = decltype(T)::value + 1;
+      v[t] = l96(x[t]);
+    });
+  } else {
+    const int shift1 = log2n - log2ns1 - LOGKB;
+    static_for<KB - 1>([&](auto T) {
+      constexpr int t = decltype(T)::value + 1;
+      const uint64_t e = a1 * (uint64_t)t;
+      const int rho = (int)(e >> log2ns1);
+      const uint64_t cc = e & (ns1 - 1);
+      const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
+      v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw1 + (cc << shift1) * TwLayout<KD>::WORDS, rot, l, m);
+    });
+  }
+  dft_base<KD, INV>(v, m);
+  const uint64_t obase = a + (t1 << log2ns) + ((c0 + (uint64_t)g) << (log2ns + 2 * LOGKB));
+  static_for<KB>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    uint64_t d;
+    if constexpr (LAST) {
+      d = canonicalize<KD, W, U>(v[t], l, m);
+    } else {
+      d = seminorm<KD, W, U>(v[t], m);
+    }
+    out[(uint64_t)m * sd_out + (obase + (uint64_t)t * ns1) * se_out] = d;
+  });
+}
+
+// ---------------------------------------------------------------------------
 // elementwise operations (one element per k lanes)
 // ---------------------------------------------------------------------------
 template <int KD, int W, int U, int OP>
@@ -175,7 +428,52 @@ inline unsigned blocks_for(uint64_t groups, int G) {
 }
 
 template <int KD, int W, int U>
+hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
+  if constexpr (KD != 8) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int LOGKB = ilog2(2 * KD);
+    if (p.log2n < 2 * LOGKB || p.log2ns + 2 * LOGKB > p.log2n) return hipErrorInvalidValue;
+    if (p.wide) {
+      // 8 blocks per workgroup: both halves with uniform twiddles
+      if (p.log2n - 2 * LOGKB - p.log2ns < 3) return hipErrorInvalidValue;
+      const uint64_t wgs = p.nvec << (p.log2n - 2 * LOGKB - 3);
+#define GFP_LAUNCH2U(INV, MODE, LAST)                                                                        \
+  hipLaunchKernelGGL((k_pass2u<KD, W, U, INV, MODE, LAST>), dim3((unsigned)wgs), dim3(Span2UGeo<KD>::THREADS), 0, st, \
+                     p.in, p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.log2n, p.log2ns, p.nvec,     \
+                     p.vin, p.vout)
+      if (p.scale) {
+        if (p.last) GFP_LAUNCH2U(true, MODE_SCALE, true); else GFP_LAUNCH2U(true, MODE_SCALE, false);
+      } else if (p.inverse) {
+        if (p.last) GFP_LAUNCH2U(true, MODE_PLAIN, true); else GFP_LAUNCH2U(true, MODE_PLAIN, false);
+      } else {
+        if (p.last) GFP_LAUNCH2U(false, MODE_PLAIN, true); else GFP_LAUNCH2U(false, MODE_PLAIN, false);
+      }
+#undef GFP_LAUNCH2U
+      return hipGetLastError();
+    }
+    const uint64_t blocks = (p.nvec << (p.log2n - 2 * LOGKB));
+    const unsigned nb = (unsigned)((blocks + Span2Geo<KD>::BPW - 1) / Span2Geo<KD>::BPW);
+    if (nb == 0) return hipSuccess;
+#define GFP_LAUNCH2(INV, MODE, LAST)                                                                                 \
+  hipLaunchKernelGGL((k_pass2<KD, W, U, INV, MODE, LAST>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, p.out, \
+                     p.se_out, p.sd_out, p.tw, p.tw1, p.log2n, p.log2ns, p.nvec, p.vin, p.vout)
+    if (p.scale) {
+      if (p.last) GFP_LAUNCH2(true, MODE_SCALE, true); else GFP_LAUNCH2(true, MODE_SCALE, false);
+    } else if (p.inverse) {
+      if (p.last) GFP_LAUNCH2(true, MODE_PLAIN, true); else GFP_LAUNCH2(true, MODE_PLAIN, false);
+    } else {
+      if (p.last) GFP_LAUNCH2(false, MODE_PLAIN, true); else GFP_LAUNCH2(false, MODE_PLAIN, false);
+    }
+#undef GFP_LAUNCH2
+    return hipGetLastError();
+  }
+}
+
+template <int KD, int W, int U>
 hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
+  if (p.span == 2) return launch_pass2_t<KD, W, U>(p, st);
+  if (p.span != 1) return hipErrorInvalidValue;
   const unsigned nb = blocks_for(p.ngroups * p.nvec, Geo<KD>::G);
   if (nb == 0) return hipSuccess;
 #define GFP_LAUNCH(INV, MODE, LAST, UNIF)                                                                           \

@@ -30,6 +30,7 @@ GFP_EPENDING = 8
 
 OP_ADD, OP_SUB, OP_MUL, OP_MUL_POW_R, OP_MUL_CONST, OP_MUL_SCALE = range(6)
 BATCH_GRAPH = 1
+LAYOUT_DIGIT_MAJOR, LAYOUT_ELEMENT_MAJOR = 0, 1
 
 
 class PolymulDesc(ctypes.Structure):
@@ -96,6 +97,9 @@ SIGNATURES = {
     "gfp_polymul_batched_workspace_size": (_int, [_vp, _u32, _vp, ctypes.POINTER(_u64)]),
     "gfp_polymul_batched": (_int, [_vp, _u32, _vp, _vp, _u64, _int, _vp]),
     "gfp_elementwise": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _u64, _i64, _pu64, _vp]),
+    "gfp_plan_get": (_int, [_vp, _u64, _u64, _int, ctypes.c_char_p, _u32]),
+    "gfp_plan_set": (_int, [_vp, _u64, _u64, _int, ctypes.c_char_p]),
+    "gfp_tune": (_int, [_vp, _u64, _u64, _int, _vp, ctypes.c_char_p, _u32, ctypes.POINTER(ctypes.c_double)]),
     "gfp_server_create": (_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]),
     "gfp_server_submit": (_int, [_vp, ctypes.POINTER(Request), ctypes.POINTER(_u64)]),
     "gfp_server_poll": (_int, [_vp, _u64, ctypes.POINTER(Result)]),
@@ -271,6 +275,23 @@ class Field:
             if workspace is not None else (None, 0)
         _check(lib().gfp_polymul_batched(self._h, len(descs), descs, wp, wb, BATCH_GRAPH if graph else 0,
                                          _stream(stream)), "gfp_polymul_batched")
+
+    def plan(self, n: int, nvec: int = 1, layout: int = LAYOUT_DIGIT_MAJOR) -> str:
+        """Stage grouping used for nvec transforms of size n, e.g. '1211'."""
+        buf = ctypes.create_string_buffer(32)
+        _check(lib().gfp_plan_get(self._h, n, nvec, layout, buf, 32), "gfp_plan_get")
+        return buf.value.decode()
+
+    def set_plan(self, n: int, plan, nvec: int = 1, layout: int = LAYOUT_DIGIT_MAJOR):
+        """Set (or with None / '' reset) the stage grouping for (n, batch class, layout)."""
+        _check(lib().gfp_plan_set(self._h, n, nvec, layout, plan.encode() if plan else None), "gfp_plan_set")
+
+    def tune(self, n: int, nvec: int = 1, layout: int = LAYOUT_DIGIT_MAJOR, stream=None):
+        """Autotune the stage grouping for (n, batch class, layout); returns (plan, us)."""
+        buf = ctypes.create_string_buffer(32)
+        us = ctypes.c_double()
+        _check(lib().gfp_tune(self._h, n, nvec, layout, _stream(stream), buf, 32, ctypes.byref(us)), "gfp_tune")
+        return buf.value.decode(), us.value
 
     def elementwise(self, op, x, y=None, z=None, n=None, s=0, c=None, stream=None):
         n = x.shape[1] if n is None else n

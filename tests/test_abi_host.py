@@ -138,3 +138,33 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert int(got["%s.%s" % (cname, fname)]) == getattr(py, fname).offset, (cname, fname)
+
+
+def test_plan_strings():
+    """Plan bookkeeping is host-only: defaults, per batch class and layout,
+    validation."""
+    _lib()
+    f = gfp.Field(**P8)
+    em = gfp.LAYOUT_ELEMENT_MAJOR
+    assert f.plan(2 ** 20) == "w21" and f.plan(2 ** 20, layout=em) == "w12"
+    assert f.plan(4096) == "12" and f.plan(256) == "2" and f.plan(16) == "1"
+    f.set_plan(4096, "21", nvec=8)
+    assert f.plan(4096, nvec=8) == "21" and f.plan(4096, nvec=63) == "21"
+    assert f.plan(4096) == "12" and f.plan(4096, nvec=64) == "12" and f.plan(4096, nvec=8, layout=em) == "12"
+    f.set_plan(4096, "w1", layout=em)  # wide pair at s = 0: 2^12 / (256 * 1) >= 8 blocks
+    assert f.plan(4096, layout=em) == "w1"
+    for bad in ("3", "22", "1", "1a1", "0111", "1w", "W1"):
+        with pytest.raises(gfp.GFPError) as e:
+            f.set_plan(4096, bad)
+        assert e.value.code == gfp.GFP_EINVAL
+    f.set_plan(4096, None, nvec=8)
+    assert f.plan(4096, nvec=8) == "12"
+    assert f.plan(2 ** 20, layout=em) == "w12"
+    f.set_plan(2 ** 20, "1w11")
+    assert f.plan(2 ** 20) == "1w11"
+    with pytest.raises(gfp.GFPError):
+        f.set_plan(2 ** 20, "111w")  # the last pair has one block per twiddle base
+    g = gfp.Field(**P16)
+    assert g.plan(2 ** 20) == "1111"
+    with pytest.raises(gfp.GFPError):
+        g.set_plan(32768, "21")
