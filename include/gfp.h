@@ -110,6 +110,8 @@ int gfp_fft_inverse(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t 
  * v[i * k + d] (ld ignored), the layout the transforms use between passes. */
 #define GFP_PASS_IN_ELEMENT_MAJOR 1
 #define GFP_PASS_OUT_ELEMENT_MAJOR 2
+#define GFP_PASS_PAIR 4 /* passes s and s+1 in one launch, as plan character '2' */
+#define GFP_PASS_WIDE 8 /* passes s and s+1 in one launch, as plan character 'w' */
 
 /* One radix-K pass (stage s, 0 <= s < e) of the transform schedule used by
  * gfp_fft_forward / gfp_fft_inverse: for every j < n/K the K elements
@@ -123,7 +125,10 @@ int gfp_fft_inverse(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t 
  * canonical encoding.  x and y must not overlap.  flags: GFP_PASS_* layout
  * bits (0 = both digit-major).  gfp_fft_forward runs pass 0 digit-major to
  * element-major, the middle passes element-major, the last pass
- * element-major to digit-major.  For instrumentation and custom schedules. */
+ * element-major to digit-major.  With GFP_PASS_PAIR or GFP_PASS_WIDE the
+ * launch runs passes s and s+1 (s + 1 < e, k = 8; for WIDE also
+ * n / (K^2 K^s) >= 8), exactly as that character of a plan does.  For
+ * instrumentation and custom schedules. */
 int gfp_fft_pass(const gfp_field* f, uint64_t n, int s, int inverse, int flags, const uint64_t* x, uint64_t ld_x,
                  uint64_t* y, uint64_t ld_y, void* stream);
 

@@ -705,14 +705,18 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   int log2n, e;
   int rc = check_size(f, n, &log2n, &e);
   if (rc != GFP_OK) return rc;
-  if (s < 0 || s >= e || (flags & ~3)) return GFP_EINVAL;
+  if (s < 0 || s >= e || (flags & ~15)) return GFP_EINVAL;
+  const bool wide = (flags & GFP_PASS_WIDE) != 0;
+  const int span = (wide || (flags & GFP_PASS_PAIR)) ? 2 : 1;
+  const int lk = log2_exact(2ull * f->k);
+  if (span == 2 && (s + 1 >= e || !gfpk::span2_supported((int)f->k))) return GFP_EINVAL;
+  if (wide && log2n - 2 * lk - s * lk < 3) return GFP_EINVAL;
   const bool in_em = (flags & GFP_PASS_IN_ELEMENT_MAJOR) != 0;
   const bool out_em = (flags & GFP_PASS_OUT_ELEMENT_MAJOR) != 0;
   if ((!in_em && ld_x < n) || (!out_em && ld_y < n)) return GFP_EINVAL;
   const DevTables* t = nullptr;
   rc = get_tables(f, n, &t);
   if (rc != GFP_OK) return rc;
-  const int lk = log2_exact(2ull * f->k);
   gfpk::PassArgs p;
   p.in = x;
   p.se_in = in_em ? f->k : 1;
@@ -726,7 +730,10 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   p.inverse = inverse != 0;
   p.scale = p.inverse && s == 0;
   p.tw = p.scale ? t->ninv : (p.inverse ? t->inv : t->fwd);
-  p.last = (s == e - 1);
+  p.tw1 = p.inverse ? t->inv : t->fwd;
+  p.span = span;
+  p.wide = wide;
+  p.last = (s + span - 1 == e - 1);
   return hip_status(gfpk::launch_pass((int)f->k, f->w, f->u, p, (hipStream_t)stream));
 }
 

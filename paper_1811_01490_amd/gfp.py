@@ -223,8 +223,11 @@ class Field:
         n = x.shape[1] if n is None else n
         return self._transform(lib().gfp_fft_inverse, "gfp_fft_inverse", x, n, y, workspace, stream)
 
-    def fft_pass(self, s, x, y, n, inverse=False, in_element_major=False, out_element_major=False, stream=None):
-        """One pass; element-major tensors are flat (n * k,) int64 device tensors."""
+    def fft_pass(self, s, x, y, n, inverse=False, in_element_major=False, out_element_major=False, stream=None,
+                 code="1"):
+        """One launch of a plan starting at pass s: code '1' (one pass), '2'
+        or 'w' (passes s and s+1 fused); element-major tensors are flat
+        (n * k,) int64 device tensors."""
         def ptr(t, em, name):
             if em:
                 if not t.is_cuda or t.numel() < n * self.k:
@@ -233,7 +236,7 @@ class Field:
             return _vec(t, self.k, n, name)
         px, ldx = ptr(x, in_element_major, "x")
         py, ldy = ptr(y, out_element_major, "y")
-        flags = (1 if in_element_major else 0) | (2 if out_element_major else 0)
+        flags = (1 if in_element_major else 0) | (2 if out_element_major else 0) | {"1": 0, "2": 4, "w": 8}[code]
         _check(lib().gfp_fft_pass(self._h, n, s, int(inverse), flags, px, ldx, py, ldy, _stream(stream)),
                "gfp_fft_pass")
         return y
