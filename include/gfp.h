@@ -6,8 +6,9 @@
  * Practice with the BPAS Library"):
  *   - the field and the radix-r element encoding: section 2;
  *   - the primitive N-th root w with w^(N/2k) = r: section 2.1, Alg. 1;
- *   - the DFT at w, computed for N = K^e, K = 2k, with base case DFT_K at
- *     w^(N/K) = r: section 1.1 (eq. CTCT), section 4.1 (eq. sixstepfft),
+ *   - the DFT at w, computed for N = R K^e, K = 2k, R = 2^j < K, with base
+ *     case DFT_K at w^(N/K) = r and one DFT_R at w^(N/R) = r^(K/R): section
+ *     1.1 (eq. CTCT), section 4.1 (eq. sixstepfft; any power of two N),
  *     section 4.3 (Alg. DFT_general);
  *   - the inverse transform (1/N) DFT at w^-1 and the product of two
  *     polynomials by forward transforms, a pointwise product and an inverse
@@ -89,7 +90,9 @@ int gfp_field_info(const gfp_field* f, uint32_t* k, uint64_t* r, uint32_t* log2_
  * of k uint64_t, canonical encoding.  Host-only. */
 int gfp_root_of_unity(const gfp_field* f, uint64_t n, int inverse, uint64_t* digits);
 
-/* Transform sizes: n = K^e, K = 2k, e >= 1, n <= 2^log2_max_n and n <= 2^25.
+/* Transform sizes: n a power of two, K = 2k <= n <= 2^log2_max_n and
+ * n <= 2^25.  n = R K^e with R = 2^j < K runs a radix-R pass (DFT_R at
+ * r^(K/R), no twiddles) before the e radix-K passes.
  * Workspace bytes needed by gfp_fft_forward / gfp_fft_inverse of size n. */
 int gfp_fft_workspace_size(const gfp_field* f, uint64_t n, uint64_t* bytes);
 
@@ -113,27 +116,31 @@ int gfp_fft_inverse(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t 
 #define GFP_PASS_PAIR 4 /* passes s and s+1 in one launch, as plan character '2' */
 #define GFP_PASS_WIDE 8 /* passes s and s+1 in one launch, as plan character 'w' */
 
-/* One radix-K pass (stage s, 0 <= s < e) of the transform schedule used by
- * gfp_fft_forward / gfp_fft_inverse: for every j < n/K the K elements
- * x[j + t n/K] are multiplied by the twiddles w_L^(a t) (L = K^(s+1),
- * a = j mod K^s; for the inverse: the conjugate twiddles, and at s = 0 the
- * factor 1/n), transformed by DFT_K at r (r^-1) and written to
- * y[(j - a) K + a + t K^s] (section 1.1, eq. CTCT; section 4.1).  Running
- * s = 0..e-1 with y of one pass as x of the next is the full transform.
- * Outputs of s < e-1 are not canonical: every digit is in [0, 2^64) and the
- * value is congruent mod p (the next pass accepts this); s = e-1 writes the
+/* One pass (stage s) of the transform schedule used by gfp_fft_forward /
+ * gfp_fft_inverse, n = R K^e.  The stages are s = 0..S-1 with S = e + 1 when
+ * R > 1 (stage 0 is then the radix-R pass) and S = e otherwise.  A radix-K
+ * stage with Ns = R K^(s') (s' its index among the radix-K stages): for
+ * every j < n/K the K elements x[j + t n/K] are multiplied by the twiddles
+ * w_L^(a t) (L = K Ns, a = j mod Ns; for the inverse the conjugate
+ * twiddles), transformed by DFT_K at r (r^-1) and written to
+ * y[(j - a) K + a + t Ns] (section 1.1, eq. CTCT; section 4.1).  The radix-R
+ * stage does the same with K replaced by R, Ns = 1 and DFT_R at r^(K/R).
+ * Stage 0 of the inverse also multiplies by 1/n.  Running s = 0..S-1 with
+ * y of one pass as x of the next is the full transform.  Outputs of
+ * s < S-1 are not canonical: every digit is in [0, 2^64) and the value is
+ * congruent mod p (the next pass accepts this); s = S-1 writes the
  * canonical encoding.  x and y must not overlap.  flags: GFP_PASS_* layout
- * bits (0 = both digit-major).  gfp_fft_forward runs pass 0 digit-major to
- * element-major, the middle passes element-major, the last pass
+ * bits (0 = both digit-major).  gfp_fft_forward runs stage 0 digit-major to
+ * element-major, the middle stages element-major, the last stage
  * element-major to digit-major.  With GFP_PASS_PAIR or GFP_PASS_WIDE the
- * launch runs passes s and s+1 (s + 1 < e, k = 8; for WIDE also
- * n / (K^2 K^s) >= 8), exactly as that character of a plan does.  For
+ * launch runs radix-K stages s and s+1 (s + 1 < S, k = 8; for WIDE also
+ * n / (K^2 Ns) >= 8), exactly as that character of a plan does.  For
  * instrumentation and custom schedules. */
 int gfp_fft_pass(const gfp_field* f, uint64_t n, int s, int inverse, int flags, const uint64_t* x, uint64_t ld_x,
                  uint64_t* y, uint64_t ld_y, void* stream);
 
 /* Transform size used by gfp_polymul for la + lb - 1 output coefficients:
- * the smallest K^e >= la + lb - 1 (and >= K). */
+ * the smallest power of two >= la + lb - 1 (and >= K). */
 int gfp_polymul_size(const gfp_field* f, uint64_t la, uint64_t lb, uint64_t* n);
 
 /* Workspace bytes for gfp_polymul(la, lb). */
@@ -191,15 +198,17 @@ int gfp_elementwise(const gfp_field* f, int op, const uint64_t* x, uint64_t ld_x
 
 /* ---- Stage groupings and the autotuner -------------------------------------
  *
- * A transform of size n = K^e runs as a sequence of launches, each covering
+ * A transform of size n = R K^e runs as a sequence of launches: the radix-R
+ * pass alone (when R > 1), then the e radix-K passes, each launch covering
  * one radix-K pass or (k = 8) two consecutive passes fused in one launch,
  * with the stride permutation between them (section 4.1, eq. sixstepfft)
  * staged through LDS so the intermediate never goes to HBM.  A plan is a
  * string with one character per launch: '1' one pass, '2' two fused passes
  * (two K^2-element blocks per workgroup; the second pass reads its twiddles
  * per element group), 'w' two fused passes over eight blocks per workgroup
- * (wavefront-uniform twiddles in both passes; needs n / (K^2 K^s) >= 8 at
- * its first pass s).  Example: "1211" for e = 5.  Plans are kept per
+ * (wavefront-uniform twiddles in both passes; needs n / (K^2 R K^s) >= 8 at
+ * its first radix-K pass s).  The plan covers the radix-K passes only.
+ * Example: "1211" for e = 5.  Plans are kept per
  * (n, batch class, layout): the batch class is the number of same-size
  * transforms one launch covers (1, 2-7, 8-63, 64 and more: gfp_polymul runs
  * 2 forward and 1 inverse, gfp_polymul_batched 2C and C); the layout is that

@@ -135,28 +135,38 @@ __device__ __forceinline__ void bfly(L96& a, L96& b, int m) {
   }
 }
 
-template <int KD, bool INV>
-__device__ __forceinline__ void dft_base(L96 (&v)[2 * KD], int m) {
+// DFT_P, P = 2^LP <= K, at root r^(K/P) (a primitive P-th root of unity,
+// since r has order K = 2k): the first LP levels of the same network.  At
+// level half-size H the butterfly j uses (r^(K/P))^(j P/(2H)) = r^(j K/(2H)),
+// the exponent DFT_K uses at that level.
+template <int KD, bool INV, int LP>
+__device__ __forceinline__ void dft_pow2(L96 (&v)[1 << LP], int m) {
   constexpr int KB = 2 * KD;
-  constexpr int LG = ilog2(KB);
-  L96 a[KB];
-  static_for<KB>([&](auto I) {
+  constexpr int P = 1 << LP;
+  static_assert(P >= 2 && P <= KB, "DFT size");
+  L96 a[P];
+  static_for<P>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    a[i] = v[brev(i, LG)];
+    a[i] = v[brev(i, LP)];
   });
-  static_for<LG>([&](auto S) {
+  static_for<LP>([&](auto S) {
     constexpr int H = 1 << decltype(S)::value;  // half size of this level
-    static_for<KB / 2>([&](auto B) {
+    static_for<P / 2>([&](auto B) {
       constexpr int blk = decltype(B)::value / H, j = decltype(B)::value % H;
       constexpr int i0 = blk * 2 * H + j;
       constexpr int e = j * (KB / (2 * H));  // exponent of r, 0 <= e < KD
       bfly<KD, INV, e>(a[i0], a[i0 + H], m);
     });
   });
-  static_for<KB>([&](auto I) {
+  static_for<P>([&](auto I) {
     constexpr int i = decltype(I)::value;
     v[i] = a[i];
   });
+}
+
+template <int KD, bool INV>
+__device__ __forceinline__ void dft_base(L96 (&v)[2 * KD], int m) {
+  dft_pow2<KD, INV, ilog2(2 * KD)>(v, m);
 }
 
 // ------------------------------------------------------------------------

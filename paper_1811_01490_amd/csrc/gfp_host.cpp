@@ -177,10 +177,12 @@ int upload(const std::vector<uint32_t>& host, uint32_t** dev) {
 }
 
 // valid transform size: n = K^e, e >= 1, within the field and the build limit
+// n = R K^e with R = 2^(log2n - e log2 K) < K: *e radix-K passes, preceded
+// by one radix-R pass when R > 1.
 int check_size(const gfp_field* f, uint64_t n, int* log2n, int* e) {
   const int lg = log2_exact(n);
   const int lk = log2_exact(2ull * f->k);
-  if (lg < 0 || lg < lk || lg % lk != 0) return GFP_EUNSUPPORTED;
+  if (lg < 0 || lg < lk) return GFP_EUNSUPPORTED;
   if ((uint64_t)lg > f->log2max || (uint64_t)lg > kMaxLog2N) return GFP_EUNSUPPORTED;
   *log2n = lg;
   *e = lg / lk;
@@ -303,14 +305,16 @@ int code_passes(int c) { return c == LC_ONE ? 1 : 2; }
 char code_char(int c) { return c == LC_WIDE ? 'w' : (char)('0' + c); }
 int char_code(char c) { return c == '1' ? LC_ONE : c == '2' ? LC_PAIR : c == 'w' ? LC_WIDE : 0; }
 
+// The plan covers the e radix-K passes (after the radix-R pass, if any).
 bool plan_valid(const gfp_field* f, int log2n, int e, const std::vector<int>& plan) {
   const int lk = log2_exact(2ull * f->k);
+  const int lr = log2n - e * lk;
   int s = 0;
   for (int c : plan) {
     if (c < LC_ONE || c > LC_WIDE) return false;
     if (c != LC_ONE && !gfpk::span2_supported((int)f->k)) return false;
     if (s + code_passes(c) > e) return false;
-    if (c == LC_WIDE && log2n - 2 * lk - s * lk < 3) return false;  // 8 blocks per twiddle base
+    if (c == LC_WIDE && log2n - 2 * lk - lr - s * lk < 3) return false;  // 8 blocks per twiddle base
     s += code_passes(c);
   }
   return s == e;
@@ -325,14 +329,15 @@ std::string plan_text(const std::vector<int>& plan) {
 // Untuned choice (k = 8), the fastest plans measured on MI355X for one
 // transform (digit-major ends) and for the two forward transforms of a
 // product (element-major); k = 16 runs one pass per launch.
-std::vector<int> default_plan(const gfp_field* f, int e, int layout) {
+std::vector<int> default_plan(const gfp_field* f, int log2n, int e, int layout) {
   std::vector<int> plan;
   if (!gfpk::span2_supported((int)f->k)) return std::vector<int>(e, LC_ONE);
   static const char* dm[] = {"", "1", "2", "12", "121", "w21"};
   static const char* em[] = {"", "1", "2", "12", "22", "w12"};
   if (e <= 5) {
     for (const char* c = (layout == GFP_LAYOUT_ELEMENT_MAJOR ? em : dm)[e]; *c; ++c) plan.push_back(char_code(*c));
-    return plan;
+    if (plan_valid(f, log2n, e, plan)) return plan;
+    plan.clear();
   }
   int left = e;
   while (left > 0) {
@@ -347,7 +352,12 @@ std::vector<int> plan_for(gfp_field* f, int log2n, int e, uint64_t nvec, int lay
   std::lock_guard<std::mutex> g(f->mu);
   auto it = f->plans.find(std::make_tuple(log2n, batch_class(nvec), layout));
   if (it != f->plans.end()) return it->second;
-  return default_plan(f, e, layout);
+  return default_plan(f, log2n, e, layout);
+}
+
+// Launches of a transform: the radix-R pass (if any) and the plan's.
+size_t launch_count(const gfp_field* f, int log2n, int e, const std::vector<int>& plan) {
+  return plan.size() + (log2n != e * log2_exact(2ull * f->k) ? 1 : 0);
 }
 
 int view_layout(const VecView& X, const VecView& Y) {
@@ -363,10 +373,15 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
   if (rc != GFP_OK) return rc;
   if (!plan_valid(f, log2n, e, plan)) return GFP_EINVAL;
   const int lk = log2_exact(2ull * f->k);
-  const int nl = (int)plan.size();
+  const int lr = log2n - e * lk;  // radix-R pass first when lr > 0
+  // launch codes in order: 0 = the radix-R pass
+  std::vector<int> codes;
+  if (lr > 0) codes.push_back(0);
+  codes.insert(codes.end(), plan.begin(), plan.end());
+  const int nl = (int)codes.size();
   if (nl == 1 && X.p == Y.p) return GFP_EINVAL;  // a single launch cannot run in place
   VecView src = X;
-  int s = 0;
+  int s = 0;  // radix-K passes done
   for (int i = 0; i < nl; ++i) {
     VecView dst;
     if (i == nl - 1) {
@@ -385,22 +400,27 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
     p.se_out = dst.se;
     p.sd_out = dst.sd;
     p.log2n = log2n;
-    p.log2ns = s * lk;
     p.ngroups = n >> lk;
     p.inverse = inverse;
-    p.scale = inverse && s == 0;
+    p.scale = inverse && i == 0;
     p.tw = p.scale ? t->ninv : (inverse ? t->inv : t->fwd);
     p.tw1 = inverse ? t->inv : t->fwd;
-    p.span = code_passes(plan[i]);
-    p.wide = plan[i] == LC_WIDE;
     p.last = (i == nl - 1) && canonical;
     p.nvec = nvec;
     p.vin = src.vs;
     p.vout = dst.vs;
+    if (codes[i] == 0) {
+      p.log2ns = 0;
+      p.radix_log2 = lr;
+    } else {
+      p.log2ns = lr + s * lk;
+      p.span = code_passes(codes[i]);
+      p.wide = codes[i] == LC_WIDE;
+      s += p.span;
+    }
     hipError_t he = gfpk::launch_pass((int)f->k, f->w, f->u, p, st);
     if (he != hipSuccess) return hip_status(he);
     src = dst;
-    s += code_passes(plan[i]);
   }
   return GFP_OK;
 }
@@ -428,7 +448,7 @@ int transform_entry(const gfp_field* cf, uint64_t n, const uint64_t* x, uint64_t
   if (rc != GFP_OK) return rc;
   VecView X{x, 1, ldx, 0}, Y{y, 1, ldy, 0};
   const std::vector<int> plan = plan_for(f, log2n, e, 1, GFP_LAYOUT_DIGIT_MAJOR);
-  if (plan.size() == 1 && x == y) {
+  if (launch_count(f, log2n, e, plan) == 1 && x == y) {
     // one launch cannot run in place: transform into W2 (digit-major, ld n), copy back
     VecView T{w + n * f->k, 1, n, 0};
     rc = run_transform_plan(f, log2n, e, plan, inverse, X, T, 1, true, w, w, st);
@@ -705,12 +725,16 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   int log2n, e;
   int rc = check_size(f, n, &log2n, &e);
   if (rc != GFP_OK) return rc;
-  if (s < 0 || s >= e || (flags & ~15)) return GFP_EINVAL;
+  const int lk = log2_exact(2ull * f->k);
+  const int lr = log2n - e * lk;
+  const int total = e + (lr > 0 ? 1 : 0);  // passes: the radix-R one first, if any
+  if (s < 0 || s >= total || (flags & ~15)) return GFP_EINVAL;
+  const bool radix_r = lr > 0 && s == 0;
+  const int sk = s - (lr > 0 ? 1 : 0);  // index among the radix-K passes
   const bool wide = (flags & GFP_PASS_WIDE) != 0;
   const int span = (wide || (flags & GFP_PASS_PAIR)) ? 2 : 1;
-  const int lk = log2_exact(2ull * f->k);
-  if (span == 2 && (s + 1 >= e || !gfpk::span2_supported((int)f->k))) return GFP_EINVAL;
-  if (wide && log2n - 2 * lk - s * lk < 3) return GFP_EINVAL;
+  if (span == 2 && (radix_r || s + 1 >= total || !gfpk::span2_supported((int)f->k))) return GFP_EINVAL;
+  if (wide && log2n - 2 * lk - lr - sk * lk < 3) return GFP_EINVAL;
   const bool in_em = (flags & GFP_PASS_IN_ELEMENT_MAJOR) != 0;
   const bool out_em = (flags & GFP_PASS_OUT_ELEMENT_MAJOR) != 0;
   if ((!in_em && ld_x < n) || (!out_em && ld_y < n)) return GFP_EINVAL;
@@ -725,7 +749,8 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   p.se_out = out_em ? f->k : 1;
   p.sd_out = out_em ? 1 : ld_y;
   p.log2n = log2n;
-  p.log2ns = s * lk;
+  p.log2ns = radix_r ? 0 : lr + sk * lk;
+  p.radix_log2 = radix_r ? lr : 0;
   p.ngroups = n >> lk;
   p.inverse = inverse != 0;
   p.scale = p.inverse && s == 0;
@@ -733,7 +758,7 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   p.tw1 = p.inverse ? t->inv : t->fwd;
   p.span = span;
   p.wide = wide;
-  p.last = (s + span - 1 == e - 1);
+  p.last = (s + span - 1 == total - 1);
   return hip_status(gfpk::launch_pass((int)f->k, f->w, f->u, p, (hipStream_t)stream));
 }
 
@@ -743,7 +768,7 @@ int gfp_polymul_size(const gfp_field* f, uint64_t la, uint64_t lb, uint64_t* n) 
   uint64_t N = 2ull * f->k;
   while (N < need) {
     if (N > (1ull << kMaxLog2N)) return GFP_EUNSUPPORTED;
-    N *= 2ull * f->k;
+    N *= 2;
   }
   int log2n, e;
   int rc = check_size(f, N, &log2n, &e);

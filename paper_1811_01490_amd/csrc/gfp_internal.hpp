@@ -31,6 +31,9 @@ struct PassArgs {
   // stride permutation between them staged in LDS; tw1 is the table of the
   // second pass (tw the first pass's, or its scale entry), `last` applies
   // to the second pass.
+  // radix_log2 > 0: the radix-R first pass (R = 2^radix_log2 < K, Ns = 1)
+  // of a transform of size R K^e; span, wide and tw1 are then unused
+  int radix_log2 = 0;
   int span = 1;
   bool wide = false;  // span 2 over 8 blocks per workgroup (needs N / (K^2 Ns) >= 8)
   const uint32_t* tw1 = nullptr;

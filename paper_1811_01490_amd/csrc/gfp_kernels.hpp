@@ -127,6 +127,50 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
 }
 
 // ---------------------------------------------------------------------------
+// first pass of a transform of size N = R K^e, 1 < R = 2^LR < K
+// ---------------------------------------------------------------------------
+// Radix R with Ns = 1 (no twiddles): for every j < N/R the R elements
+// x[j + t N/R] go through DFT_R at w^(N/R) = r^(K/R) and land at j R + t.
+// The radix-K passes that follow run with Ns = R K^s (section 4.1: any
+// factorisation N = N1 N2 with the base case at powers of r).  MODE_SCALE
+// multiplies every element by the 1/N entry first (inverse transform).
+template <int KD, int W, int U, bool INV, int MODE, int LR>
+__global__ __launch_bounds__(256) void k_pass_r(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
+                                                uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
+                                                const uint32_t* __restrict__ tw, int log2n, uint64_t nvec,
+                                                uint64_t vin, uint64_t vout) {
+  typedef Geo<KD> Gm;
+  constexpr int R = 1 << LR;
+  const int l = Gm::lane();
+  const int m = Gm::digit(l);
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const uint64_t J = wave * Gm::G + Gm::group(l);
+  const int log2nr = log2n - LR;  // groups per vector
+  uint64_t vec = J >> log2nr;
+  const bool active = vec < nvec;
+  const uint64_t j = active ? (J & ((1ull << log2nr) - 1)) : 0;
+  if (!active) vec = 0;
+  in += vec * vin;
+  out += vec * vout;
+  L96 v[R];
+  static_for<R>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    const uint64_t x = in[(uint64_t)m * sd_in + (j + ((uint64_t)t << log2nr)) * se_in];
+    if constexpr (MODE == MODE_SCALE) {
+      v[t] = mul_twiddle<KD, W, U>(x, tw, 0, l, m);
+    } else {
+      v[t] = l96(x);
+    }
+  });
+  dft_pow2<KD, INV, LR>(v, m);
+  static_for<R>([&](auto T) {
+    constexpr int t = decltype(T)::value;
+    const uint64_t d = seminorm<KD, W, U>(v[t], m);
+    if (active) out[(uint64_t)m * sd_out + (j * R + t) * se_out] = d;
+  });
+}
+
+// ---------------------------------------------------------------------------
 // two radix-K passes s, s+1 in one launch (a stage group of two)
 // ---------------------------------------------------------------------------
 // Block q of a vector (q < N/K^2): a = q mod Ns, c = q / Ns.  Its K^2
@@ -470,8 +514,37 @@ hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
   }
 }
 
+template <int KD, int W, int U, int LR>
+hipError_t launch_pass_r_lr(const PassArgs& p, hipStream_t st) {
+  const unsigned nb = blocks_for(p.nvec << (p.log2n - LR), Geo<KD>::G);
+  if (nb == 0) return hipSuccess;
+#define GFP_LAUNCH_R(INV, MODE)                                                                                 \
+  hipLaunchKernelGGL((k_pass_r<KD, W, U, INV, MODE, LR>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, p.out, \
+                     p.se_out, p.sd_out, p.tw, p.log2n, p.nvec, p.vin, p.vout)
+  if (p.scale) GFP_LAUNCH_R(true, MODE_SCALE);
+  else if (p.inverse) GFP_LAUNCH_R(true, MODE_PLAIN);
+  else GFP_LAUNCH_R(false, MODE_PLAIN);
+#undef GFP_LAUNCH_R
+  return hipGetLastError();
+}
+
+template <int KD, int W, int U>
+hipError_t launch_pass_r_t(const PassArgs& p, hipStream_t st) {
+  if (p.log2ns != 0 || p.last || p.log2n < p.radix_log2 + ilog2(2 * KD)) return hipErrorInvalidValue;
+  switch (p.radix_log2) {
+    case 1: return launch_pass_r_lr<KD, W, U, 1>(p, st);
+    case 2: return launch_pass_r_lr<KD, W, U, 2>(p, st);
+    case 3: return launch_pass_r_lr<KD, W, U, 3>(p, st);
+    case 4:
+      if constexpr (KD >= 16) return launch_pass_r_lr<KD, W, U, 4>(p, st);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int KD, int W, int U>
 hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
+  if (p.radix_log2 != 0) return launch_pass_r_t<KD, W, U>(p, st);
   if (p.span == 2) return launch_pass2_t<KD, W, U>(p, st);
   if (p.span != 1) return hipErrorInvalidValue;
   const unsigned nb = blocks_for(p.ngroups * p.nvec, Geo<KD>::G);

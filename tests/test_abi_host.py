@@ -71,14 +71,16 @@ def test_error_codes():
     L.gfp_field_destroy(h)
     f = gfp.Field(**P8)
     b = ctypes.c_uint64()
-    for bad_n in (0, 8, 32, 100, 2 ** 26):
+    for bad_n in (0, 8, 24, 100, 2 ** 26):  # not a power of two, below K = 16, above 2^25
         assert L.gfp_fft_workspace_size(f.handle, bad_n, ctypes.byref(b)) in (gfp.GFP_EUNSUPPORTED, gfp.GFP_EINVAL)
-    assert L.gfp_fft_workspace_size(f.handle, 4096, ctypes.byref(b)) == gfp.GFP_OK
-    assert b.value == 2 * 4096 * 8 * 8
+    for n in (16, 32, 4096, 2 ** 13, 2 ** 25):  # any power of two from K on
+        assert L.gfp_fft_workspace_size(f.handle, n, ctypes.byref(b)) == gfp.GFP_OK
+        assert b.value == 2 * n * 8 * 8
     assert f.polymul_size(2048, 2048) == 4096
     assert f.polymul_size(1, 1) == 16
-    assert f.polymul_size(2 ** 19, 2 ** 19) == 2 ** 20
-    assert f.polymul_size(9, 9) == 256 and f.polymul_size(8, 9) == 16
+    assert f.polymul_size(9, 9) == 32 and f.polymul_size(1000, 1000) == 2048
+    assert f.polymul_size(2 ** 19, 2 ** 19) == 2 ** 20 and f.polymul_size(2 ** 18, 2 ** 18) == 2 ** 19
+    assert f.polymul_size(2 ** 18 + 2, 2 ** 18) == 2 ** 20 and f.polymul_size(8, 9) == 16
     # null / short-ld arguments are rejected before any device work
     assert L.gfp_fft_forward(f.handle, 4096, None, 4096, ctypes.c_void_p(8), 4096, None, 0, None) == gfp.GFP_EINVAL
     assert L.gfp_fft_forward(f.handle, 4096, ctypes.c_void_p(8), 4000, ctypes.c_void_p(8), 4096, None, 0, None) == gfp.GFP_EINVAL
@@ -162,6 +164,11 @@ def test_plan_strings():
     assert f.plan(2 ** 20, layout=em) == "w12"
     f.set_plan(2 ** 20, "1w11")
     assert f.plan(2 ** 20) == "1w11"
+    # n = R K^e: the plan covers the e radix-K passes after the radix-R pass
+    assert f.plan(2 ** 13) == "12" and f.plan(32) == "1" and f.plan(2 ** 19) == "121"
+    f.set_plan(2 ** 13, "w1")  # 2^13 / (256 * 2) = 16 blocks per base
+    with pytest.raises(gfp.GFPError):
+        f.set_plan(2 ** 13, "1w")
     with pytest.raises(gfp.GFPError):
         f.set_plan(2 ** 20, "111w")  # the last pair has one block per twiddle base
     g = gfp.Field(**P16)

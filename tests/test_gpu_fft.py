@@ -33,8 +33,12 @@ def _field(name):
     return GFPField(**params), Field(params["k"], params["r"])
 
 
+# N = K^e, and N = R K^e (a radix-R pass first, R = 2, 4, 8, 16 < K)
 CASES = [("k8", 16), ("k8", 256), ("k8", 4096), ("k16", 32), ("k16", 1024),
-         ("k8t", 256), ("k8t", 4096), ("k16t", 1024)]
+         ("k8t", 256), ("k8t", 4096), ("k16t", 1024),
+         ("k8", 32), ("k8", 64), ("k8", 128), ("k8", 512), ("k8", 2048), ("k8", 8192),
+         ("k16", 64), ("k16", 128), ("k16", 256), ("k16", 512), ("k16", 2048), ("k16", 16384),
+         ("k8t", 128), ("k16t", 256)]
 
 
 @pytest.mark.parametrize("name,N", CASES)
@@ -88,7 +92,7 @@ def test_in_place_and_padded_ld(torch_mod):
 
     F, f = _field("k8")
     k, r = F.k, F.r
-    for N in (16, 256, 4096):  # e = 1 (copy-back path), 2, 3
+    for N in (16, 32, 256, 4096, 8192):  # one launch (copy-back path), radix-2 + one pass, ...
         x = gi.operand(k, r, N, gi.BASE_SEED + 5, 0, edge_frac=0.02)
         want = to_host(f.fft_forward(to_device(x)))
         buf = to_device(x)
@@ -109,7 +113,8 @@ def test_in_place_and_padded_ld(torch_mod):
         assert np.array_equal(o2, want)
 
 
-@pytest.mark.parametrize("name,N", [("k8", 65536), ("k16", 32768)])
+@pytest.mark.parametrize("name,N", [("k8", 65536), ("k16", 32768), ("k8", 2 ** 17), ("k8", 2 ** 19),
+                                    ("k16", 2 ** 19), ("k16", 2 ** 16)])
 def test_round_trip_mid(torch_mod, name, N):
     from paper_1811_01490_amd import to_device, to_host
 
@@ -119,14 +124,13 @@ def test_round_trip_mid(torch_mod, name, N):
     assert np.array_equal(back, x)
 
 
-@pytest.mark.parametrize("name", ["k8", "k16"])
-def test_full_size_sampled(torch_mod, name):
-    """N = 2^20 (16^5 for k = 8, 32^4 for k = 16): sampled outputs by Horner,
-    round trip exact."""
+@pytest.mark.parametrize("name,N", [("k8", 2 ** 20), ("k16", 2 ** 20), ("k8", 2 ** 19)])
+def test_full_size_sampled(torch_mod, name, N):
+    """N = 2^20 (16^5 for k = 8, 32^4 for k = 16) and 2^19 = 8 16^4: sampled
+    outputs by Horner, round trip exact."""
     from paper_1811_01490_amd import to_device, to_host
 
     F, f = _field(name)
-    N = 2 ** 20
     seed = gi.BASE_SEED + (1 if name == "k8" else 2)
     x = gi.operand(F.k, F.r, N, seed, 0, edge_frac=0.001)
     dx = to_device(x)

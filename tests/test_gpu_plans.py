@@ -35,19 +35,36 @@ def compositions(e, log2n=None, s=0):
     return out
 
 
-@pytest.mark.parametrize("N", [256, 4096])
+def compositions_n(N, lk=4):
+    """Plans for size N = R K^e (k = 8): the radix-R pass is implicit, the
+    plan covers the e radix-K passes starting at Ns = R."""
+    lg = N.bit_length() - 1
+    return compositions(lg // lk, lg - (lg % lk), 0) if lg % lk == 0 else \
+        [p for p in compositions(lg // lk, lg - (lg % lk), 0) if _wide_ok(p, lg, lg % lk)]
+
+
+def _wide_ok(plan, lg, lr):
+    s = 0
+    for c in plan:
+        if c == "w" and lg - 8 - lr - 4 * s < 3:
+            return False
+        s += 1 if c == "1" else 2
+    return True
+
+
+@pytest.mark.parametrize("N", [256, 4096, 512, 8192])
 def test_every_plan_matches_oracle(torch_mod, N):
     from paper_1811_01490_amd import Field, to_device, to_host
 
     F = GFPField(**P8)
     f = Field(**P8)
-    e = {256: 2, 4096: 3}[N]
+    e = (N.bit_length() - 1) // 4
     x = gi.operand(F.k, F.r, N, gi.BASE_SEED + 700 + N, 0, edge_frac=0.03)
     y = gi.operand(F.k, F.r, N, gi.BASE_SEED + 700 + N, 1, edge_frac=0.03)
     w = F.paper_root_of_unity(N)
     want_f = T.dft(to_ints(x, F.r), w, F.p) if N <= 256 else T.ntt(to_ints(x, F.r), w, F.p)
     want_i = T.idft(to_ints(y, F.r), w, F.p) if N <= 256 else T.intt(to_ints(y, F.r), w, F.p)
-    for plan in compositions(e, N.bit_length() - 1):
+    for plan in compositions_n(N):
         f.set_plan(N, plan)
         assert f.plan(N) == plan
         got = to_host(f.fft_forward(to_device(x)))
@@ -61,7 +78,7 @@ def test_every_plan_matches_oracle(torch_mod, N):
     f.set_plan(N, None)
 
 
-@pytest.mark.parametrize("N", [65536, 2 ** 20])
+@pytest.mark.parametrize("N", [65536, 2 ** 20, 2 ** 19])
 def test_every_plan_agrees(torch_mod, N):
     """All plans give the output of the all-single-pass plan (pinned to the
     oracle by the transform tests), forward and inverse, digit-major with a
@@ -71,11 +88,10 @@ def test_every_plan_agrees(torch_mod, N):
     from paper_1811_01490_amd import Field, to_device, to_host
 
     f = Field(**P8)
-    e = {65536: 4, 2 ** 20: 5}[N]
     x = gi.operand(8, P8["r"], N, gi.BASE_SEED + 710, 0, edge_frac=0.005)
     dx = to_device(x)
     ref_f = ref_i = None
-    for plan in compositions(e, N.bit_length() - 1):
+    for plan in compositions_n(N):
         f.set_plan(N, plan)
         yf = torch.full((8, N + 8), 3, dtype=torch.int64, device="cuda")
         f.fft_forward(dx, y=yf, n=N)
