@@ -487,6 +487,35 @@ __device__ __forceinline__ L96 mul_twiddle_uniform(uint64_t x, const uint32_t* _
   return mul_core<KD, W, U>(x0, x1, y, s0, s1, s2, m);
 }
 
+// x * tw where lane m holds digit m of x (no rotation) and the table entry
+// is wavefront-uniform: limbs through scalar loads, the lane's correction sum
+// S_m = suffix(m + 1) through one vector load at a fixed per-lane offset.
+// Keeps the loads of one slot's product from being hoisted above the
+// previous slot's work (which only raises register pressure).
+__device__ __forceinline__ void slot_fence() { asm volatile("" ::: "memory"); }
+
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_entry_uniform(uint64_t x, const uint32_t* __restrict__ tw, int m) {
+  slot_fence();
+  YLimbs<KD> y;
+  static_for<3 * KD>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    y.l[i] = tw[TwLayout<KD>::LIMBS + i];
+  });
+  const uint32_t* suf = tw + TwLayout<KD>::SUF + 3 * (m + 1);
+  return mul_core<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), y, suf[0], suf[1], suf[2], m);
+}
+
+// The same with a per-group entry (vector loads of the limbs).
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_entry(uint64_t x, const uint32_t* __restrict__ tw, int m) {
+  slot_fence();
+  YLimbs<KD> y;
+  tw_limbs<KD>(tw, y);
+  const uint32_t* suf = tw + TwLayout<KD>::SUF + 3 * (m + 1);
+  return mul_core<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), y, suf[0], suf[1], suf[2], m);
+}
+
 // x * y for two data elements: every lane of the element loads all of y's
 // digits (same addresses across the element's lanes) and derives the limbs
 // and its correction sum (rot = 0: S_m = sum_{t > m} y_t).

@@ -27,9 +27,11 @@ namespace {
 const uint64_t kMaxLog2N = 25;
 
 struct DevTables {
-  uint32_t* fwd = nullptr;  // n/K entries: w^j
-  uint32_t* inv = nullptr;  // n/K entries: w^-j
-  uint32_t* ninv = nullptr; // one entry: 1/n
+  uint32_t* fwd = nullptr;   // n/K entries: w^j
+  uint32_t* inv = nullptr;   // n/K entries: w^-j
+  uint32_t* fwd2 = nullptr;  // n/K entries: w^(K j) (n >= K^2)
+  uint32_t* inv2 = nullptr;  // n/K entries: w^-(K j)
+  uint32_t* ninv = nullptr;  // one entry: 1/n
 };
 
 struct DevConsts {
@@ -176,8 +178,8 @@ int upload(const std::vector<uint32_t>& host, uint32_t** dev) {
   return GFP_OK;
 }
 
-// valid transform size: n = K^e, e >= 1, within the field and the build limit
-// n = R K^e with R = 2^(log2n - e log2 K) < K: *e radix-K passes, preceded
+// valid transform size: a power of two n >= K within the field and the build
+// limit.  n = R K^e with R = 2^(log2n - e log2 K) < K: *e radix-K passes, preceded
 // by one radix-R pass when R > 1.
 int check_size(const gfp_field* f, uint64_t n, int* log2n, int* e) {
   const int lg = log2_exact(n);
@@ -209,6 +211,15 @@ int get_tables(gfp_field* f, uint64_t n, const DevTables** out) {
     build_table(f, root_mont(f, n, true), cnt, host);
     rc = upload(host, &t.inv);
   }
+  // w^K = w_{n/K} (the roots are nested): twiddles of the passes before the last
+  if (rc == GFP_OK && n >= 4ull * f->k * f->k) {
+    build_table(f, root_mont(f, n / (2ull * f->k), false), cnt, host);
+    rc = upload(host, &t.fwd2);
+    if (rc == GFP_OK) {
+      build_table(f, root_mont(f, n / (2ull * f->k), true), cnt, host);
+      rc = upload(host, &t.inv2);
+    }
+  }
   if (rc == GFP_OK) {
     // 1/n = n^(p-2)
     const Mont& M = *f->mont;
@@ -222,6 +233,8 @@ int get_tables(gfp_field* f, uint64_t n, const DevTables** out) {
   if (rc != GFP_OK) {
     (void)hipFree(t.fwd);
     (void)hipFree(t.inv);
+    (void)hipFree(t.fwd2);
+    (void)hipFree(t.inv2);
     (void)hipFree(t.ninv);
     return rc;
   }
@@ -405,6 +418,7 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
     p.scale = inverse && i == 0;
     p.tw = p.scale ? t->ninv : (inverse ? t->inv : t->fwd);
     p.tw1 = inverse ? t->inv : t->fwd;
+    p.tw2 = inverse ? t->inv2 : t->fwd2;
     p.last = (i == nl - 1) && canonical;
     p.nvec = nvec;
     p.vin = src.vs;
@@ -669,6 +683,8 @@ int gfp_field_destroy(gfp_field* f) {
     (void)hipSetDevice(kv.first.first);
     (void)hipFree(kv.second.fwd);
     (void)hipFree(kv.second.inv);
+    (void)hipFree(kv.second.fwd2);
+    (void)hipFree(kv.second.inv2);
     (void)hipFree(kv.second.ninv);
   }
   for (auto& kv : f->consts) {
@@ -756,6 +772,7 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   p.scale = p.inverse && s == 0;
   p.tw = p.scale ? t->ninv : (p.inverse ? t->inv : t->fwd);
   p.tw1 = p.inverse ? t->inv : t->fwd;
+  p.tw2 = p.inverse ? t->inv2 : t->fwd2;
   p.span = span;
   p.wide = wide;
   p.last = (s + span - 1 == total - 1);

@@ -37,6 +37,9 @@ struct PassArgs {
   int span = 1;
   bool wide = false;  // span 2 over 8 blocks per workgroup (needs N / (K^2 Ns) >= 8)
   const uint32_t* tw1 = nullptr;
+  // table of w^(K i) (w^-(K i) for the inverse), i < N/K: the twiddles of
+  // every radix-K pass but the last, without a rotation
+  const uint32_t* tw2 = nullptr;
 };
 // Largest span a launch supports for k (0 if none beyond 1).
 bool span2_supported(int k);

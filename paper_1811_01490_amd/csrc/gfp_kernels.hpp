@@ -30,11 +30,14 @@ enum { MODE_PLAIN = 0, MODE_SCALE = 1 };
 // twiddles and rotations of a wavefront are uniform: the table entry is read
 // with scalar loads into SGPRs and feeds v_mad_u64_u32 as its SGPR operand.
 // Used when every a has at least G groups (all passes but the last).
-template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF>
+// T2: the twiddles come from the table of w^(K i) without rotations (every
+// pass but the last); otherwise from the table of w^j with r^rho rotations.
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T2>
 __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
                                               uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
-                                              const uint32_t* __restrict__ tw, int log2n, int log2ns, uint64_t ngroups,
-                                              uint64_t nvec, uint64_t vin, uint64_t vout) {
+                                              const uint32_t* __restrict__ tw, const uint32_t* __restrict__ tw2,
+                                              int log2n, int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin,
+                                              uint64_t vout) {
   typedef Geo<KD> Gm;
   constexpr int KB = Gm::KB;
   constexpr int LOGKB = ilog2(KB);
@@ -93,6 +96,19 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
       static_for<KB - 1>([&](auto T) {
         constexpr int t = decltype(T)::value + 1;
         v[t] = l96(x[t]);
+      });
+    } else if constexpr (T2) {
+      // every exponent a t N / (K Ns) is a multiple of K: w^(a t N / (K Ns))
+      // is entry (a t) N / (K^2 Ns) of the table of w^(K i), no rotation
+      const int sh2 = log2n - 2 * LOGKB - log2ns;
+      static_for<KB - 1>([&](auto T) {
+        constexpr int t = decltype(T)::value + 1;
+        const uint32_t* e = tw2 + ((a * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS;
+        if constexpr (UNIF) {
+          v[t] = mul_entry_uniform<KD, W, U>(x[t], e, m);
+        } else {
+          v[t] = mul_entry<KD, W, U>(x[t], e, m);
+        }
       });
     } else {
       const int shift = log2n - log2ns - LOGKB;  // table stride N / (Ns K)
@@ -191,11 +207,14 @@ struct Span2Geo {
   static constexpr int ROW = KB * KD + 8;      // u64 words per LDS row, padded by 64 bytes
 };
 
-template <int KD, int W, int U, bool INV, int MODE, bool LAST>
+// T2B: the second pass is not the last one and takes its twiddles from the
+// table of w^(K i); the first pass never is the last and always does.
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B>
 __global__ __launch_bounds__(256) void k_pass2(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
                                                uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
                                                const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
-                                               int log2n, int log2ns, uint64_t nvec, uint64_t vin, uint64_t vout) {
+                                               const uint32_t* __restrict__ tw2, int log2n, int log2ns, uint64_t nvec,
+                                               uint64_t vin, uint64_t vout) {
   static_assert(KD == 8, "the fused pass pair is built for k = 8");
   typedef Geo<KD> Gm;
   typedef Span2Geo<KD> SG;
@@ -246,14 +265,11 @@ __global__ __launch_bounds__(256) void k_pass2(const uint64_t* __restrict__ in, 
         v[t] = l96(x[t]);
       });
     } else {
-      const int shift = log2n - log2ns - LOGKB;
+      // pass s is not the last radix-K pass: table of w^(K i), no rotation
+      const int sh2 = log2n - 2 * LOGKB - log2ns;
       static_for<KB - 1>([&](auto T) {
         constexpr int t = decltype(T)::value + 1;
-        const uint64_t e = a * (uint64_t)t;
-        const int rho = (int)(e >> log2ns);
-        const uint64_t cc = e & (ns - 1);
-        const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
-        v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw0 + (cc << shift) * TwLayout<KD>::WORDS, rot, l, m);
+        v[t] = mul_entry_uniform<KD, W, U>(x[t], tw2 + ((a * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS, m);
       });
     }
   }
@@ -274,16 +290,24 @@ __global__ __launch_bounds__(256) void k_pass2(const uint64_t* __restrict__ in, 
   const int log2ns1 = log2ns + LOGKB;
   const uint64_t ns1 = ns << LOGKB;
   const uint64_t a1 = a + (t1 << log2ns);
-  const int shift1 = log2n - log2ns1 - LOGKB;
   v[0] = l96(x[0]);
-  static_for<KB - 1>([&](auto T) {
-    constexpr int t = decltype(T)::value + 1;
-    const uint64_t e = a1 * (uint64_t)t;
-    const int rho = (int)(e >> log2ns1);
-    const uint64_t cc = e & (ns1 - 1);
-    const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
-    v[t] = mul_twiddle<KD, W, U>(x[t], tw1 + (cc << shift1) * TwLayout<KD>::WORDS, rot, l, m);
-  });
+  if constexpr (T2B) {
+    const int sh2 = log2n - 2 * LOGKB - log2ns1;
+    static_for<KB - 1>([&](auto T) {
+      constexpr int t = decltype(T)::value + 1;
+      v[t] = mul_entry<KD, W, U>(x[t], tw2 + ((a1 * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS, m);
+    });
+  } else {
+    const int shift1 = log2n - log2ns1 - LOGKB;
+    static_for<KB - 1>([&](auto T) {
+      constexpr int t = decltype(T)::value + 1;
+      const uint64_t e = a1 * (uint64_t)t;
+      const int rho = (int)(e >> log2ns1);
+      const uint64_t cc = e & (ns1 - 1);
+      const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
+      v[t] = mul_twiddle<KD, W, U>(x[t], tw1 + (cc << shift1) * TwLayout<KD>::WORDS, rot, l, m);
+    });
+  }
   dft_base<KD, INV>(v, m);
   const uint64_t obase = a + (t1 << log2ns) + (c << (log2ns + 2 * LOGKB));
   static_for<KB>([&](auto T) {
@@ -314,11 +338,12 @@ struct Span2UGeo {
   static constexpr int THREADS = 64 * NBLK * KB / Geo<KD>::G;
 };
 
-template <int KD, int W, int U, bool INV, int MODE, bool LAST>
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B>
 __global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
                                                  uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
                                                  const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
-                                                 int log2n, int log2ns, uint64_t nvec, uint64_t vin, uint64_t vout) {
+                                                 const uint32_t* __restrict__ tw2, int log2n, int log2ns, uint64_t nvec,
+                                                 uint64_t vin, uint64_t vout) {
   static_assert(KD == 8, "the fused pass pair is built for k = 8");
   typedef Geo<KD> Gm;
   typedef Span2UGeo<KD> SG;
@@ -365,14 +390,11 @@ __global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in
         v[t] = l96(x[t]);
       });
     } else {
-      const int shift = log2n - log2ns - LOGKB;
+      // pass s is not the last radix-K pass: table of w^(K i), no rotation
+      const int sh2 = log2n - 2 * LOGKB - log2ns;
       static_for<KB - 1>([&](auto T) {
         constexpr int t = decltype(T)::value + 1;
-        const uint64_t e = a * (uint64_t)t;
-        const int rho = (int)(e >> log2ns);
-        const uint64_t cc = e & (ns - 1);
-        const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
-        v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw0 + (cc << shift) * TwLayout<KD>::WORDS, rot, l, m);
+        v[t] = mul_entry_uniform<KD, W, U>(x[t], tw2 + ((a * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS, m);
       });
     }
   }
@@ -397,6 +419,12 @@ __global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in
     static_for<KB - 1>([&](auto T) {
       constexpr int t = decltype(T)::value + 1;
       v[t] = l96(x[t]);
+    });
+  } else if constexpr (T2B) {
+    const int sh2 = log2n - 2 * LOGKB - log2ns1;
+    static_for<KB - 1>([&](auto T) {
+      constexpr int t = decltype(T)::value + 1;
+      v[t] = mul_entry_uniform<KD, W, U>(x[t], tw2 + ((a1 * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS, m);
     });
   } else {
     const int shift1 = log2n - log2ns1 - LOGKB;
@@ -478,37 +506,49 @@ hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
   } else {
     constexpr int LOGKB = ilog2(2 * KD);
     if (p.log2n < 2 * LOGKB || p.log2ns + 2 * LOGKB > p.log2n) return hipErrorInvalidValue;
+    // the second pass takes the w^(K i) table unless it is the last pass
+    const bool t2b = !p.last && p.log2n - 2 * LOGKB - (p.log2ns + LOGKB) >= 0;
     if (p.wide) {
       // 8 blocks per workgroup: both halves with uniform twiddles
       if (p.log2n - 2 * LOGKB - p.log2ns < 3) return hipErrorInvalidValue;
       const uint64_t wgs = p.nvec << (p.log2n - 2 * LOGKB - 3);
-#define GFP_LAUNCH2U(INV, MODE, LAST)                                                                        \
-  hipLaunchKernelGGL((k_pass2u<KD, W, U, INV, MODE, LAST>), dim3((unsigned)wgs), dim3(Span2UGeo<KD>::THREADS), 0, st, \
-                     p.in, p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.log2n, p.log2ns, p.nvec,     \
-                     p.vin, p.vout)
+#define GFP_LAUNCH2U(INV, MODE, LAST, T2B)                                                                       \
+  hipLaunchKernelGGL((k_pass2u<KD, W, U, INV, MODE, LAST, T2B>), dim3((unsigned)wgs), dim3(Span2UGeo<KD>::THREADS), 0, \
+                     st, p.in, p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.log2n, p.log2ns,  \
+                     p.nvec, p.vin, p.vout)
+#define GFP_LAUNCH2U_T(INV, MODE)                   \
+  if (p.last) GFP_LAUNCH2U(INV, MODE, true, false); \
+  else if (t2b) GFP_LAUNCH2U(INV, MODE, false, true); \
+  else GFP_LAUNCH2U(INV, MODE, false, false);
       if (p.scale) {
-        if (p.last) GFP_LAUNCH2U(true, MODE_SCALE, true); else GFP_LAUNCH2U(true, MODE_SCALE, false);
+        GFP_LAUNCH2U_T(true, MODE_SCALE)
       } else if (p.inverse) {
-        if (p.last) GFP_LAUNCH2U(true, MODE_PLAIN, true); else GFP_LAUNCH2U(true, MODE_PLAIN, false);
+        GFP_LAUNCH2U_T(true, MODE_PLAIN)
       } else {
-        if (p.last) GFP_LAUNCH2U(false, MODE_PLAIN, true); else GFP_LAUNCH2U(false, MODE_PLAIN, false);
+        GFP_LAUNCH2U_T(false, MODE_PLAIN)
       }
+#undef GFP_LAUNCH2U_T
 #undef GFP_LAUNCH2U
       return hipGetLastError();
     }
     const uint64_t blocks = (p.nvec << (p.log2n - 2 * LOGKB));
     const unsigned nb = (unsigned)((blocks + Span2Geo<KD>::BPW - 1) / Span2Geo<KD>::BPW);
     if (nb == 0) return hipSuccess;
-#define GFP_LAUNCH2(INV, MODE, LAST)                                                                                 \
-  hipLaunchKernelGGL((k_pass2<KD, W, U, INV, MODE, LAST>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, p.out, \
-                     p.se_out, p.sd_out, p.tw, p.tw1, p.log2n, p.log2ns, p.nvec, p.vin, p.vout)
+#define GFP_LAUNCH2(INV, MODE, LAST, T2B)                                                                         \
+  hipLaunchKernelGGL((k_pass2<KD, W, U, INV, MODE, LAST, T2B>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, \
+                     p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.log2n, p.log2ns, p.nvec, p.vin, p.vout)
+#define GFP_LAUNCH2_T(INV, MODE)                   \
+  if (p.last) GFP_LAUNCH2(INV, MODE, true, false); \
+  else if (t2b) GFP_LAUNCH2(INV, MODE, false, true); \
+  else GFP_LAUNCH2(INV, MODE, false, false);
     if (p.scale) {
-      if (p.last) GFP_LAUNCH2(true, MODE_SCALE, true); else GFP_LAUNCH2(true, MODE_SCALE, false);
+      GFP_LAUNCH2_T(true, MODE_SCALE)
     } else if (p.inverse) {
-      if (p.last) GFP_LAUNCH2(true, MODE_PLAIN, true); else GFP_LAUNCH2(true, MODE_PLAIN, false);
+      GFP_LAUNCH2_T(true, MODE_PLAIN)
     } else {
-      if (p.last) GFP_LAUNCH2(false, MODE_PLAIN, true); else GFP_LAUNCH2(false, MODE_PLAIN, false);
+      GFP_LAUNCH2_T(false, MODE_PLAIN)
     }
+#undef GFP_LAUNCH2_T
 #undef GFP_LAUNCH2
     return hipGetLastError();
   }
@@ -549,23 +589,28 @@ hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
   if (p.span != 1) return hipErrorInvalidValue;
   const unsigned nb = blocks_for(p.ngroups * p.nvec, Geo<KD>::G);
   if (nb == 0) return hipSuccess;
-#define GFP_LAUNCH(INV, MODE, LAST, UNIF)                                                                           \
-  hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST, UNIF>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, \
-                     p.out, p.se_out, p.sd_out, p.tw, p.log2n, p.log2ns, p.ngroups, p.nvec, p.vin, p.vout)
-  // uniform twiddles when every base a has at least one wavefront of groups
+#define GFP_LAUNCH(INV, MODE, LAST, UNIF, T2)                                                                       \
+  hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST, UNIF, T2>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, \
+                     p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.log2n, p.log2ns, p.ngroups, p.nvec, p.vin, p.vout)
+  // uniform twiddles when every base a has at least one wavefront of groups;
+  // the w^(K i) table for every pass but the last
   const int lk = ilog2(2 * KD);
   const bool unif = p.log2ns > 0 && (p.log2n - lk - p.log2ns) >= ilog2(Geo<KD>::G);
+  const bool t2 = !p.last && p.log2n - 2 * lk - p.log2ns >= 0;
+#define GFP_LAUNCH_T(INV)                                                    \
+  if (p.last) GFP_LAUNCH(INV, MODE_PLAIN, true, false, false);               \
+  else if (unif && t2) GFP_LAUNCH(INV, MODE_PLAIN, false, true, true);       \
+  else if (unif) GFP_LAUNCH(INV, MODE_PLAIN, false, true, false);            \
+  else if (t2) GFP_LAUNCH(INV, MODE_PLAIN, false, false, true);              \
+  else GFP_LAUNCH(INV, MODE_PLAIN, false, false, false);
   if (p.scale) {
-    if (p.last) GFP_LAUNCH(true, MODE_SCALE, true, false); else GFP_LAUNCH(true, MODE_SCALE, false, false);
+    if (p.last) GFP_LAUNCH(true, MODE_SCALE, true, false, false); else GFP_LAUNCH(true, MODE_SCALE, false, false, false);
   } else if (p.inverse) {
-    if (p.last) GFP_LAUNCH(true, MODE_PLAIN, true, false);
-    else if (unif) GFP_LAUNCH(true, MODE_PLAIN, false, true);
-    else GFP_LAUNCH(true, MODE_PLAIN, false, false);
+    GFP_LAUNCH_T(true)
   } else {
-    if (p.last) GFP_LAUNCH(false, MODE_PLAIN, true, false);
-    else if (unif) GFP_LAUNCH(false, MODE_PLAIN, false, true);
-    else GFP_LAUNCH(false, MODE_PLAIN, false, false);
+    GFP_LAUNCH_T(false)
   }
+#undef GFP_LAUNCH_T
 #undef GFP_LAUNCH
   return hipGetLastError();
 }

@@ -45,16 +45,16 @@ def kernel_key(name: str) -> str:
     'k_pass<8,63,34,fwd,last>' (',unif' for the uniform-twiddle variant,
     'inv' and 'scale' for the inverse); the fused pairs likewise as
     'k_pass2<...>' and 'k_pass2u<...>' (the wide variant)."""
-    m = re.search(r"(k_pass2u?)<(\d+), (\d+), (\d+), (true|false), (\d), (true|false)>", name)
+    m = re.search(r"(k_pass2u?)<(\d+), (\d+), (\d+), (true|false), (\d), (true|false), (true|false)>", name)
     if m:
-        kern, k, w, u, inv, mode, last = m.groups()
+        kern, k, w, u, inv, mode, last, t2 = m.groups()
         key = "%s<%s,%s,%s,%s,%s" % (kern, k, w, u, "inv" if inv == "true" else "fwd", "last" if last == "true" else "mid")
         if mode == "1":
             key += ",scale"
         return key + ">"
-    m = re.search(r"k_pass<(\d+), (\d+), (\d+), (true|false), (\d), (true|false), (true|false)>", name)
+    m = re.search(r"k_pass<(\d+), (\d+), (\d+), (true|false), (\d), (true|false), (true|false), (true|false)>", name)
     if m:
-        k, w, u, inv, mode, last, unif = m.groups()
+        k, w, u, inv, mode, last, unif, t2 = m.groups()
         key = "k_pass<%s,%s,%s,%s,%s" % (k, w, u, "inv" if inv == "true" else "fwd", "last" if last == "true" else "mid")
         if mode == "1":
             key += ",scale"
