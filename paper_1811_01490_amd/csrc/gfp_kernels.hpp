@@ -19,6 +19,23 @@
 namespace gfpk {
 
 // ---------------------------------------------------------------------------
+// XCD-aware workgroup order
+// ---------------------------------------------------------------------------
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+// Mapping dispatch index b to logical index (b mod 8) (G / 8) + b / 8 gives
+// every XCD one contiguous range of logical workgroups, run in order, so
+// neighbouring workgroups meet in the same L2.  That pays when the input or
+// the output is digit-major (a workgroup touches half of each 128-byte line,
+// its neighbour the other half) and costs 1-3% otherwise (measured), so it is
+// used only then.  A pure permutation of the work; identity when G is not a multiple
+// of 8.
+__device__ __forceinline__ uint64_t xcd_block(bool on) {
+  const uint64_t b = blockIdx.x, g = gridDim.x;
+  if (!on || (g & 7)) return b;
+  return (b & 7) * (g >> 3) + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
 // one radix-K Stockham pass
 // ---------------------------------------------------------------------------
 // MODE_PLAIN: twiddles from the table (forward or inverse table).
@@ -45,7 +62,7 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
   const int m = Gm::digit(l);
   // A launch covers nvec transforms of the same size: vector v reads
   // in + v vin and writes out + v vout.
-  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const uint64_t wave = xcd_block(se_in == 1 || se_out == 1) * (blockDim.x / 64) + (threadIdx.x >> 6);
   const uint64_t nk = ngroups;  // N / K
   const int log2nk = log2n - LOGKB;
   const uint64_t ns = 1ull << log2ns;
@@ -227,7 +244,7 @@ __global__ __launch_bounds__(256) void k_pass2(const uint64_t* __restrict__ in, 
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int bw = wv / SG::WPB, h = wv % SG::WPB;
   const int log2nb = log2n - 2 * LOGKB;  // blocks per vector
-  uint64_t gq = (uint64_t)blockIdx.x * SG::BPW + bw;
+  uint64_t gq = xcd_block(se_in == 1 || se_out == 1) * SG::BPW + bw;
   uint64_t vec = gq >> log2nb;
   const bool active = vec < nvec;
   if (!active) {
@@ -357,7 +374,7 @@ __global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int log2nb = log2n - 2 * LOGKB;      // blocks per vector
   const int log2wpv = log2nb - 3;            // workgroups per vector
-  const uint64_t wg = blockIdx.x;
+  const uint64_t wg = xcd_block(se_in == 1 || se_out == 1);
   const uint64_t vec = wg >> log2wpv;
   const uint64_t r = wg & ((1ull << log2wpv) - 1);
   in += vec * vin;
