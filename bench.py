@@ -321,8 +321,10 @@ def _cpu_model():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=300,
+                    help="untimed steps first; the first call also builds the twiddle tables on the host, and the "
+                         "GPU clock needs tens of ms of work to come back up after that idle time")
     ap.add_argument("--pass-reps", type=int, default=50)
     ap.add_argument("--cpu-sample-log2", type=int, default=19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
