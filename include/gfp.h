@@ -196,6 +196,26 @@ int gfp_polymul_batched(const gfp_field* f, uint32_t n, const gfp_polymul_desc* 
 int gfp_elementwise(const gfp_field* f, int op, const uint64_t* x, uint64_t ld_x, const uint64_t* y, uint64_t ld_y,
                     uint64_t* z, uint64_t ld_z, uint64_t n, int64_t s, const uint64_t* c_host, void* stream);
 
+/* ---- Integer products ---------------------------------------------------------
+ *
+ * c = a * b for non-negative integers of na and nb 64-bit words (device
+ * memory, little-endian; c has na + nb words and must not overlap a or b):
+ * the application the paper starts from (section 1) -- an integer is a
+ * polynomial evaluated at a power of two, so the product is a polynomial
+ * product over Z/pZ (section 3.3, Alg. Fast Convolution) followed by the
+ * evaluation.  The integers are cut into W-bit coefficients (r = 2^W + 2^U,
+ * so each is one radix-r digit); the coefficients of the product stay below
+ * min(la, lb) 2^(2W) < p, so their canonical digits give them exactly; they
+ * are converted back to binary, added at their bit offsets and the carries
+ * resolved by a carry-lookahead scan, all on the device.  One coefficient
+ * carries W of the k W bits an element holds: a denser packing would need a
+ * radix conversion of every coefficient.  Sizes: la + lb - 1 coefficients
+ * (la = ceil(64 na / W)) within the transform limit.  Workspace as for the
+ * transforms (gfp_bigint_mul_workspace_size bytes, or NULL). */
+int gfp_bigint_mul_workspace_size(const gfp_field* f, uint64_t na, uint64_t nb, uint64_t* bytes);
+int gfp_bigint_mul(const gfp_field* f, const uint64_t* a, uint64_t na, const uint64_t* b, uint64_t nb, uint64_t* c,
+                   void* workspace, uint64_t ws_bytes, void* stream);
+
 /* ---- Stage groupings and the autotuner -------------------------------------
  *
  * A transform of size n = R K^e runs as a sequence of launches: the radix-R

@@ -824,6 +824,95 @@ int gfp_polymul(const gfp_field* cf, const uint64_t* a, uint64_t la, uint64_t ld
   return polymul_chunk(f, log2n, e, &q, 1, w, st);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// integer products (section 1: an integer product is a polynomial product
+// evaluated at a power of two)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BigintPlan {
+  uint64_t la, lb, lc, nw, N;
+  int log2n, e;
+  // workspace offsets in words
+  uint64_t oA, oB, oC, oPoly, oLo, oHi, oBytes;
+  uint64_t words;
+};
+
+int plan_bigint(const gfp_field* f, uint64_t na, uint64_t nb, BigintPlan& p) {
+  if (!f || na == 0 || nb == 0) return GFP_EINVAL;
+  if (!f->gpu_shape) return GFP_EUNSUPPORTED;
+  const uint64_t W = (uint64_t)f->w;
+  p.la = (64 * na + W - 1) / W;
+  p.lb = (64 * nb + W - 1) / W;
+  p.lc = p.la + p.lb - 1;
+  p.nw = na + nb;
+  int rc = gfp_polymul_size(f, p.la, p.lb, &p.N);
+  if (rc != GFP_OK) return rc;
+  // C_m < min(la, lb) 2^(2W) must stay below r^4 (four digits are read) and p
+  if ((2 * W + 26) > 4 * W || (2 * W + 26) > (uint64_t)f->k * W) return GFP_EUNSUPPORTED;
+  check_size(f, p.N, &p.log2n, &p.e);
+  const uint64_t k = f->k;
+  p.oA = 0;
+  p.oB = p.oA + k * p.la;
+  p.oC = p.oB + k * p.lb;
+  p.oPoly = p.oC + k * p.lc;
+  p.oLo = p.oPoly + chunk_words(p.N, k, 1);
+  p.oHi = p.oLo + p.nw;
+  p.oBytes = p.oHi + p.nw;  // flags (nw bytes), block aggregates and carries (2 bytes per block)
+  const uint64_t nbk = gfpk::bigint_scan_blocks(p.nw);
+  p.words = p.oBytes + (p.nw + 2 * nbk + 7) / 8;
+  return GFP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gfp_bigint_mul_workspace_size(const gfp_field* f, uint64_t na, uint64_t nb, uint64_t* bytes) {
+  if (!bytes) return GFP_EINVAL;
+  BigintPlan p;
+  int rc = plan_bigint(f, na, nb, p);
+  if (rc != GFP_OK) return rc;
+  *bytes = p.words * 8;
+  return GFP_OK;
+}
+
+int gfp_bigint_mul(const gfp_field* cf, const uint64_t* a, uint64_t na, const uint64_t* b, uint64_t nb, uint64_t* c,
+                   void* workspace, uint64_t ws_bytes, void* stream) {
+  gfp_field* f = const_cast<gfp_field*>(cf);
+  if (!a || !b || !c) return GFP_EINVAL;
+  BigintPlan p;
+  int rc = plan_bigint(f, na, nb, p);
+  if (rc != GFP_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  Scratch s;
+  uint64_t* w = nullptr;
+  rc = get_workspace(workspace, ws_bytes, p.words * 8, st, s, &w);
+  if (rc != GFP_OK) return rc;
+  const int k = (int)f->k;
+  uint64_t* A = w + p.oA;
+  uint64_t* B = w + p.oB;
+  uint64_t* C = w + p.oC;
+  hipError_t he = gfpk::launch_bigint_split(a, na, A, p.la, k, f->w, st);
+  if (he == hipSuccess) he = gfpk::launch_bigint_split(b, nb, B, p.lb, k, f->w, st);
+  if (he != hipSuccess) return hip_status(he);
+  PolyReq q{A, p.la, p.la, B, p.lb, p.lb, C, p.lc};
+  rc = polymul_chunk(f, p.log2n, p.e, &q, 1, w + p.oPoly, st);
+  if (rc != GFP_OK) return rc;
+  uint8_t* flags = (uint8_t*)(w + p.oBytes);
+  uint8_t* agg = flags + p.nw;
+  uint8_t* cin = agg + gfpk::bigint_scan_blocks(p.nw);
+  he = gfpk::launch_bigint_combine(C, p.lc, f->w, f->u, p.nw, w + p.oLo, w + p.oHi, st);
+  if (he == hipSuccess) he = gfpk::launch_bigint_carry(w + p.oLo, w + p.oHi, p.nw, c, flags, agg, cin, st);
+  return hip_status(he);
+}
+
+}  // extern "C"
+
+extern "C" {
+
 int gfp_polymul_batched_workspace_size(const gfp_field* cf, uint32_t n, const gfp_polymul_desc* d, uint64_t* bytes) {
   if (!bytes) return GFP_EINVAL;
   BatchPlan plan;

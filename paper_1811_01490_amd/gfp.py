@@ -97,6 +97,8 @@ SIGNATURES = {
     "gfp_polymul_batched_workspace_size": (_int, [_vp, _u32, _vp, ctypes.POINTER(_u64)]),
     "gfp_polymul_batched": (_int, [_vp, _u32, _vp, _vp, _u64, _int, _vp]),
     "gfp_elementwise": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _u64, _i64, _pu64, _vp]),
+    "gfp_bigint_mul_workspace_size": (_int, [_vp, _u64, _u64, ctypes.POINTER(_u64)]),
+    "gfp_bigint_mul": (_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, _u64, _vp]),
     "gfp_plan_get": (_int, [_vp, _u64, _u64, _int, ctypes.c_char_p, _u32]),
     "gfp_plan_set": (_int, [_vp, _u64, _u64, _int, ctypes.c_char_p]),
     "gfp_tune": (_int, [_vp, _u64, _u64, _int, _vp, ctypes.c_char_p, _u32, ctypes.POINTER(ctypes.c_double)]),
@@ -278,6 +280,28 @@ class Field:
             if workspace is not None else (None, 0)
         _check(lib().gfp_polymul_batched(self._h, len(descs), descs, wp, wb, BATCH_GRAPH if graph else 0,
                                          _stream(stream)), "gfp_polymul_batched")
+
+    def bigint_mul(self, a, b, c=None, workspace=None, stream=None):
+        """c = a * b for integers held as 1-D int64/uint64 device tensors of
+        64-bit little-endian words; c gets len(a) + len(b) words."""
+        for t, name in ((a, "a"), (b, "b")):
+            if t.dim() != 1 or not t.is_cuda or t.dtype not in (torch.int64, torch.uint64) or t.stride(0) != 1:
+                raise ValueError("%s must be a contiguous 1-D int64 device tensor" % name)
+        na, nb = a.numel(), b.numel()
+        if c is None:
+            c = torch.empty(na + nb, dtype=a.dtype, device=a.device)
+        if c.dim() != 1 or c.numel() < na + nb or c.stride(0) != 1:
+            raise ValueError("c must be a contiguous 1-D tensor of at least na + nb words")
+        wp, wb = (ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()) \
+            if workspace is not None else (None, 0)
+        _check(lib().gfp_bigint_mul(self._h, ctypes.c_void_p(a.data_ptr()), na, ctypes.c_void_p(b.data_ptr()), nb,
+                                    ctypes.c_void_p(c.data_ptr()), wp, wb, _stream(stream)), "gfp_bigint_mul")
+        return c
+
+    def bigint_mul_workspace_size(self, na: int, nb: int) -> int:
+        v = _u64()
+        _check(lib().gfp_bigint_mul_workspace_size(self._h, na, nb, ctypes.byref(v)), "gfp_bigint_mul_workspace_size")
+        return v.value
 
     def plan(self, n: int, nvec: int = 1, layout: int = LAYOUT_DIGIT_MAJOR) -> str:
         """Stage grouping used for nvec transforms of size n, e.g. '1211'."""

@@ -175,3 +175,20 @@ def test_plan_strings():
     assert g.plan(2 ** 20) == "1111"
     with pytest.raises(gfp.GFPError):
         g.set_plan(32768, "21")
+
+
+def test_bigint_sizes():
+    """Workspace sizing of integer products is host-only."""
+    L = _lib()
+    f = gfp.Field(**P8)
+    b = ctypes.c_uint64()
+    assert L.gfp_bigint_mul_workspace_size(f.handle, 0, 5, ctypes.byref(b)) == gfp.GFP_EINVAL
+    assert L.gfp_bigint_mul_workspace_size(f.handle, 5, 5, None) == gfp.GFP_EINVAL
+    assert L.gfp_bigint_mul(f.handle, None, 1, ctypes.c_void_p(8), 1, ctypes.c_void_p(8), None, 0, None) == gfp.GFP_EINVAL
+    small = f.bigint_mul_workspace_size(10, 10)
+    big = f.bigint_mul_workspace_size(2 ** 16, 2 ** 16)
+    assert 0 < small < big
+    # la + lb - 1 = 2 ceil(64 2^18 / 63) - 1 > 2^19: transform size 2^20, products above 2^25 refused
+    assert f.bigint_mul_workspace_size(2 ** 18, 2 ** 18) > big
+    with pytest.raises(gfp.GFPError):
+        f.bigint_mul_workspace_size(2 ** 25, 2 ** 25)
