@@ -308,6 +308,39 @@ def served_leg(torch, dev, n_req: int, loads, workspace_gib: int, slots: int, ex
     }
 
 
+def bigint_leg(torch, dev, words: int, reps: int):
+    """Integer product of two random `words`-word integers through the k = 8
+    polynomial product (63-bit coefficients), operands and result resident
+    in HBM; time per product with HIP events."""
+    import numpy as np
+
+    import gfp_inputs as gi
+    from paper_1811_01490_amd import Field
+
+    f = Field(K_DIG, R)
+    g = gi.rng(gi.BASE_SEED + 5, 0)
+    a = torch.from_numpy(g.integers(0, 2 ** 64, size=words, dtype=np.uint64).view(np.int64)).to(dev)
+    b = torch.from_numpy(g.integers(0, 2 ** 64, size=words, dtype=np.uint64).view(np.int64)).to(dev)
+    c = torch.empty(2 * words, dtype=torch.int64, device=dev)
+    ws = torch.empty(f.bigint_mul_workspace_size(words, words) // 8 + 1, dtype=torch.int64, device=dev)
+    for _ in range(3):
+        f.bigint_mul(a, b, c=c, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        f.bigint_mul(a, b, c=c, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n = f.polymul_size((64 * words + 62) // 63, (64 * words + 62) // 63)
+    f.close()
+    return {"workload": "product of two uniform random %d-bit integers (seed 1811014905), 63-bit coefficients over "
+                        "p = (2^63+2^34)^8+1" % (64 * words),
+            "words": words, "transform_size": n, "ms": round(ms, 4),
+            "input_bits_per_s": round(2 * 64 * words / (ms * 1e-3), 1)}
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -331,6 +364,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-bigint", action="store_true")
+    ap.add_argument("--bigint-words", type=int, default=2 ** 18)
     ap.add_argument("--served-requests", type=int, default=10000)
     ap.add_argument("--served-loads", default="0.7", help="comma-separated fractions of the plain saturated rate")
     ap.add_argument("--served-workspace-gib", type=int, default=16)
@@ -469,6 +504,8 @@ def main():
     if not args.no_served:
         out["served"] = served_leg(torch, dev, args.served_requests, [float(x) for x in args.served_loads.split(",")],
                                    args.served_workspace_gib, args.served_slots, args.served_express_log2n)
+    if not args.no_bigint:
+        out["bigint"] = bigint_leg(torch, dev, args.bigint_words, 20)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
     print(json.dumps(out), flush=True)
