@@ -113,9 +113,11 @@ def cpu_baseline(sample_log2: int):
 def batched_leg(torch, f, dev, reps: int):
     """Config 3: 256 products over the k = 8 prime, transform sizes N_i drawn
     uniformly from {16^2, 16^3, 16^4, 16^5} (log-uniform in N), la = lb = N_i / 2,
-    uniform coefficients.  Times 256 separate gfp_polymul calls against one
-    gfp_polymul_batched call replayed from its hipGraph, on one stream, and
-    checks that both give the same 256 products."""
+    uniform coefficients.  The stage grouping of every (size, batch class)
+    either path uses is autotuned first (gfp_tune).  Times 256 separate
+    gfp_polymul calls against one gfp_polymul_batched call replayed from its
+    hipGraph, on one stream, and checks that both give the same 256
+    products."""
     import numpy as np
 
     import gfp_inputs as gi
@@ -129,6 +131,18 @@ def batched_leg(torch, f, dev, reps: int):
         a = to_device(gi.uniform_digits(K_DIG, R, n // 2, seed, 2 + 2 * i), dev)
         b = to_device(gi.uniform_digits(K_DIG, R, n // 2, seed, 3 + 2 * i), dev)
         reqs.append((a, b))
+    # autotune the stage grouping of every (size, batch class) both paths use:
+    # gfp_polymul runs 2 forward and 1 inverse transform per product, the
+    # batched path 2C and C per chunk of C requests (element-major)
+    from paper_1811_01490_amd.gfp import LAYOUT_ELEMENT_MAJOR
+
+    tuned = {}
+    for n in sorted(set(sizes)):
+        per = f.polymul_workspace_size(n // 2, n // 2)
+        chunk = min(sizes.count(n), max(1, (4 << 30) // per))
+        for nvec in sorted({1, 2, chunk, 2 * chunk}):
+            plan, us = f.tune(n, nvec=nvec, layout=LAYOUT_ELEMENT_MAJOR)
+            tuned["%d/%d" % (n, nvec)] = {"plan": plan, "us": round(us, 1)}
     c_plain = [torch.empty((K_DIG, a.shape[1] + b.shape[1] - 1), dtype=torch.int64, device=dev) for a, b in reqs]
     c_batch = [torch.empty_like(c) for c in c_plain]
     ws1 = torch.empty(f.polymul_workspace_size(2 ** 19, 2 ** 19) // 8, dtype=torch.int64, device=dev)
@@ -171,6 +185,7 @@ def batched_leg(torch, f, dev, reps: int):
         "batched_coeffs_per_s": round(coefs / (t_batch * 1e-3), 1),
         "plain_coeffs_per_s": round(coefs / (t_plain * 1e-3), 1),
         "identical_outputs": bool(same),
+        "tuned_plans": tuned,
     }
 
 
