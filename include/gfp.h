@@ -352,6 +352,13 @@ int gfp_server_get_stats(gfp_server* s, gfp_server_stats* out);
  * are released and every ticket becomes invalid.  NULL is accepted. */
 int gfp_server_destroy(gfp_server* s);
 
+/* Input validation (the library assumes canonical inputs and does not check
+ * them on the hot path).  Counts the elements of the digit-major vector x
+ * (n elements, ld_x >= n, device memory) whose digits are not the canonical
+ * encoding of section 2 (every digit below r, or p - 1 as (0, ..., 0, r)),
+ * into the host *bad.  Synchronises the stream; not for stream capture. */
+int gfp_check_canonical(const gfp_field* f, const uint64_t* x, uint64_t ld_x, uint64_t n, void* stream, uint64_t* bad);
+
 /* Static description of an error code. */
 const char* gfp_strerror(int code);
 

@@ -34,6 +34,35 @@ __global__ __launch_bounds__(256) void k_unpad(const CopyBatch desc, const uint6
   cd.dst[(uint64_t)d * cd.ld + i] = work[(uint64_t)v * n * k + i * k + d];
 }
 
+// Elements of a digit-major vector that are not canonical (section 2: every
+// digit below r, or p - 1 written as (0, ..., 0, r)), counted into *bad
+// (vector atomics).  One thread per element.
+__global__ __launch_bounds__(256) void k_check_canonical(const uint64_t* __restrict__ x, uint64_t ld, uint64_t n,
+                                                         uint32_t k, uint64_t r, unsigned long long* bad) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool ok = true;
+  if (i < n) {
+    const uint64_t top = x[(uint64_t)(k - 1) * ld + i];
+    bool low_zero = true, below = top < r;
+    for (uint32_t d = 0; d + 1 < k; ++d) {
+      const uint64_t v = x[(uint64_t)d * ld + i];
+      below = below && v < r;
+      low_zero = low_zero && v == 0;
+    }
+    ok = below || (top == r && low_zero);
+  }
+  const uint64_t m = __ballot(!ok);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(bad, (unsigned long long)__popcll(m));
+}
+
+hipError_t launch_check_canonical(const uint64_t* x, uint64_t ld, uint64_t n, int k, uint64_t r, uint64_t* bad,
+                                  hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_canonical, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, ld, n, (uint32_t)k, r,
+                     (unsigned long long*)bad);
+  return hipGetLastError();
+}
+
 hipError_t launch_pad(int k, const CopyDesc* d, uint32_t nvec, uint64_t* work, uint64_t n, hipStream_t st) {
   if (nvec == 0) return hipSuccess;
   if (nvec > kCopyBatch) return hipErrorInvalidValue;

@@ -1039,6 +1039,23 @@ int gfp_elementwise(const gfp_field* cf, int op, const uint64_t* x, uint64_t ld_
   return hip_status(he);
 }
 
+int gfp_check_canonical(const gfp_field* f, const uint64_t* x, uint64_t ld_x, uint64_t n, void* stream,
+                        uint64_t* bad) {
+  if (!f || !bad || (n && !x) || ld_x < n) return GFP_EINVAL;
+  *bad = 0;
+  if (n == 0) return GFP_OK;
+  hipStream_t st = (hipStream_t)stream;
+  Scratch s;
+  uint64_t* dev = nullptr;
+  int rc = get_workspace(nullptr, 0, 8, st, s, &dev);
+  if (rc != GFP_OK) return rc;
+  hipError_t he = hipMemsetAsync(dev, 0, 8, st);
+  if (he == hipSuccess) he = gfpk::launch_check_canonical(x, ld_x, n, (int)f->k, f->r, dev, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(bad, dev, 8, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  return hip_status(he);
+}
+
 int gfp_plan_get(const gfp_field* cf, uint64_t n, uint64_t nvec, int layout, char* buf, uint32_t len) {
   gfp_field* f = const_cast<gfp_field*>(cf);
   if (!f || !buf || nvec == 0 || (layout != GFP_LAYOUT_DIGIT_MAJOR && layout != GFP_LAYOUT_ELEMENT_MAJOR))

@@ -80,6 +80,10 @@ uint64_t bigint_scan_blocks(uint64_t nw);
 hipError_t launch_bigint_carry(const uint64_t* lo, const uint64_t* hi, uint64_t nw, uint64_t* c, uint8_t* flags,
                                uint8_t* agg, uint8_t* cin, hipStream_t st);
 
+// count of non-canonical elements of a digit-major vector into *bad (device)
+hipError_t launch_check_canonical(const uint64_t* x, uint64_t ld, uint64_t n, int k, uint64_t r, uint64_t* bad,
+                                  hipStream_t st);
+
 bool shape_supported(int k, int w, int u);
 hipError_t launch_pass(int k, int w, int u, const PassArgs& p, hipStream_t st);
 hipError_t launch_elementwise(int k, int w, int u, const EwArgs& a, hipStream_t st);

@@ -99,6 +99,7 @@ SIGNATURES = {
     "gfp_elementwise": (_int, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _u64, _i64, _pu64, _vp]),
     "gfp_bigint_mul_workspace_size": (_int, [_vp, _u64, _u64, ctypes.POINTER(_u64)]),
     "gfp_bigint_mul": (_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, _u64, _vp]),
+    "gfp_check_canonical": (_int, [_vp, _vp, _u64, _u64, _vp, ctypes.POINTER(_u64)]),
     "gfp_plan_get": (_int, [_vp, _u64, _u64, _int, ctypes.c_char_p, _u32]),
     "gfp_plan_set": (_int, [_vp, _u64, _u64, _int, ctypes.c_char_p]),
     "gfp_tune": (_int, [_vp, _u64, _u64, _int, _vp, ctypes.c_char_p, _u32, ctypes.POINTER(ctypes.c_double)]),
@@ -280,6 +281,16 @@ class Field:
             if workspace is not None else (None, 0)
         _check(lib().gfp_polymul_batched(self._h, len(descs), descs, wp, wb, BATCH_GRAPH if graph else 0,
                                          _stream(stream)), "gfp_polymul_batched")
+
+    def check_canonical(self, x, n=None, stream=None) -> int:
+        """Number of elements of x (a (k, ld) device tensor) that are not
+        canonically encoded; synchronises the stream."""
+        n = x.shape[1] if n is None else n
+        px, ldx = _vec(x, self.k, n, "x")
+        bad = _u64()
+        _check(lib().gfp_check_canonical(self._h, px, ldx, n, _stream(stream), ctypes.byref(bad)),
+               "gfp_check_canonical")
+        return bad.value
 
     def bigint_mul(self, a, b, c=None, workspace=None, stream=None):
         """c = a * b for integers held as 1-D int64/uint64 device tensors of

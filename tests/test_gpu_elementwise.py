@@ -101,3 +101,23 @@ def test_mul_large_random(torch_mod):
     assert canonical_mask(z, r).all()
     bad = [i for i in range(n) if zi[i] != xi[i] * yi[i] % F.p]
     assert not bad, bad[:5]
+
+
+def test_check_canonical(torch_mod):
+    """gfp_check_canonical counts exactly the elements outside the section 2
+    encoding: a digit >= r, or a top digit r with a nonzero lower digit."""
+    from paper_1811_01490_amd import Field, to_device
+
+    for params in SHAPES[:2]:
+        k, r = params["k"], params["r"]
+        f = Field(k, r)
+        x = gi.operand(k, r, 5000, gi.BASE_SEED + 900, 0, edge_frac=0.05)  # includes p - 1 = (0, ..., 0, r)
+        assert f.check_canonical(to_device(x)) == 0
+        bad = x.copy()
+        bad[0, 10] = np.uint64(r)           # digit 0 equal to r
+        bad[k - 1, 20] = np.uint64(r + 1)   # top digit above r
+        bad[k - 1, 30] = np.uint64(r)       # top digit r with a nonzero lower digit
+        bad[3, 30] = np.uint64(1)
+        bad[2, 4999] = np.uint64(2 ** 64 - 1)
+        assert f.check_canonical(to_device(bad)) == 4
+        assert f.check_canonical(to_device(bad), n=4999) == 3
