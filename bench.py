@@ -356,6 +356,42 @@ def bigint_leg(torch, dev, words: int, reps: int):
             "input_bits_per_s": round(2 * 64 * words / (ms * 1e-3), 1)}
 
 
+# The paper's FFT timings (Table fftoverprimefield, FFT-based column, serial
+# CPU, machine unstated, units inferred as ms) for its test primes (Table
+# testprimes); the k = 32 rows need a shape this library does not build.
+PAPER_FFT_MS = [(8, 2 ** 59 + 2 ** 16, 256, 0.211), (8, 2 ** 59 + 2 ** 16, 4096, 5.961),
+                (16, 2 ** 58 + 2 ** 10, 1024, 1.819), (16, 2 ** 58 + 2 ** 10, 32768, 109.681)]
+
+
+def paper_context_leg(torch, dev):
+    """Forward transforms on the paper's own FFT workloads (same primes and
+    sizes), for context only: the paper's numbers are serial CPU code on
+    unstated hardware."""
+    import gfp_inputs as gi
+    from paper_1811_01490_amd import Field, to_device
+
+    rows = []
+    for k, r, n, paper_ms in PAPER_FFT_MS:
+        f = Field(k, r)
+        x = to_device(gi.uniform_digits(k, r, n, gi.BASE_SEED + 6, 0), dev)
+        y = torch.empty_like(x)
+        ws = torch.empty(f.fft_workspace_size(n) // 8, dtype=torch.int64, device=dev)
+        for _ in range(200):
+            f.fft_forward(x, y=y, workspace=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(200):
+            f.fft_forward(x, y=y, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / 200 * 1e3
+        rows.append({"k": k, "r": "2^%d+2^%d" % (r.bit_length() - 1, (r & -r).bit_length() - 1), "N": n,
+                     "gpu_us": round(us, 2), "paper_cpu_ms": paper_ms, "ratio": round(paper_ms * 1e3 / us, 1)})
+        f.close()
+    return rows
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -380,9 +416,11 @@ def main():
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-bigint", action="store_true")
+    ap.add_argument("--no-paper-context", action="store_true")
     ap.add_argument("--bigint-words", type=int, default=2 ** 18)
     ap.add_argument("--served-requests", type=int, default=10000)
-    ap.add_argument("--served-loads", default="0.7", help="comma-separated fractions of the plain saturated rate")
+    ap.add_argument("--served-loads", default="0.5,0.7,0.9",
+                    help="comma-separated fractions of the plain saturated rate")
     ap.add_argument("--served-workspace-gib", type=int, default=16)
     ap.add_argument("--served-slots", type=int, default=2)
     ap.add_argument("--served-express-log2n", type=int, default=16,
@@ -521,6 +559,8 @@ def main():
                                    args.served_workspace_gib, args.served_slots, args.served_express_log2n)
     if not args.no_bigint:
         out["bigint"] = bigint_leg(torch, dev, args.bigint_words, 20)
+    if not args.no_paper_context:
+        out["paper_context"] = paper_context_leg(torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
     print(json.dumps(out), flush=True)
