@@ -111,7 +111,7 @@ def cpu_baseline(sample_log2: int):
 
 
 def batched_leg(torch, f, dev, reps: int):
-    """Config 3: 256 products over the k = 8 prime, transform sizes N_i drawn
+    """Batched workload: 256 products over the k = 8 prime, transform sizes N_i drawn
     uniformly from {16^2, 16^3, 16^4, 16^5} (log-uniform in N), la = lb = N_i / 2,
     uniform coefficients.  The stage grouping of every (size, batch class)
     either path uses is autotuned first (gfp_tune).  Times 256 separate
@@ -190,7 +190,7 @@ def batched_leg(torch, f, dev, reps: int):
 
 
 def served_leg(torch, dev, n_req: int, loads, workspace_gib: int, slots: int, express_log2n: int):
-    """Config 4: a stream of n_req product requests, each over the k = 8 or the
+    """Served workload: a stream of n_req product requests, each over the k = 8 or the
     k = 16 prime (fair coin), la = lb = floor(2^U), U uniform on [8, 19],
     Poisson arrivals.  The arrival rate is `load` times the saturated request
     rate of the plain path (all requests back to back, one gfp_polymul each,

@@ -36,8 +36,9 @@ def _run(params, la, lb, seed, edge=0.02):
     return F, a, b, c
 
 
-def test_config0_schoolbook(torch_mod):
-    """k = 8, la = lb = 2048 (transform size 16^3 = 4096)."""
+def test_degree_2048_schoolbook(torch_mod):
+    """k = 8, la = lb = 2048 (transform size 16^3 = 4096), every coefficient
+    against the schoolbook product."""
     F, a, b, c = _run(P8, 2048, 2048, gi.BASE_SEED + 0)
     want = T.polymul(to_ints(a, F.r), to_ints(b, F.r), F.p)
     got = to_ints(c, F.r)
@@ -52,13 +53,16 @@ def test_ragged_schoolbook(torch_mod, params, la, lb):
     assert to_ints(c, F.r) == T.polymul(to_ints(a, F.r), to_ints(b, F.r), F.p)
 
 
-@pytest.mark.parametrize("params,cfg", [(P8, 1), (P16, 2)], ids=["config1-k8", "config2-k16"])
-def test_full_size_sampled(torch_mod, params, cfg):
+@pytest.mark.parametrize("params,wl", [(P8, 1), (P16, 2)], ids=["k8-2e19", "k16-2e19"])
+def test_full_size_sampled(torch_mod, params, wl):
+    """la = lb = 2^19 (transform size 2^20): sampled coefficients by their
+    definition, and Schwartz-Zippel at random points (wl selects the seed of
+    the workload: 1 for the k = 8 prime, 2 for k = 16)."""
     la = lb = 2 ** 19
-    F, a, b, c = _run(params, la, lb, gi.BASE_SEED + cfg, edge=0.0005)
+    F, a, b, c = _run(params, la, lb, gi.BASE_SEED + wl, edge=0.0005)
     ai, bi = to_ints(a, F.r), to_ints(b, F.r)
-    g = random.Random(cfg)
-    cols = gi.sample_indices(la + lb - 1, 6, gi.BASE_SEED + cfg, 3, must=(0, 1, la - 1, la, la + lb - 2))
+    g = random.Random(wl)
+    cols = gi.sample_indices(la + lb - 1, 6, gi.BASE_SEED + wl, 3, must=(0, 1, la - 1, la, la + lb - 2))
     cv = to_ints(c[:, cols], F.r)
     for m, got in zip(cols, cv):
         assert got == T.polymul_coeff(ai, bi, m, F.p), m
