@@ -427,7 +427,7 @@ def main():
                     help="the last slot serves only transform sizes up to 2^this (0: no express slot)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (one transform does not span GPUs). "
+        print("bench.py measures one GPU: the library has no multi-GPU path (one transform does not span GPUs). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

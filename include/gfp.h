@@ -47,7 +47,7 @@ extern "C" {
 
 #define GFP_OK 0
 #define GFP_EINVAL 1       /* bad argument (null pointer, ld < n, size not allowed) */
-#define GFP_EUNSUPPORTED 2 /* field or size outside what this build implements */
+#define GFP_EUNSUPPORTED 2 /* field or size outside what the library implements */
 #define GFP_ENOMEM 3       /* device or host allocation failed */
 #define GFP_EAGAIN 4       /* request loop: no capacity right now */
 #define GFP_EDEVICE 5      /* HIP runtime error */
@@ -66,7 +66,7 @@ extern "C" {
 typedef struct gfp_field gfp_field;
 
 /* Create the field Z/pZ, p = r^k + 1 (section 2).  Host-only; touches no GPU.
- * k must be a power of two and r even; this build runs transforms for
+ * k must be a power of two and r even; the library runs transforms for
  * k in {8, 16} with r = 2^w + 2^u for (k, w, u) in {(8, 63, 34), (8, 59, 16),
  * (16, 62, 36), (16, 58, 10)} (Table 1 and Table testprimes).  p is checked
  * with a Miller-Rabin probable-prime test (12 fixed bases).
