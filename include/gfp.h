@@ -180,7 +180,9 @@ int gfp_polymul_batched_workspace_size(const gfp_field* f, uint32_t n, const gfp
  * (required with GFP_BATCH_GRAPH), or NULL for a stream-ordered allocation.
  * flags & GFP_BATCH_GRAPH: the launch sequence is captured into a hipGraph
  * on the first call with this exact argument list (descriptors, workspace,
- * stream) and replayed on later calls; stream must not be NULL.  Results
+ * stream) and plans, and replayed on later calls; stream must not be NULL.
+ * A field keeps at most 64 such graphs; capturing another evicts the oldest
+ * after synchronising the stream it was last launched on.  Results
  * do not depend on the batch composition (bit-identical to gfp_polymul).
  * Errors: GFP_EINVAL (bad descriptor, n == 0, NULL stream with
  * GFP_BATCH_GRAPH, workspace too small), GFP_EUNSUPPORTED, GFP_EDEVICE. */

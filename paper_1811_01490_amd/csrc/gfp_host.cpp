@@ -25,6 +25,7 @@ using gfp::Mont;
 namespace {
 
 const uint64_t kMaxLog2N = 25;
+const size_t kMaxGraphs = 64;  // captured batched-product graphs kept per field
 
 struct DevTables {
   uint32_t* fwd = nullptr;   // n/K entries: w^j
@@ -53,7 +54,16 @@ struct gfp_field {
   std::mutex mu;
   std::map<std::pair<int, uint64_t>, DevTables> tables;
   std::map<int, DevConsts> consts;
-  std::map<uint64_t, hipGraphExec_t> graphs;  // batched products, keyed by argument hash
+  // batched products captured as graphs, keyed by a hash of the argument
+  // list and the plan generation; at most kMaxGraphs, the oldest evicted
+  struct Graph {
+    hipGraphExec_t exec;
+    hipStream_t stream;
+    uint64_t seq;
+  };
+  std::map<uint64_t, Graph> graphs;
+  uint64_t graph_seq = 0;
+  uint64_t plan_gen = 0;  // bumped by every plan change
   // stage groupings: (log2 n, batch class, layout) -> launch codes (1: one
   // pass, 2: fused pair, 3: wide fused pair), set by gfp_plan_set /
   // gfp_tune; keys without an entry use default_plan
@@ -691,7 +701,7 @@ int gfp_field_destroy(gfp_field* f) {
     (void)hipSetDevice(kv.first);
     (void)hipFree(kv.second.one);
   }
-  for (auto& kv : f->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : f->graphs) (void)hipGraphExecDestroy(kv.second.exec);
   if (!f->tables.empty() || !f->consts.empty()) (void)hipSetDevice(dev);
   delete f;
   return GFP_OK;
@@ -953,13 +963,17 @@ int gfp_polymul_batched(const gfp_field* cf, uint32_t n, const gfp_polymul_desc*
   int dev = 0;
   (void)hipGetDevice(&dev);
   key = hash_bytes(key, &dev, sizeof(dev));
-  hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(f->mu);
+    key = hash_bytes(key, &f->plan_gen, sizeof(f->plan_gen));  // a new plan means a new launch sequence
     auto it = f->graphs.find(key);
-    if (it != f->graphs.end()) exec = it->second;
+    if (it != f->graphs.end()) {
+      // launched under the lock, so an eviction cannot destroy it in between
+      return hip_status(hipGraphLaunch(it->second.exec, st));
+    }
   }
-  if (!exec) {
+  hipGraphExec_t exec = nullptr;
+  {
     hipError_t he = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (he != hipSuccess) return hip_status(he);
     rc = enqueue_batch(f, plan, w, st);
@@ -974,13 +988,23 @@ int gfp_polymul_batched(const gfp_field* cf, uint32_t n, const gfp_polymul_desc*
     (void)hipGraphDestroy(g);
     if (he != hipSuccess) return hip_status(he);
     std::lock_guard<std::mutex> lk(f->mu);
-    auto ins = f->graphs.emplace(key, exec);
-    if (!ins.second) {  // another thread captured the same list meanwhile
+    auto it = f->graphs.find(key);
+    if (it != f->graphs.end()) {  // another thread captured the same list meanwhile
       (void)hipGraphExecDestroy(exec);
-      exec = ins.first->second;
+      return hip_status(hipGraphLaunch(it->second.exec, st));
     }
+    if (f->graphs.size() >= kMaxGraphs) {
+      // evict the oldest; its last launch must have finished first
+      auto old = f->graphs.begin();
+      for (auto j = f->graphs.begin(); j != f->graphs.end(); ++j)
+        if (j->second.seq < old->second.seq) old = j;
+      (void)hipStreamSynchronize(old->second.stream);
+      (void)hipGraphExecDestroy(old->second.exec);
+      f->graphs.erase(old);
+    }
+    f->graphs.emplace(key, gfp_field::Graph{exec, st, ++f->graph_seq});
+    return hip_status(hipGraphLaunch(exec, st));
   }
-  return hip_status(hipGraphLaunch(exec, st));
 }
 
 int gfp_elementwise(const gfp_field* cf, int op, const uint64_t* x, uint64_t ld_x, const uint64_t* y, uint64_t ld_y,
@@ -1078,6 +1102,7 @@ int gfp_plan_set(gfp_field* f, uint64_t n, uint64_t nvec, int layout, const char
   if (!text || !*text) {
     std::lock_guard<std::mutex> g(f->mu);
     f->plans.erase(key);
+    ++f->plan_gen;
     return GFP_OK;
   }
   std::vector<int> plan;
@@ -1089,6 +1114,7 @@ int gfp_plan_set(gfp_field* f, uint64_t n, uint64_t nvec, int layout, const char
   if (!plan_valid(f, log2n, e, plan)) return GFP_EINVAL;
   std::lock_guard<std::mutex> g(f->mu);
   f->plans[key] = plan;
+  ++f->plan_gen;
   return GFP_OK;
 }
 
@@ -1162,6 +1188,7 @@ int gfp_tune(gfp_field* f, uint64_t n, uint64_t nvec, int layout, void* stream, 
   {
     std::lock_guard<std::mutex> g(f->mu);
     f->plans[std::make_tuple(log2n, batch_class(nvec), layout)] = best_plan;
+    ++f->plan_gen;
   }
   if (us) *us = best_us;
   if (best) {

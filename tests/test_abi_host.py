@@ -192,3 +192,29 @@ def test_bigint_sizes():
     assert f.bigint_mul_workspace_size(2 ** 18, 2 ** 18) > big
     with pytest.raises(gfp.GFPError):
         f.bigint_mul_workspace_size(2 ** 25, 2 ** 25)
+
+
+def test_plan_cache_round_trip(tmp_path):
+    """Plans exported to the JSON cache come back into a fresh field object;
+    entries of another architecture or field are not applied."""
+    _lib()
+    from paper_1811_01490_amd import autotune
+
+    em = gfp.LAYOUT_ELEMENT_MAJOR
+    f = gfp.Field(**P8)
+    f.set_plan(2 ** 20, "1121")
+    f.set_plan(2 ** 20, "212", nvec=16, layout=em)
+    f.set_plan(4096, "w1", nvec=100, layout=em)
+    keys = [(2 ** 20, 1, 0), (2 ** 20, 16, em), (4096, 100, em), (256, 1, 0)]
+    entries = autotune.export_plans(f, keys)
+    assert entries == {"1048576|0|0": "1121", "1048576|2|1": "212", "4096|3|1": "w1", "256|0|0": "2"}
+    path = str(tmp_path / "plans.json")
+    autotune.save(path, f, entries, arch="gfx950")
+    g = gfp.Field(**P8)
+    assert g.plan(2 ** 20) == "w21"  # default before loading
+    assert autotune.load(path, g, arch="gfx942") == 0  # another architecture
+    assert autotune.load(path, gfp.Field(**P16), arch="gfx950") == 0  # another field
+    assert autotune.load(path, g, arch="gfx950") == 4
+    assert g.plan(2 ** 20) == "1121" and g.plan(2 ** 20, nvec=9, layout=em) == "212"
+    assert g.plan(4096, nvec=64, layout=em) == "w1" and g.plan(256) == "2"
+    assert autotune.batch_class(1) == 0 and autotune.batch_class(7) == 1 and autotune.batch_class(63) == 2

@@ -86,3 +86,40 @@ def test_batched_graph_replays(torch_mod):
             stream.synchronize()
             for i, c in enumerate(outs):
                 assert to_ints(to_host(c), F.r) == want[i], (rep, i)
+
+
+def test_graph_cache_bound_and_plan_changes(torch_mod):
+    """More distinct argument lists than the cache keeps (so old graphs are
+    evicted), and a plan change between replays: every call still gives the
+    single-product results."""
+    import torch
+
+    from paper_1811_01490_amd import Field, to_host
+    from paper_1811_01490_amd.gfp import LAYOUT_ELEMENT_MAJOR
+
+    f = Field(P8["k"], P8["r"])
+    sizes = [(100, 60), (1500, 1000), (7, 9)]
+    _, dev = _batch(P8, sizes, gi.BASE_SEED + 302)
+    ref = [to_host(f.polymul(a, b)) for a, b in dev]
+    n_out = sum(a.shape[1] + b.shape[1] - 1 for a, b in dev)
+    pool = torch.zeros((8, n_out + 80), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.Stream()
+    ws = None
+    for call in range(70):  # 70 distinct output offsets -> 70 argument lists
+        if call == 40:
+            f.set_plan(4096, "111", nvec=2, layout=LAYOUT_ELEMENT_MAJOR)
+        outs, off = [], call
+        for a, b in dev:
+            n = a.shape[1] + b.shape[1] - 1
+            outs.append(pool[:, off:off + n])
+            off += n
+        descs = f.batch_descs([(a, b, c) for (a, b), c in zip(dev, outs)])
+        if ws is None:
+            ws = torch.empty(f.polymul_batched_workspace_size(descs) // 8 + 1, dtype=torch.int64, device="cuda")
+        with torch.cuda.stream(stream):
+            f.polymul_batched(descs, workspace=ws, graph=True, stream=stream)
+            if call in (0, 39, 41, 69):
+                f.polymul_batched(descs, workspace=ws, graph=True, stream=stream)  # a replay
+        stream.synchronize()
+        for i, c in enumerate(outs):
+            assert np.array_equal(to_host(c.contiguous()), ref[i]), (call, i)
