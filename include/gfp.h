@@ -326,12 +326,15 @@ typedef struct gfp_server_stats {
  * express_log2n > 40 or with fewer than 2 slots), GFP_ENOMEM, GFP_EDEVICE. */
 int gfp_server_create(const gfp_server_config* cfg, gfp_server** out);
 
-/* Queue one request; returns at once with a ticket (1, 2, ...).  The request
- * is copied; the buffers it names stay the caller's and must not be touched
- * until the ticket is done.  Errors: GFP_EINVAL (bad pointers or lengths),
- * GFP_EUNSUPPORTED (field or size), GFP_ENOMEM (its workspace exceeds one
- * slot's share, so it could never run), GFP_EAGAIN (max_pending requests are
- * waiting; try again later), GFP_ECANCELED (the server is shutting down). */
+/* Queue one request; returns at once with a ticket (1, 2, ...), except that
+ * the first request of a transform size not yet used with this field on the
+ * server's device builds that size's twiddle tables first, on the caller's
+ * thread.  The request is copied; the buffers it names stay the caller's and
+ * must not be touched until the ticket is done.  Errors: GFP_EINVAL (bad
+ * pointers or lengths), GFP_EUNSUPPORTED (field or size), GFP_ENOMEM (its
+ * workspace exceeds one slot's share, so it could never run, or no device
+ * memory for the tables), GFP_EAGAIN (max_pending requests are waiting; try
+ * again later), GFP_ECANCELED (the server is shutting down), GFP_EDEVICE. */
 int gfp_server_submit(gfp_server* s, const gfp_request* req, uint64_t* ticket);
 
 /* If the request is done, write its result, forget the ticket and return

@@ -6,7 +6,9 @@
 // row.  So k = 8 interleaves two elements per row and k = 16 uses one row per
 // element.  Multiplying by r^i (section 2.3: a cyclic shift of the digits with
 // the wrapped digits negated, since r^k = -1) is then a DPP row rotation by
-// i * GPL lanes plus a per-lane sign, with no data leaving the row.
+// i * GPL lanes plus a per-lane sign, with no data leaving the row.  For
+// k = 32 an element spans half a wavefront (lane (l & 32) | d holds digit d)
+// and the rotations are ds_bpermute lane permutations within the half.
 //
 // Digits in flight are "lazy": a digit is any integer, the element being
 // sum_d t_d r^d mod p (f_x(r) in the polynomial view of section 2).  Lazy
@@ -53,15 +55,18 @@ constexpr int brev(int i, int bits) {
 // ------------------------------------------------------------------------
 template <int KD>
 struct Geo {
-  static_assert(KD == 8 || KD == 16, "k must be 8 or 16");
-  static constexpr int GPL = 16 / KD;  // elements per DPP row
-  static constexpr int G = 64 / KD;    // elements per wavefront
-  static constexpr int KB = 2 * KD;    // base-case DFT size K = 2k
+  static_assert(KD == 8 || KD == 16 || KD == 32, "k must be 8, 16 or 32");
+  static constexpr bool ROW = KD <= 16;          // an element inside one DPP row
+  static constexpr int GPL = ROW ? 16 / KD : 1;  // elements per DPP row (k <= 16)
+  static constexpr int G = 64 / KD;              // elements per wavefront
+  static constexpr int KB = 2 * KD;              // base-case DFT size K = 2k
   __device__ static __forceinline__ int lane() { return (int)(threadIdx.x & 63); }
-  __device__ static __forceinline__ int digit(int l) { return (l & 15) / GPL; }
-  __device__ static __forceinline__ int group(int l) { return (l >> 4) * GPL + (l & 15) % GPL; }
+  __device__ static __forceinline__ int digit(int l) { return ROW ? (l & 15) / GPL : (l & 31); }
+  __device__ static __forceinline__ int group(int l) { return ROW ? (l >> 4) * GPL + (l & 15) % GPL : (l >> 5); }
   // lane holding digit d of the same element as lane l
-  __device__ static __forceinline__ int lane_of(int l, int d) { return (l & 0x30) | (d * GPL) | ((l & 15) % GPL); }
+  __device__ static __forceinline__ int lane_of(int l, int d) {
+    return ROW ? ((l & 0x30) | (d * GPL) | ((l & 15) % GPL)) : ((l & 32) | d);
+  }
 };
 
 // DPP row rotate: lane i of a row takes the value of lane (i - N) mod 16.
@@ -71,6 +76,21 @@ __device__ __forceinline__ uint32_t row_ror(uint32_t v) {
     return v;
   } else {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x120 + (N & 15), 0xF, 0xF, false);
+  }
+}
+
+// Digit rotation: the lane holding digit m of an element takes the value of
+// the lane holding digit (m - N) mod k of the same element.
+template <int KD, int N>
+__device__ __forceinline__ uint32_t dig_rot(uint32_t v) {
+  constexpr int n = N & (KD - 1);
+  if constexpr (n == 0) {
+    return v;
+  } else if constexpr (Geo<KD>::ROW) {
+    return row_ror<n * Geo<KD>::GPL>(v);
+  } else {
+    const int l = (int)(threadIdx.x & 63);
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(((l & 32) | ((l - n) & 31)) << 2, (int)v);
   }
 }
 
@@ -96,11 +116,25 @@ __device__ __forceinline__ L96 l96_sub(L96 a, L96 b) {
   return c;
 }
 __device__ __forceinline__ L96 l96_sel(bool c, L96 a, L96 b) { return L96{c ? a.lo : b.lo, c ? a.hi : b.hi}; }
-template <int N>
-__device__ __forceinline__ L96 l96_ror(L96 a) {
-  uint32_t w0 = row_ror<N>((uint32_t)a.lo), w1 = row_ror<N>((uint32_t)(a.lo >> 32));
-  uint32_t w2 = row_ror<N>((uint32_t)a.hi);
+template <int KD, int N>
+__device__ __forceinline__ L96 l96_rot(L96 a) {
+  uint32_t w0 = dig_rot<KD, N>((uint32_t)a.lo), w1 = dig_rot<KD, N>((uint32_t)(a.lo >> 32));
+  uint32_t w2 = dig_rot<KD, N>((uint32_t)a.hi);
   return L96{((uint64_t)w1 << 32) | w0, (int32_t)w2};
+}
+// a r^e for a run-time exponent 0 <= e < 2k (r^k = -1): lane m takes digit
+// (m - e) mod k from the lane holding it, negated when it wrapped (m < e mod
+// k) and once more when e >= k.
+template <int KD>
+__device__ __forceinline__ L96 l96_mul_rpow(L96 a, int e, int l, int m) {
+  const int n = e & (KD - 1);
+  const int src = Geo<KD>::lane_of(l, (m - n) & (KD - 1));
+  const uint32_t w0 = (uint32_t)__shfl((int)(uint32_t)a.lo, src, 64);
+  const uint32_t w1 = (uint32_t)__shfl((int)(uint32_t)(a.lo >> 32), src, 64);
+  const uint32_t w2 = (uint32_t)__shfl((int)a.hi, src, 64);
+  const L96 b{((uint64_t)w1 << 32) | w0, (int32_t)w2};
+  const bool neg = (m < n) != ((e & KD) != 0);
+  return neg ? l96_sub(L96{0, 0}, b) : b;
 }
 __device__ __forceinline__ L96 l96_from_i128(i128 v) { return L96{(uint64_t)v, (int32_t)(uint32_t)((u128)v >> 64)}; }
 __device__ __forceinline__ i128 l96_to_i128(L96 a) { return ((i128)a.hi << 64) + (i128)a.lo; }
@@ -118,7 +152,6 @@ __device__ __forceinline__ i128 l96_to_i128(L96 a) { return ((i128)a.hi << 64) +
 // ------------------------------------------------------------------------
 template <int KD, bool INV, int EXP>
 __device__ __forceinline__ void bfly(L96& a, L96& b, int m) {
-  constexpr int GPL = Geo<KD>::GPL;
   if constexpr (EXP == 0) {
     L96 s = l96_add(a, b), d = l96_sub(a, b);
     a = s;
@@ -127,7 +160,7 @@ __device__ __forceinline__ void bfly(L96& a, L96& b, int m) {
     // forward: r^EXP = rotate by EXP, negate digits m < EXP.
     // inverse: r^-EXP = -r^(KD-EXP) = rotate by KD-EXP, negate digits m >= KD-EXP.
     constexpr int ROT = INV ? (KD - EXP) : EXP;
-    L96 bp = l96_ror<ROT * GPL>(b);
+    L96 bp = l96_rot<KD, ROT>(b);
     bool f = INV ? (m >= ROT) : (m < ROT);
     L96 s = l96_add(a, bp), d = l96_sub(a, bp);
     a = l96_sel(f, d, s);
@@ -292,8 +325,70 @@ struct Field {
   static constexpr uint64_t R = (1ull << W) + (1ull << U);
   static constexpr int SA = 64 - W;      // 2^64 = 2^SA * r - 2^SB
   static constexpr int SB = 64 - W + U;
-  static_assert(W >= 56 && W <= 63 && U >= 8 && U + 8 <= W, "unsupported radix shape");
+  // SPLIT: U close to W, so a fold with 2^64 = 2^SA r - 2^SB gains only
+  // W - U bits a round.  Then r = 2^U d with d = 2^(W-U) + 1, and an integer
+  // t splits exactly as t = q r + rho, rho = (t_h mod d) 2^U + t_l in [0, r),
+  // where t_h = floor(t / 2^U), t_l = t mod 2^U and q = floor(t_h / d).
+  // Built for the k = 32 prime of Table 1, r = 2^62 + 2^56 (d = 65).
+  static constexpr bool SPLIT = U + 8 > W;
+  static_assert(W >= 56 && W <= 63 && U >= 8 && (U + 8 <= W || (W == 62 && U == 56)), "unsupported radix shape");
 };
+
+// SPLIT division for r = 2^56 * 65.  65 is odd and 2^12 = 1 (mod 65), so
+// n mod 65 is the sum of n's 12-bit chunks (words weighted by 2^32 = 61 and
+// 2^64 = 16 mod 65) reduced once, and the quotient of the exact multiple
+// n - (n mod 65) is its product with 65^-1 mod 2^96.
+__device__ __forceinline__ uint32_t chunks12(uint32_t x) {
+  return (x >> 24) + ((x >> 12) & 0xFFFu) + (x & 0xFFFu);
+}
+
+// C = (c0, c1, c2, c3, c4) signed 160-bit (c4 carries the sign), |C| < 2^133:
+// C = Q r + T with 0 <= T < r.
+__device__ __forceinline__ void split_qr160(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t c4,
+                                            uint64_t& T, L96& Q) {
+  // n = floor(C / 2^56) + 65 * 2^78, in [0, 2^86): three words
+  const uint32_t n0 = __builtin_amdgcn_alignbit(c2, c1, 24);
+  const uint32_t n1 = __builtin_amdgcn_alignbit(c3, c2, 24);
+  const uint32_t n2 = __builtin_amdgcn_alignbit(c4, c3, 24) + (65u << 14);
+  // n mod 65 from t < 2^20, t = n (mod 65); floor(t / 65) = t ceil(2^30 / 65) >> 30
+  const uint32_t t = chunks12(n0) + 61u * chunks12(n1) + 16u * chunks12(n2);
+  const uint32_t qt = (uint32_t)(((uint64_t)t * 16519105u) >> 30);
+  const uint32_t rem = t - 65u * qt;
+  // q' = (n - rem) / 65 = (n - rem) 65^-1 mod 2^96
+  unsigned b;
+  const uint32_t m0 = __builtin_subc(n0, rem, 0u, &b);
+  const uint32_t m1 = __builtin_subc(n1, 0u, b, &b);
+  const uint32_t m2 = n2 - b;
+  constexpr uint32_t I0 = 0xC0FC0FC1u, I1 = 0x0FC0FC0Fu, I2 = 0xFC0FC0FCu;  // 65^-1 mod 2^96
+  const uint64_t pa = (uint64_t)m0 * I0;
+  const uint64_t pb = (uint64_t)m0 * I1 + (pa >> 32);
+  const uint64_t pc = (uint64_t)m1 * I0 + (uint32_t)pb;
+  const uint32_t q2 = (uint32_t)(pb >> 32) + (uint32_t)(pc >> 32) + m0 * I2 + m1 * I1 + m2 * I0;
+  // Q = q' - 2^78
+  Q.lo = ((uint64_t)(uint32_t)pc << 32) | (uint32_t)pa;
+  Q.hi = (int32_t)(q2 - (1u << 14));
+  T = ((uint64_t)((rem << 24) | (c1 & 0xFFFFFFu)) << 32) | c0;
+}
+
+// t = q r + rho for a lazy digit, |t| < 2^84.  Non-SPLIT shapes: q = t >> W
+// and rho = t - q r, true value in (-2^57, 2^W + 2^57).  SPLIT: exact,
+// 0 <= rho < r (t_h = t >> 56 has |t_h| < 2^28; floor(n / 65) for n < 2^31
+// is n ceil(2^38 / 65) >> 38).
+template <int KD, int W, int U>
+__device__ __forceinline__ void qr_split(L96 t, int64_t& q, uint64_t& rho) {
+  typedef Field<KD, W, U> F;
+  if constexpr (F::SPLIT) {
+    const int32_t th = (int32_t)(((uint32_t)t.hi << 8) | (uint32_t)(t.lo >> 56));
+    const uint32_t n = (uint32_t)(th + (65 << 23));
+    const uint32_t qp = (uint32_t)(((uint64_t)n * 4228890877u) >> 38);
+    const uint32_t rem = n - 65u * qp;
+    q = (int64_t)(int32_t)qp - (1 << 23);
+    rho = ((uint64_t)rem << 56) | (t.lo & ((1ull << 56) - 1));
+  } else {
+    q = ((int64_t)t.hi << (64 - W)) | (int64_t)(t.lo >> W);  // floor(t / 2^W)
+    rho = (t.lo & ((1ull << W) - 1)) - ((uint64_t)q << U);
+  }
+}
 
 // Limb form of y: yl[3t + c] = limb c of y_t.
 template <int KD>
@@ -333,7 +428,6 @@ __device__ __forceinline__ RotLane<KD> rot_lane(int rot, int m) {
 template <int KD, int W, int U>
 __device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<KD>& y, uint32_t s0, uint32_t s1,
                                         uint32_t s2, int m) {
-  constexpr int GPL = Geo<KD>::GPL;
   typedef Field<KD, W, U> F;
   constexpr int SA = F::SA, SB = F::SB;
   const uint32_t wrap = (m == 0) ? 0xFFFFFFFFu : 0u;
@@ -348,8 +442,8 @@ __device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<K
     a11 += (uint64_t)v1 * y1;
     a12 += (uint64_t)v1 * y2;
     if constexpr (t + 1 < KD) {
-      v0 = row_ror<GPL>(v0) ^ wrap;
-      v1 = row_ror<GPL>(v1) ^ wrap;
+      v0 = dig_rot<KD, 1>(v0) ^ wrap;
+      v1 = dig_rot<KD, 1>(v1) ^ wrap;
     }
   });
   // Cells at 32-bit positions, C = c0 + c1 2^32 + c2 2^64 + c3 2^96 - S 2^64:
@@ -378,6 +472,13 @@ __device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<K
   h0 = __builtin_subc(h0, s0, 0u, &cy);
   h1 = __builtin_subc(h1, s1, cy, &cy);
   h2 = h2 - s2 - cy;
+  if constexpr (F::SPLIT) {
+    uint64_t T;
+    L96 Qs;
+    split_qr160(l0, l1, h0, h1, h2, T, Qs);
+    const L96 nqs = l96_sub(L96{0, 0}, Qs);
+    return l96_add(l96(T), l96_rot<KD, 1>((m == KD - 1) ? nqs : Qs));
+  }
   // fold 1 (2^64 = a r - b): C = a H r + V, V = L - b H; keep V's low 64
   // bits (v0w, v1w) and Vh = V >> 64 (|Vh| < 2^45)
   uint32_t v0w, v1w, v2w, v3w;
@@ -401,7 +502,7 @@ __device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<K
   // Q_{m-1} into lane m; lane 0 takes -Q_{k-1}
   const L96 nq = l96_sub(L96{0, 0}, Q);
   const L96 qs = (m == KD - 1) ? nq : Q;
-  return l96_add(Tm, l96_ror<GPL>(qs));
+  return l96_add(Tm, l96_rot<KD, 1>(qs));
 }
 
 // Twiddle entry layout (u32 words): 3k limbs of the digits, then for
@@ -542,16 +643,15 @@ __device__ __forceinline__ L96 mul_data(uint64_t x, const uint64_t (&yd)[KD], in
 // one lane up (lane 0 takes -q_{k-1}, since r^k = -1).
 template <int KD, int W, int U>
 __device__ __forceinline__ uint64_t seminorm(L96 t, int m) {
-  constexpr int GPL = Geo<KD>::GPL;
   typedef Field<KD, W, U> F;
-  int64_t q = ((int64_t)t.hi << (64 - W)) | (int64_t)(t.lo >> W);  // floor(t / 2^W)
-  // rho = t - q 2^W - q 2^U, true value in (-2^57, 2^W + 2^57)
-  uint64_t rho = (t.lo & ((1ull << W) - 1)) - ((uint64_t)q << U);
+  int64_t q;
+  uint64_t rho;  // true value in (-2^57, 2^W + 2^57)
+  qr_split<KD, W, U>(t, q, rho);
   const bool low = (rho + (1ull << 57)) < (3ull << 57);  // rho < 2^58
   rho += low ? F::R : 0ull;
   q -= low ? 1 : 0;
   int32_t qi = (int32_t)q;
-  int32_t qin = (int32_t)row_ror<GPL>((uint32_t)qi);
+  int32_t qin = (int32_t)dig_rot<KD, 1>((uint32_t)qi);
   qin = (m == 0) ? -qin : qin;
   return rho + (uint64_t)(int64_t)qin;
 }
@@ -561,22 +661,24 @@ __device__ __forceinline__ uint64_t seminorm(L96 t, int m) {
 // take part in the lane exchanges but their result is meaningless.
 template <int KD, int W, int U>
 __device__ __forceinline__ uint64_t canonicalize(L96 t, int l, int m) {
-  constexpr int GPL = Geo<KD>::GPL;
   typedef Field<KD, W, U> F;
   // exact t = q r + rho, 0 <= rho < r
-  int64_t q = ((int64_t)t.hi << (64 - W)) | (int64_t)(t.lo >> W);
-  uint64_t rho = (t.lo & ((1ull << W) - 1)) - ((uint64_t)q << U);  // true in (-2^57, 2^W + 2^57)
-  const uint64_t off = 1ull << 57;
-  if (rho + off < off) {  // rho < 0
-    rho += F::R;
-    q -= 1;
-  } else if (rho + off >= F::R + off) {  // rho >= r
-    rho -= F::R;
-    q += 1;
+  int64_t q;
+  uint64_t rho;  // true value in (-2^57, 2^W + 2^57)
+  qr_split<KD, W, U>(t, q, rho);
+  if constexpr (!F::SPLIT) {
+    const uint64_t off = 1ull << 57;
+    if (rho + off < off) {  // rho < 0
+      rho += F::R;
+      q -= 1;
+    } else if (rho + off >= F::R + off) {  // rho >= r
+      rho -= F::R;
+      q += 1;
+    }
   }
   // v_m = rho_m + q_{m-1}; v_0 = rho_0 - q_{k-1}.  Now X = sum v_m r^m exactly.
   int32_t qi = (int32_t)q;
-  int32_t qin = (int32_t)row_ror<GPL>((uint32_t)qi);
+  int32_t qin = (int32_t)dig_rot<KD, 1>((uint32_t)qi);
   qin = (m == 0) ? -qin : qin;
   uint64_t v = rho + (uint64_t)(int64_t)qin;  // true value in (-2^27, r + 2^27)
   const uint64_t NEG = 0ull - (1ull << 28);
@@ -588,7 +690,7 @@ __device__ __forceinline__ uint64_t canonicalize(L96 t, int l, int m) {
     const int c = isneg ? -1 : (isbig ? 1 : 0);
     if (!__any(c != 0)) break;
     v = v - (uint64_t)(int64_t)c * F::R;
-    int cin = (int)row_ror<GPL>((uint32_t)c);
+    int cin = (int)dig_rot<KD, 1>((uint32_t)c);
     if (m == 0) cin = 0;
     if (m == KD - 1) top += c;
     v += (uint64_t)(int64_t)cin;
@@ -604,7 +706,7 @@ __device__ __forceinline__ uint64_t canonicalize(L96 t, int l, int m) {
       const int c = isneg ? -1 : (isbig ? 1 : 0);
       if (!__any(c != 0)) break;
       v = v - (uint64_t)(int64_t)c * F::R;
-      int cin = (int)row_ror<GPL>((uint32_t)c);
+      int cin = (int)dig_rot<KD, 1>((uint32_t)c);
       if (m == 0) cin = 0;
       if (m == KD - 1) top2 += c;
       v += (uint64_t)(int64_t)cin;

@@ -40,6 +40,10 @@ struct PassArgs {
   // table of w^(K i) (w^-(K i) for the inverse), i < N/K: the twiddles of
   // every radix-K pass but the last, without a rotation
   const uint32_t* tw2 = nullptr;
+  // set with scale (inverse pass 0): the pass input is the pointwise product
+  // in[i] in2[i] of two transforms; in2 has the strides of in and its digits
+  // contiguous (sd_in 1), and the product is then multiplied by tw[0]
+  const uint64_t* in2 = nullptr;
 };
 // Largest span a launch supports for k (0 if none beyond 1).
 bool span2_supported(int k);
@@ -99,5 +103,9 @@ inline uint64_t chunk_cap(uint64_t per_request_bytes) {
 
 // words per twiddle-table entry (see TwLayout in gfp_device.hpp)
 inline int tw_words(int k) { return (6 * k + 6) & ~3; }
+
+// Builds (once per device and size) the twiddle tables of transforms of size
+// n on the current device; a status code of gfp.h.
+int prepare_tables(const gfp_field* f, uint64_t n);
 
 }  // namespace gfpk

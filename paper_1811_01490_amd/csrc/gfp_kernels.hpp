@@ -40,7 +40,37 @@ __device__ __forceinline__ uint64_t xcd_block(bool on) {
 // ---------------------------------------------------------------------------
 // MODE_PLAIN: twiddles from the table (forward or inverse table).
 // MODE_SCALE: every slot multiplied by one constant (inverse pass 0: 1/N).
-enum { MODE_PLAIN = 0, MODE_SCALE = 1 };
+// MODE_PRODUCT: the slots are the pointwise products of two transforms
+// (section 1: the product of polynomials is the inverse transform of the
+// product of their transforms), each then multiplied by the constant, so
+// the pointwise step of a polynomial product costs no launch of its own.
+enum { MODE_PLAIN = 0, MODE_SCALE = 1, MODE_PRODUCT = 2 };
+
+// MODE_SCALE / MODE_PRODUCT slot value.  x: this lane's digit of the first
+// factor; y: the second factor's element, k contiguous digits (every lane
+// of the element reads all of them, 16 bytes at a time); c: the constant
+// (UC: its limbs read with scalar loads into SGPRs, 3k of them).
+template <int KD, int W, int U, int MODE, bool UC = false>
+__device__ __forceinline__ L96 first_slot(uint64_t x, const uint64_t* __restrict__ y, const uint32_t* __restrict__ c,
+                                          int l, int m) {
+  if constexpr (MODE == MODE_PRODUCT) {
+    slot_fence();
+    uint64_t yd[KD];
+    const ulonglong2* y2 = reinterpret_cast<const ulonglong2*>(y);
+    static_for<KD / 2>([&](auto T) {
+      constexpr int i = decltype(T)::value;
+      const ulonglong2 v = y2[i];
+      yd[2 * i] = v.x;
+      yd[2 * i + 1] = v.y;
+    });
+    x = seminorm<KD, W, U>(mul_data<KD, W, U>(x, yd, m), m);
+  }
+  if constexpr (UC) {
+    return mul_twiddle_uniform<KD, W, U>(x, c, 0, l, m);
+  } else {
+    return mul_twiddle<KD, W, U>(x, c, 0, l, m);
+  }
+}
 
 // UNIF: the K^(e-1-s) groups sharing one twiddle base a are spread over
 // whole wavefronts (group g of a wavefront is j = a + (qb G + g) Ns), so the
@@ -50,8 +80,8 @@ enum { MODE_PLAIN = 0, MODE_SCALE = 1 };
 // T2: the twiddles come from the table of w^(K i) without rotations (every
 // pass but the last); otherwise from the table of w^j with r^rho rotations.
 template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T2>
-__global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
-                                              uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
+__global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
+                                              uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
                                               const uint32_t* __restrict__ tw, const uint32_t* __restrict__ tw2,
                                               int log2n, int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin,
                                               uint64_t vout) {
@@ -90,22 +120,31 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
     vec = 0;
   }
   in += vec * vin;
+  if constexpr (MODE == MODE_PRODUCT) in2 += vec * vin;
   out += vec * vout;
 
+  // all slots loaded up front, except for the pointwise product, whose
+  // second operand loads already keep enough reads in flight
   uint64_t x[KB];
-  static_for<KB>([&](auto T) {
-    constexpr int t = decltype(T)::value;
-    x[t] = in[(uint64_t)m * sd_in + (jj + (uint64_t)t * nk) * se_in];
-  });
+  if constexpr (MODE != MODE_PRODUCT) {
+    static_for<KB>([&](auto T) {
+      constexpr int t = decltype(T)::value;
+      x[t] = in[(uint64_t)m * sd_in + (jj + (uint64_t)t * nk) * se_in];
+    });
+  }
 
   // Twiddle of slot t: w_L^(a t) = r^rho w^(c N/L) with rho = (a t) / Ns,
   // c = (a t) mod Ns.  r^rho is a digit rotation: lane m takes digit
   // (m - rho) mod k of the element from the lane holding it.
   L96 v[KB];
-  if constexpr (MODE == MODE_SCALE) {
+  if constexpr (MODE != MODE_PLAIN) {
     static_for<KB>([&](auto T) {
       constexpr int t = decltype(T)::value;
-      v[t] = mul_twiddle<KD, W, U>(x[t], tw, 0, l, m);
+      if constexpr (MODE == MODE_PRODUCT) {
+        slot_fence();
+        x[t] = in[(uint64_t)m * sd_in + (jj + (uint64_t)t * nk) * se_in];
+      }
+      v[t] = first_slot<KD, W, U, MODE, (KD <= 16)>(x[t], in2 + (jj + (uint64_t)t * nk) * se_in, tw, l, m);
     });
   } else {
     v[0] = l96(x[0]);
@@ -160,6 +199,112 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
 }
 
 // ---------------------------------------------------------------------------
+// one radix-K pass for k = 32 (K = 64): DFT_64 as DFT_8 x DFT_8 through LDS
+// ---------------------------------------------------------------------------
+// 64 lazy slots per lane do not fit in registers, so the base case is split
+// once more by the same factorisation (section 4.1), now inside DFT_64 where
+// every twiddle is a power of w_64 = r: with t = t1 + 8 t2 and u = u2 + 8 u1,
+//   X[u2 + 8 u1] = sum_t1 r^(8 t1 u1) r^(t1 u2) sum_t2 x[t1 + 8 t2] r^(8 t2 u2).
+// A workgroup of 4 wavefronts takes two groups j (one per half wavefront).
+// Round A: wavefront w, for t1 = w and w + 4, loads slots t1 + 8 t2, applies
+// the pass twiddle (as k_pass), runs DFT_8 over t2 (root r^8), multiplies
+// output u2 by r^(t1 u2) and stores it, semi-normalised, to LDS.  Round B:
+// for u2 = w and w + 4, DFT_8 over t1 and output u = u2 + 8 u1 goes to
+// (j - a) K + a + u Ns.
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2>
+__global__ __launch_bounds__(256) void k_pass_k32(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
+                                                  uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out,
+                                                  uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
+                                                  const uint32_t* __restrict__ tw2, int log2n, int log2ns,
+                                                  uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout) {
+  static_assert(KD == 32, "the split base case is built for k = 32");
+  typedef Geo<KD> Gm;
+  constexpr int KB = Gm::KB;
+  constexpr int LOGKB = ilog2(KB);
+  __shared__ uint64_t lds[KB * 64];  // [u2][t1][lane], 32 KiB
+  const int l = Gm::lane();
+  const int m = Gm::digit(l);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int log2nk = log2n - LOGKB;
+  const uint64_t nk = ngroups;
+  const uint64_t J = (uint64_t)blockIdx.x * 2 + (uint64_t)Gm::group(l);  // group over all vectors
+  uint64_t vec = J >> log2nk;
+  uint64_t j = J & (nk - 1);
+  const bool active = vec < nvec;
+  if (!active) {
+    vec = 0;
+    j = 0;
+  }
+  const uint64_t ns = 1ull << log2ns;
+  const uint64_t a = j & (ns - 1);
+  in += vec * vin;
+  if constexpr (MODE == MODE_PRODUCT) in2 += vec * vin;
+  out += vec * vout;
+
+  // ---- round A
+  static_for<2>([&](auto H) {
+    const int t1 = w + 4 * decltype(H)::value;
+    L96 v[8];
+    static_for<8>([&](auto T) {
+      constexpr int t2 = decltype(T)::value;
+      const uint64_t t = (uint64_t)(t1 + 8 * t2);
+      const uint64_t e = j + t * nk;
+      const uint64_t x = in[(uint64_t)m * sd_in + e * se_in];
+      slot_fence();
+      if constexpr (MODE != MODE_PLAIN) {
+        v[t2] = first_slot<KD, W, U, MODE>(x, in2 + e * se_in, tw, l, m);
+      } else if constexpr (T2) {
+        // w^(a t N / (K Ns)) = entry (a t) N / (K^2 Ns) of the w^(K i) table
+        const int sh2 = log2n - 2 * LOGKB - log2ns;
+        v[t2] = (log2ns == 0) ? l96(x) : mul_entry<KD, W, U>(x, tw2 + ((a * t) << sh2) * TwLayout<KD>::WORDS, m);
+      } else {
+        if (log2ns == 0) {
+          v[t2] = l96(x);
+        } else {
+          const int shift = log2n - log2ns - LOGKB;
+          const uint64_t at = a * t;
+          const int rho = (int)(at >> log2ns);
+          const uint64_t c = at & (ns - 1);
+          const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
+          v[t2] = mul_twiddle<KD, W, U>(x, tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
+        }
+      }
+    });
+    dft_pow2<KD, INV, 3>(v, m);
+    static_for<8>([&](auto V) {
+      constexpr int u2 = decltype(V)::value;
+      const int e = (t1 * u2) & (2 * KD - 1);
+      const L96 y = l96_mul_rpow<KD>(v[u2], INV ? ((2 * KD - e) & (2 * KD - 1)) : e, l, m);
+      lds[(u2 * 8 + t1) * 64 + l] = seminorm<KD, W, U>(y, m);
+    });
+  });
+  __syncthreads();
+
+  // ---- round B
+  const uint64_t obase = (j - a) * KB + a;
+  static_for<2>([&](auto H) {
+    const int u2 = w + 4 * decltype(H)::value;
+    L96 v[8];
+    static_for<8>([&](auto T) {
+      constexpr int t1 = decltype(T)::value;
+      v[t1] = l96(lds[(u2 * 8 + t1) * 64 + l]);
+    });
+    dft_pow2<KD, INV, 3>(v, m);
+    static_for<8>([&](auto V) {
+      constexpr int u1 = decltype(V)::value;
+      const uint64_t u = (uint64_t)(u2 + 8 * u1);
+      uint64_t d;
+      if constexpr (LAST) {
+        d = canonicalize<KD, W, U>(v[u1], l, m);
+      } else {
+        d = seminorm<KD, W, U>(v[u1], m);
+      }
+      if (active) out[(uint64_t)m * sd_out + (obase + u * ns) * se_out] = d;
+    });
+  });
+}
+
+// ---------------------------------------------------------------------------
 // first pass of a transform of size N = R K^e, 1 < R = 2^LR < K
 // ---------------------------------------------------------------------------
 // Radix R with Ns = 1 (no twiddles): for every j < N/R the R elements
@@ -168,8 +313,8 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, u
 // factorisation N = N1 N2 with the base case at powers of r).  MODE_SCALE
 // multiplies every element by the 1/N entry first (inverse transform).
 template <int KD, int W, int U, bool INV, int MODE, int LR>
-__global__ __launch_bounds__(256) void k_pass_r(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
-                                                uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
+__global__ __launch_bounds__(256) void k_pass_r(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
+                                                uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
                                                 const uint32_t* __restrict__ tw, int log2n, uint64_t nvec,
                                                 uint64_t vin, uint64_t vout) {
   typedef Geo<KD> Gm;
@@ -184,13 +329,14 @@ __global__ __launch_bounds__(256) void k_pass_r(const uint64_t* __restrict__ in,
   const uint64_t j = active ? (J & ((1ull << log2nr) - 1)) : 0;
   if (!active) vec = 0;
   in += vec * vin;
+  if constexpr (MODE == MODE_PRODUCT) in2 += vec * vin;
   out += vec * vout;
   L96 v[R];
   static_for<R>([&](auto T) {
     constexpr int t = decltype(T)::value;
     const uint64_t x = in[(uint64_t)m * sd_in + (j + ((uint64_t)t << log2nr)) * se_in];
-    if constexpr (MODE == MODE_SCALE) {
-      v[t] = mul_twiddle<KD, W, U>(x, tw, 0, l, m);
+    if constexpr (MODE != MODE_PLAIN) {
+      v[t] = first_slot<KD, W, U, MODE, (KD <= 16)>(x, in2 + (j + ((uint64_t)t << log2nr)) * se_in, tw, l, m);
     } else {
       v[t] = l96(x);
     }
@@ -227,8 +373,8 @@ struct Span2Geo {
 // T2B: the second pass is not the last one and takes its twiddles from the
 // table of w^(K i); the first pass never is the last and always does.
 template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B>
-__global__ __launch_bounds__(256) void k_pass2(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
-                                               uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
+__global__ __launch_bounds__(256) void k_pass2(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
+                                               uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
                                                const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
                                                const uint32_t* __restrict__ tw2, int log2n, int log2ns, uint64_t nvec,
                                                uint64_t vin, uint64_t vout) {
@@ -253,6 +399,7 @@ __global__ __launch_bounds__(256) void k_pass2(const uint64_t* __restrict__ in, 
   }
   const uint64_t q = gq & ((1ull << log2nb) - 1);
   in += vec * vin;
+  if constexpr (MODE == MODE_PRODUCT) in2 += vec * vin;
   out += vec * vout;
   const uint64_t ns = 1ull << log2ns;
   const uint64_t a = q & (ns - 1);  // uniform over the wavefront
@@ -269,10 +416,10 @@ __global__ __launch_bounds__(256) void k_pass2(const uint64_t* __restrict__ in, 
     x[t] = in[(uint64_t)m * sd_in + (base + (uint64_t)t * n1) * se_in];
   });
   L96 v[KB];
-  if constexpr (MODE == MODE_SCALE) {
+  if constexpr (MODE != MODE_PLAIN) {
     static_for<KB>([&](auto T) {
       constexpr int t = decltype(T)::value;
-      v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw0, 0, l, m);
+      v[t] = first_slot<KD, W, U, MODE, true>(x[t], in2 + (base + (uint64_t)t * n1) * se_in, tw0, l, m);
     });
   } else {
     v[0] = l96(x[0]);
@@ -356,8 +503,8 @@ struct Span2UGeo {
 };
 
 template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B>
-__global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in, uint64_t se_in, uint64_t sd_in,
-                                                 uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
+__global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
+                                                 uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
                                                  const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
                                                  const uint32_t* __restrict__ tw2, int log2n, int log2ns, uint64_t nvec,
                                                  uint64_t vin, uint64_t vout) {
@@ -378,6 +525,7 @@ __global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in
   const uint64_t vec = wg >> log2wpv;
   const uint64_t r = wg & ((1ull << log2wpv) - 1);
   in += vec * vin;
+  if constexpr (MODE == MODE_PRODUCT) in2 += vec * vin;
   out += vec * vout;
   const uint64_t ns = 1ull << log2ns;
   const uint64_t a = r & (ns - 1);         // uniform over the workgroup
@@ -394,10 +542,10 @@ __global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in
     x[t] = in[(uint64_t)m * sd_in + (base + (uint64_t)t * n1) * se_in];
   });
   L96 v[KB];
-  if constexpr (MODE == MODE_SCALE) {
+  if constexpr (MODE != MODE_PLAIN) {
     static_for<KB>([&](auto T) {
       constexpr int t = decltype(T)::value;
-      v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw0, 0, l, m);
+      v[t] = first_slot<KD, W, U, MODE, true>(x[t], in2 + (base + (uint64_t)t * n1) * se_in, tw0, l, m);
     });
   } else {
     v[0] = l96(x[0]);
@@ -531,13 +679,15 @@ hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
       const uint64_t wgs = p.nvec << (p.log2n - 2 * LOGKB - 3);
 #define GFP_LAUNCH2U(INV, MODE, LAST, T2B)                                                                       \
   hipLaunchKernelGGL((k_pass2u<KD, W, U, INV, MODE, LAST, T2B>), dim3((unsigned)wgs), dim3(Span2UGeo<KD>::THREADS), 0, \
-                     st, p.in, p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.log2n, p.log2ns,  \
-                     p.nvec, p.vin, p.vout)
+                     st, p.in, p.in2, p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.log2n,     \
+                     p.log2ns, p.nvec, p.vin, p.vout)
 #define GFP_LAUNCH2U_T(INV, MODE)                   \
   if (p.last) GFP_LAUNCH2U(INV, MODE, true, false); \
   else if (t2b) GFP_LAUNCH2U(INV, MODE, false, true); \
   else GFP_LAUNCH2U(INV, MODE, false, false);
-      if (p.scale) {
+      if (p.in2) {
+        GFP_LAUNCH2U_T(true, MODE_PRODUCT)
+      } else if (p.scale) {
         GFP_LAUNCH2U_T(true, MODE_SCALE)
       } else if (p.inverse) {
         GFP_LAUNCH2U_T(true, MODE_PLAIN)
@@ -552,13 +702,15 @@ hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
     const unsigned nb = (unsigned)((blocks + Span2Geo<KD>::BPW - 1) / Span2Geo<KD>::BPW);
     if (nb == 0) return hipSuccess;
 #define GFP_LAUNCH2(INV, MODE, LAST, T2B)                                                                         \
-  hipLaunchKernelGGL((k_pass2<KD, W, U, INV, MODE, LAST, T2B>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, \
-                     p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.log2n, p.log2ns, p.nvec, p.vin, p.vout)
+  hipLaunchKernelGGL((k_pass2<KD, W, U, INV, MODE, LAST, T2B>), dim3(nb), dim3(256), 0, st, p.in, p.in2, p.se_in,   \
+                     p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.log2n, p.log2ns, p.nvec, p.vin, p.vout)
 #define GFP_LAUNCH2_T(INV, MODE)                   \
   if (p.last) GFP_LAUNCH2(INV, MODE, true, false); \
   else if (t2b) GFP_LAUNCH2(INV, MODE, false, true); \
   else GFP_LAUNCH2(INV, MODE, false, false);
-    if (p.scale) {
+    if (p.in2) {
+      GFP_LAUNCH2_T(true, MODE_PRODUCT)
+    } else if (p.scale) {
       GFP_LAUNCH2_T(true, MODE_SCALE)
     } else if (p.inverse) {
       GFP_LAUNCH2_T(true, MODE_PLAIN)
@@ -576,9 +728,10 @@ hipError_t launch_pass_r_lr(const PassArgs& p, hipStream_t st) {
   const unsigned nb = blocks_for(p.nvec << (p.log2n - LR), Geo<KD>::G);
   if (nb == 0) return hipSuccess;
 #define GFP_LAUNCH_R(INV, MODE)                                                                                 \
-  hipLaunchKernelGGL((k_pass_r<KD, W, U, INV, MODE, LR>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, p.out, \
-                     p.se_out, p.sd_out, p.tw, p.log2n, p.nvec, p.vin, p.vout)
-  if (p.scale) GFP_LAUNCH_R(true, MODE_SCALE);
+  hipLaunchKernelGGL((k_pass_r<KD, W, U, INV, MODE, LR>), dim3(nb), dim3(256), 0, st, p.in, p.in2, p.se_in, p.sd_in, \
+                     p.out, p.se_out, p.sd_out, p.tw, p.log2n, p.nvec, p.vin, p.vout)
+  if (p.in2) GFP_LAUNCH_R(true, MODE_PRODUCT);
+  else if (p.scale) GFP_LAUNCH_R(true, MODE_SCALE);
   else if (p.inverse) GFP_LAUNCH_R(true, MODE_PLAIN);
   else GFP_LAUNCH_R(false, MODE_PLAIN);
 #undef GFP_LAUNCH_R
@@ -595,20 +748,59 @@ hipError_t launch_pass_r_t(const PassArgs& p, hipStream_t st) {
     case 4:
       if constexpr (KD >= 16) return launch_pass_r_lr<KD, W, U, 4>(p, st);
       return hipErrorInvalidValue;
+    case 5:
+      if constexpr (KD >= 32) return launch_pass_r_lr<KD, W, U, 5>(p, st);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int KD, int W, int U>
+hipError_t launch_pass_k32_t(const PassArgs& p, hipStream_t st) {
+  constexpr int lk = ilog2(2 * KD);
+  if (p.log2n < lk || p.log2ns + lk > p.log2n) return hipErrorInvalidValue;
+  const uint64_t groups = p.ngroups * p.nvec;
+  const unsigned nb = (unsigned)((groups + 1) / 2);  // two groups per workgroup
+  if (nb == 0) return hipSuccess;
+#define GFP_LAUNCH32(INV, MODE, LAST, T2)                                                                         \
+  hipLaunchKernelGGL((k_pass_k32<KD, W, U, INV, MODE, LAST, T2>), dim3(nb), dim3(256), 0, st, p.in, p.in2, p.se_in, \
+                     p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.log2n, p.log2ns, p.ngroups, p.nvec, p.vin,  \
+                     p.vout)
+  const bool t2 = !p.last && p.log2n - 2 * lk - p.log2ns >= 0;
+#define GFP_LAUNCH32_T(INV, MODE)                  \
+  if (p.last) GFP_LAUNCH32(INV, MODE, true, false); \
+  else if (t2) GFP_LAUNCH32(INV, MODE, false, true); \
+  else GFP_LAUNCH32(INV, MODE, false, false);
+  if (p.in2) {
+    GFP_LAUNCH32_T(true, MODE_PRODUCT)
+  } else if (p.scale) {
+    GFP_LAUNCH32_T(true, MODE_SCALE)
+  } else if (p.inverse) {
+    GFP_LAUNCH32_T(true, MODE_PLAIN)
+  } else {
+    GFP_LAUNCH32_T(false, MODE_PLAIN)
+  }
+#undef GFP_LAUNCH32_T
+#undef GFP_LAUNCH32
+  return hipGetLastError();
+}
+
+template <int KD, int W, int U>
 hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
+  if (p.in2 && (!p.scale || p.sd_in != 1 || (p.se_in & 1) || (p.vin & 1) || (reinterpret_cast<uintptr_t>(p.in2) & 15)))
+    return hipErrorInvalidValue;  // the product operand is read 16 bytes at a time
   if (p.radix_log2 != 0) return launch_pass_r_t<KD, W, U>(p, st);
   if (p.span == 2) return launch_pass2_t<KD, W, U>(p, st);
   if (p.span != 1) return hipErrorInvalidValue;
+  if constexpr (KD == 32) {
+    return launch_pass_k32_t<KD, W, U>(p, st);
+  } else {
   const unsigned nb = blocks_for(p.ngroups * p.nvec, Geo<KD>::G);
   if (nb == 0) return hipSuccess;
 #define GFP_LAUNCH(INV, MODE, LAST, UNIF, T2)                                                                       \
-  hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST, UNIF, T2>), dim3(nb), dim3(256), 0, st, p.in, p.se_in, p.sd_in, \
-                     p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.log2n, p.log2ns, p.ngroups, p.nvec, p.vin, p.vout)
+  hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST, UNIF, T2>), dim3(nb), dim3(256), 0, st, p.in, p.in2, p.se_in,   \
+                     p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.log2n, p.log2ns, p.ngroups, p.nvec, p.vin,      \
+                     p.vout)
   // uniform twiddles when every base a has at least one wavefront of groups;
   // the w^(K i) table for every pass but the last
   const int lk = ilog2(2 * KD);
@@ -620,7 +812,10 @@ hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
   else if (unif) GFP_LAUNCH(INV, MODE_PLAIN, false, true, false);            \
   else if (t2) GFP_LAUNCH(INV, MODE_PLAIN, false, false, true);              \
   else GFP_LAUNCH(INV, MODE_PLAIN, false, false, false);
-  if (p.scale) {
+  if (p.in2) {
+    if (p.last) GFP_LAUNCH(true, MODE_PRODUCT, true, false, false);
+    else GFP_LAUNCH(true, MODE_PRODUCT, false, false, false);
+  } else if (p.scale) {
     if (p.last) GFP_LAUNCH(true, MODE_SCALE, true, false, false); else GFP_LAUNCH(true, MODE_SCALE, false, false, false);
   } else if (p.inverse) {
     GFP_LAUNCH_T(true)
@@ -630,6 +825,7 @@ hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
 #undef GFP_LAUNCH_T
 #undef GFP_LAUNCH
   return hipGetLastError();
+  }
 }
 
 template <int KD, int W, int U>

@@ -321,6 +321,14 @@ int gfp_server_submit(gfp_server* s, const gfp_request* req, uint64_t* ticket) {
   if (rc != GFP_OK) return rc;
   r.cap = gfpk::chunk_cap(r.per);
   if (r.per > s->slot_bytes) return GFP_ENOMEM;
+  // tables of a size not seen before are built here, on the caller's
+  // thread, so that no worker stalls on them while its peers wait
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return GFP_EDEVICE;
+  if (prev != s->cfg.device && hipSetDevice(s->cfg.device) != hipSuccess) return GFP_EDEVICE;
+  rc = gfpk::prepare_tables(req->field, r.n);
+  if (prev != s->cfg.device) (void)hipSetDevice(prev);
+  if (rc != GFP_OK) return rc;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stopping) return GFP_ECANCELED;
   if (s->queue.size() >= s->cfg.max_pending) {

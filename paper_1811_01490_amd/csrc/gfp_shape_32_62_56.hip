@@ -1,0 +1,11 @@
+// Kernels for k = 32, r = 2^62 + 2^56.
+#include "gfp_kernels.hpp"
+
+namespace gfpk {
+
+hipError_t launch_pass_32_62_56(const PassArgs& p, hipStream_t st) { return launch_pass_t<32, 62, 56>(p, st); }
+hipError_t launch_elementwise_32_62_56(const EwArgs& a, hipStream_t st) {
+  return launch_elementwise_t<32, 62, 56>(a, st);
+}
+
+}  // namespace gfpk

@@ -8,7 +8,7 @@ import re
 
 import pytest
 
-from oracle.field import GFPField, P8, P16
+from oracle.field import GFPField, P8, P16, P32
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "gfp.h")
@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("params", [P8, P16, dict(k=8, r=2 ** 59 + 2 ** 16), dict(k=16, r=2 ** 58 + 2 ** 10)])
+@pytest.mark.parametrize("params", [P8, P16, P32, dict(k=8, r=2 ** 59 + 2 ** 16), dict(k=16, r=2 ** 58 + 2 ** 10)])
 def test_field_create_info_and_roots(params):
     _lib()
     F = GFPField(**params)
@@ -175,6 +175,23 @@ def test_plan_strings():
     assert g.plan(2 ** 20) == "1111"
     with pytest.raises(gfp.GFPError):
         g.set_plan(32768, "21")
+
+
+def test_k32_field_host():
+    """The k = 32 prime of Table 1 (r = 2^62 + 2^56, K = 64): root of unity
+    from Alg. 1 as the oracle's, product sizes from K = 64 on, plans of
+    radix-64 passes one per launch (no fused pair at k = 32)."""
+    L = _lib()
+    f = gfp.Field(**P32)
+    F = GFPField(**P32)
+    out = (ctypes.c_uint64 * 32)()
+    for n in (64, 4096, 2 ** 18):
+        assert L.gfp_root_of_unity(f.handle, n, 0, out) == gfp.GFP_OK
+        assert [int(v) for v in out] == F.from_int(F.paper_root_of_unity(n))
+    assert f.polymul_size(1, 1) == 64 and f.polymul_size(2048, 2048) == 4096
+    assert f.plan(2 ** 18) == "111" and f.plan(8192) == "11" and f.plan(64) == "1"
+    with pytest.raises(gfp.GFPError):
+        f.set_plan(4096, "2")
 
 
 def test_bigint_sizes():

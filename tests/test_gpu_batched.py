@@ -8,7 +8,7 @@ import pytest
 
 import gfp_inputs as gi
 from oracle import transform as T
-from oracle.field import GFPField, P8, P16
+from oracle.field import GFPField, P8, P16, P32
 from tests.helpers import canonical_mask, to_ints
 
 pytestmark = pytest.mark.gpu
@@ -35,7 +35,7 @@ def _batch(params, sizes, seed):
     return reqs, dev
 
 
-@pytest.mark.parametrize("params", [P8, P16], ids=["k8", "k16"])
+@pytest.mark.parametrize("params", [P8, P16, P32], ids=["k8", "k16", "k32"])
 def test_batched_mixed_sizes(torch_mod, params):
     import torch
 
@@ -57,8 +57,35 @@ def test_batched_mixed_sizes(torch_mod, params):
         assert canonical_mask(ch, F.r).all(), i
         single = to_host(f.polymul(da, db))
         assert np.array_equal(ch, single), i
-        if a.shape[1] * b.shape[1] <= 2048 * 2048:
+        if a.shape[1] * b.shape[1] <= (2048 * 2048 if F.k < 32 else 600 * 600):
             assert to_ints(ch, F.r) == T.polymul(to_ints(a, F.r), to_ints(b, F.r), F.p), i
+
+
+@pytest.mark.parametrize("params", [P8, P16, P32], ids=["k8", "k16", "k32"])
+def test_fused_pointwise_product(torch_mod, params):
+    """64 products of transform size 4096 in one chunk (2^18 elements) take
+    the pointwise product inside the inverse transform's first launch; one
+    product alone takes the separate product launch.  Both must agree, and
+    one of them with the schoolbook product."""
+    import torch
+
+    from paper_1811_01490_amd import Field, to_host
+
+    F = GFPField(**params)
+    f = Field(params["k"], params["r"])
+    sizes = [(2048, 2048)] * 63 + [(2047, 2049)]
+    reqs, dev = _batch(params, sizes, gi.BASE_SEED + 310)
+    outs = [torch.full((F.k, a.shape[1] + b.shape[1] - 1), 7, dtype=torch.int64, device="cuda") for a, b in dev]
+    descs = f.batch_descs([(a, b, c) for (a, b), c in zip(dev, outs)])
+    f.polymul_batched(descs)
+    torch.cuda.synchronize()
+    for i, ((da, db), c) in enumerate(zip(dev, outs)):
+        ch = to_host(c)
+        assert canonical_mask(ch, F.r).all(), i
+        assert np.array_equal(ch, to_host(f.polymul(da, db))), i
+    if F.k == 8:
+        a, b = reqs[-1]
+        assert to_ints(to_host(outs[-1]), F.r) == T.polymul(to_ints(a, F.r), to_ints(b, F.r), F.p)
 
 
 def test_batched_graph_replays(torch_mod):

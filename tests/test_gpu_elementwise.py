@@ -1,5 +1,5 @@
 """Field arithmetic kernels (section 2) against the oracle, bit-exact:
-addition, subtraction, multiplication by r^s and multiplication, on the four
+addition, subtraction, multiplication by r^s and multiplication, on the five
 compiled radix shapes, with random operands and injected edge values."""
 
 import numpy as np
@@ -12,7 +12,7 @@ from tests.helpers import canonical_mask, to_ints
 pytestmark = pytest.mark.gpu
 
 SHAPES = [dict(k=8, r=2 ** 63 + 2 ** 34), dict(k=16, r=2 ** 62 + 2 ** 36),
-          dict(k=8, r=2 ** 59 + 2 ** 16), dict(k=16, r=2 ** 58 + 2 ** 10)]
+          dict(k=8, r=2 ** 59 + 2 ** 16), dict(k=16, r=2 ** 58 + 2 ** 10), dict(k=32, r=2 ** 62 + 2 ** 56)]
 
 
 @pytest.fixture(scope="module")
@@ -59,7 +59,7 @@ def test_add_sub_mul(torch_mod, params):
         assert not bad, (op, bad[:5], len(bad))
 
 
-@pytest.mark.parametrize("params", SHAPES[:2], ids=["k8", "k16"])
+@pytest.mark.parametrize("params", SHAPES[:2] + SHAPES[4:], ids=["k8", "k16", "k32"])
 def test_mul_pow_r_and_const(torch_mod, params):
     from paper_1811_01490_amd import Field, to_device, to_host
     from paper_1811_01490_amd.gfp import OP_MUL_CONST, OP_MUL_POW_R
@@ -84,12 +84,12 @@ def test_mul_pow_r_and_const(torch_mod, params):
     assert to_ints(z, r) == [(-v) % F.p for v in xi]
 
 
-def test_mul_large_random(torch_mod):
-    """200k random products on the k = 8 workload prime."""
+@pytest.mark.parametrize("params", [SHAPES[0], SHAPES[4]], ids=["k8", "k32"])
+def test_mul_large_random(torch_mod, params):
+    """200k random products on the k = 8 and k = 32 workload primes."""
     from paper_1811_01490_amd import Field, to_device, to_host
     from paper_1811_01490_amd.gfp import OP_MUL
 
-    params = SHAPES[0]
     k, r = params["k"], params["r"]
     F = GFPField(k, r)
     n = 200_003
@@ -108,7 +108,7 @@ def test_check_canonical(torch_mod):
     encoding: a digit >= r, or a top digit r with a nonzero lower digit."""
     from paper_1811_01490_amd import Field, to_device
 
-    for params in SHAPES[:2]:
+    for params in SHAPES[:2] + SHAPES[4:]:
         k, r = params["k"], params["r"]
         f = Field(k, r)
         x = gi.operand(k, r, 5000, gi.BASE_SEED + 900, 0, edge_frac=0.05)  # includes p - 1 = (0, ..., 0, r)

@@ -10,12 +10,13 @@ import pytest
 
 import gfp_inputs as gi
 from oracle import transform as T
-from oracle.field import GFPField, P8, P16
+from oracle.field import GFPField, P8, P16, P32
 from tests.helpers import canonical_mask, to_ints
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = {"k8": P8, "k16": P16, "k8t": dict(k=8, r=2 ** 59 + 2 ** 16), "k16t": dict(k=16, r=2 ** 58 + 2 ** 10)}
+SHAPES = {"k8": P8, "k16": P16, "k8t": dict(k=8, r=2 ** 59 + 2 ** 16), "k16t": dict(k=16, r=2 ** 58 + 2 ** 10),
+          "k32": P32}
 
 
 @pytest.fixture(scope="module")
@@ -38,7 +39,11 @@ CASES = [("k8", 16), ("k8", 256), ("k8", 4096), ("k16", 32), ("k16", 1024),
          ("k8t", 256), ("k8t", 4096), ("k16t", 1024),
          ("k8", 32), ("k8", 64), ("k8", 128), ("k8", 512), ("k8", 2048), ("k8", 8192),
          ("k16", 64), ("k16", 128), ("k16", 256), ("k16", 512), ("k16", 2048), ("k16", 16384),
-         ("k8t", 128), ("k16t", 256)]
+         ("k8t", 128), ("k16t", 256),
+         # k = 32 (K = 64): one pass; radix-2 + one pass; radix-32 + one pass;
+         # two passes (the last with rotated twiddles); radix-2 + two passes
+         # (the middle one from the w^(K i) table)
+         ("k32", 64), ("k32", 128), ("k32", 2048), ("k32", 4096), ("k32", 8192)]
 
 
 @pytest.mark.parametrize("name,N", CASES)
@@ -114,7 +119,7 @@ def test_in_place_and_padded_ld(torch_mod):
 
 
 @pytest.mark.parametrize("name,N", [("k8", 65536), ("k16", 32768), ("k8", 2 ** 17), ("k8", 2 ** 19),
-                                    ("k16", 2 ** 19), ("k16", 2 ** 16)])
+                                    ("k16", 2 ** 19), ("k16", 2 ** 16), ("k32", 2 ** 16), ("k32", 2 ** 17)])
 def test_round_trip_mid(torch_mod, name, N):
     from paper_1811_01490_amd import to_device, to_host
 
@@ -124,14 +129,15 @@ def test_round_trip_mid(torch_mod, name, N):
     assert np.array_equal(back, x)
 
 
-@pytest.mark.parametrize("name,N", [("k8", 2 ** 20), ("k16", 2 ** 20), ("k8", 2 ** 19)])
+@pytest.mark.parametrize("name,N", [("k8", 2 ** 20), ("k16", 2 ** 20), ("k8", 2 ** 19), ("k32", 2 ** 18)])
 def test_full_size_sampled(torch_mod, name, N):
-    """N = 2^20 (16^5 for k = 8, 32^4 for k = 16) and 2^19 = 8 16^4: sampled
+    """N = 2^20 (16^5 for k = 8, 32^4 for k = 16), 2^19 = 8 16^4 and, for
+    k = 32, the largest size of the paper's FFT table, 64^3 = 2^18: sampled
     outputs by Horner, round trip exact."""
     from paper_1811_01490_amd import to_device, to_host
 
     F, f = _field(name)
-    seed = gi.BASE_SEED + (1 if name == "k8" else 2)
+    seed = gi.BASE_SEED + {"k8": 1, "k16": 2, "k32": 3}[name]
     x = gi.operand(F.k, F.r, N, seed, 0, edge_frac=0.001)
     dx = to_device(x)
     y = f.fft_forward(dx)
