@@ -358,9 +358,10 @@ def bigint_leg(torch, dev, words: int, reps: int):
 
 # The paper's FFT timings (Table fftoverprimefield, FFT-based column, serial
 # CPU, machine unstated, units inferred as ms) for its test primes (Table
-# testprimes); the k = 32 rows need a shape this library does not build.
+# testprimes).
 PAPER_FFT_MS = [(8, 2 ** 59 + 2 ** 16, 256, 0.211), (8, 2 ** 59 + 2 ** 16, 4096, 5.961),
-                (16, 2 ** 58 + 2 ** 10, 1024, 1.819), (16, 2 ** 58 + 2 ** 10, 32768, 109.681)]
+                (16, 2 ** 58 + 2 ** 10, 1024, 1.819), (16, 2 ** 58 + 2 ** 10, 32768, 109.681),
+                (32, 2 ** 56 + 2 ** 21, 4096, 15.775), (32, 2 ** 56 + 2 ** 21, 262144, 1995.939)]
 
 
 def paper_context_leg(torch, dev):

@@ -331,6 +331,10 @@ struct Field {
   // where t_h = floor(t / 2^U), t_l = t mod 2^U and q = floor(t_h / d).
   // Built for the k = 32 prime of Table 1, r = 2^62 + 2^56 (d = 65).
   static constexpr bool SPLIT = U + 8 > W;
+  // window of the remainder rho = t - (t >> W) r of a lazy digit: it lies in
+  // (-OFF, 2^W + OFF); below 2 OFF it takes one more r, so that a carry of
+  // up to 2^31 in either direction keeps the digit inside [0, 2^64)
+  static constexpr uint64_t OFF = W >= 58 ? (1ull << 57) : (1ull << (W - 3));
   static_assert(W >= 56 && W <= 63 && U >= 8 && (U + 8 <= W || (W == 62 && U == 56)), "unsupported radix shape");
 };
 
@@ -639,15 +643,15 @@ __device__ __forceinline__ L96 mul_data(uint64_t x, const uint64_t (&yd)[KD], in
 // Normalisation
 // ------------------------------------------------------------------------
 // Semi-normalise a lazy digit (|t| < 2^84): digit' = rho + q_{m-1} in
-// [0, 2^64), where t = q r + rho with rho in [2^57, 2^64 - 2^57) and q passed
+// [0, 2^64), where t = q r + rho with rho in [OFF, 2^W + 2 OFF) and q passed
 // one lane up (lane 0 takes -q_{k-1}, since r^k = -1).
 template <int KD, int W, int U>
 __device__ __forceinline__ uint64_t seminorm(L96 t, int m) {
   typedef Field<KD, W, U> F;
   int64_t q;
-  uint64_t rho;  // true value in (-2^57, 2^W + 2^57)
+  uint64_t rho;  // true value in (-OFF, 2^W + OFF)
   qr_split<KD, W, U>(t, q, rho);
-  const bool low = (rho + (1ull << 57)) < (3ull << 57);  // rho < 2^58
+  const bool low = (rho + F::OFF) < 3 * F::OFF;  // rho < 2 OFF
   rho += low ? F::R : 0ull;
   q -= low ? 1 : 0;
   int32_t qi = (int32_t)q;

@@ -4,13 +4,14 @@
 namespace gfpk {
 
 // Radix shapes compiled in: the k = 8, 16 and 32 primes of Table 1 and the
-// two test primes of section 5.3 (Table testprimes).
+// three test primes of section 5.3 (Table testprimes).
 #define GFP_FOR_EACH_SHAPE(X) \
   X(8, 63, 34)                \
   X(8, 59, 16)                \
   X(16, 62, 36)               \
   X(16, 58, 10)               \
-  X(32, 62, 56)
+  X(32, 62, 56)               \
+  X(32, 56, 21)
 
 #define GFP_DECLARE(K, W, U)                                                \
   hipError_t launch_pass_##K##_##W##_##U(const PassArgs& p, hipStream_t st); \

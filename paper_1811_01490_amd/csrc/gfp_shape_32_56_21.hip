@@ -1,0 +1,11 @@
+// Kernels for k = 32, r = 2^56 + 2^21.
+#include "gfp_kernels.hpp"
+
+namespace gfpk {
+
+hipError_t launch_pass_32_56_21(const PassArgs& p, hipStream_t st) { return launch_pass_t<32, 56, 21>(p, st); }
+hipError_t launch_elementwise_32_56_21(const EwArgs& a, hipStream_t st) {
+  return launch_elementwise_t<32, 56, 21>(a, st);
+}
+
+}  // namespace gfpk

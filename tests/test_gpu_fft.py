@@ -16,7 +16,7 @@ from tests.helpers import canonical_mask, to_ints
 pytestmark = pytest.mark.gpu
 
 SHAPES = {"k8": P8, "k16": P16, "k8t": dict(k=8, r=2 ** 59 + 2 ** 16), "k16t": dict(k=16, r=2 ** 58 + 2 ** 10),
-          "k32": P32}
+          "k32": P32, "k32t": dict(k=32, r=2 ** 56 + 2 ** 21)}
 
 
 @pytest.fixture(scope="module")
@@ -43,7 +43,8 @@ CASES = [("k8", 16), ("k8", 256), ("k8", 4096), ("k16", 32), ("k16", 1024),
          # k = 32 (K = 64): one pass; radix-2 + one pass; radix-32 + one pass;
          # two passes (the last with rotated twiddles); radix-2 + two passes
          # (the middle one from the w^(K i) table)
-         ("k32", 64), ("k32", 128), ("k32", 2048), ("k32", 4096), ("k32", 8192)]
+         ("k32", 64), ("k32", 128), ("k32", 2048), ("k32", 4096), ("k32", 8192),
+         ("k32t", 64), ("k32t", 4096), ("k32t", 8192)]
 
 
 @pytest.mark.parametrize("name,N", CASES)
