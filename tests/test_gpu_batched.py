@@ -61,19 +61,28 @@ def test_batched_mixed_sizes(torch_mod, params):
             assert to_ints(ch, F.r) == T.polymul(to_ints(a, F.r), to_ints(b, F.r), F.p), i
 
 
-@pytest.mark.parametrize("params", [P8, P16, P32], ids=["k8", "k16", "k32"])
-def test_fused_pointwise_product(torch_mod, params):
-    """64 products of transform size 4096 in one chunk (2^18 elements) take
-    the pointwise product inside the inverse transform's first launch; one
-    product alone takes the separate product launch.  Both must agree, and
-    one of them with the schoolbook product."""
+# (prime, operand sizes, count): every chunk has 2^18 elements.  k = 8: the
+# inverse's first launch is one pass (4096 = 16^3, plan 12), a fused pair
+# (256 = 16^2, plan 2) or the radix-8 pass (2048 = 8 16^2); k = 16: the
+# radix-2 pass (4096 = 2 32^2); k = 32: the radix-64 pass (4096 = 64^2).
+FUSED = [(P8, (2048, 2048), 64), (P8, (100, 100), 1024), (P8, (1000, 1000), 128), (P16, (2048, 2048), 64),
+         (P32, (2048, 2048), 64)]
+
+
+@pytest.mark.parametrize("params,size,count", FUSED, ids=["k8-one", "k8-pair", "k8-radix8", "k16", "k32"])
+def test_fused_pointwise_product(torch_mod, params, size, count):
+    """Products in a chunk of 2^18 elements take the pointwise product inside
+    the inverse transform's first launch; one product alone takes the separate
+    product launch.  Both must agree, and one of them with the schoolbook
+    product."""
     import torch
 
     from paper_1811_01490_amd import Field, to_host
 
     F = GFPField(**params)
     f = Field(params["k"], params["r"])
-    sizes = [(2048, 2048)] * 63 + [(2047, 2049)]
+    la, lb = size
+    sizes = [(la, lb)] * (count - 1) + [(la - 1, lb + 1)]
     reqs, dev = _batch(params, sizes, gi.BASE_SEED + 310)
     outs = [torch.full((F.k, a.shape[1] + b.shape[1] - 1), 7, dtype=torch.int64, device="cuda") for a, b in dev]
     descs = f.batch_descs([(a, b, c) for (a, b), c in zip(dev, outs)])
