@@ -67,8 +67,9 @@ typedef struct gfp_field gfp_field;
 
 /* Create the field Z/pZ, p = r^k + 1 (section 2).  Host-only; touches no GPU.
  * k must be a power of two and r even; the library runs transforms for
- * k in {8, 16} with r = 2^w + 2^u for (k, w, u) in {(8, 63, 34), (8, 59, 16),
- * (16, 62, 36), (16, 58, 10)} (Table 1 and Table testprimes).  p is checked
+ * r = 2^w + 2^u with (k, w, u) in {(8, 63, 34), (8, 59, 16), (16, 62, 36),
+ * (16, 58, 10), (32, 62, 56), (32, 56, 21)} and for r = 2^63 - 2^40 with
+ * k = 64 (Table 1 and Table testprimes).  p is checked
  * with a Miller-Rabin probable-prime test (12 fixed bases).
  * Returns GFP_EINVAL (out == NULL, bad k/r), GFP_EUNSUPPORTED (shape not
  * compiled in), GFP_ENOTPRIME.  On success *out owns the field; release it
@@ -213,7 +214,8 @@ int gfp_elementwise(const gfp_field* f, int op, const uint64_t* x, uint64_t ld_x
  * carries W of the k W bits an element holds: a denser packing would need a
  * radix conversion of every coefficient.  Sizes: la + lb - 1 coefficients
  * (la = ceil(64 na / W)) within the transform limit.  Workspace as for the
- * transforms (gfp_bigint_mul_workspace_size bytes, or NULL). */
+ * transforms (gfp_bigint_mul_workspace_size bytes, or NULL).  Radices
+ * r = 2^W - 2^U are GFP_EUNSUPPORTED (a W-bit chunk can exceed r). */
 int gfp_bigint_mul_workspace_size(const gfp_field* f, uint64_t na, uint64_t nb, uint64_t* bytes);
 int gfp_bigint_mul(const gfp_field* f, const uint64_t* a, uint64_t na, const uint64_t* b, uint64_t nb, uint64_t* c,
                    void* workspace, uint64_t ws_bytes, void* stream);

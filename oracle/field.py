@@ -276,7 +276,8 @@ class GFPField:
         return pow(g, j, self.p)
 
 
-# Primes of the workloads (Table 1 rows 3, 4 and 5).
+# Primes of the workloads (Table 1 rows 3 to 6).
 P8 = dict(k=8, r=2 ** 63 + 2 ** 34)
 P16 = dict(k=16, r=2 ** 62 + 2 ** 36)
 P32 = dict(k=32, r=2 ** 62 + 2 ** 56)
+P64 = dict(k=64, r=2 ** 63 - 2 ** 40)

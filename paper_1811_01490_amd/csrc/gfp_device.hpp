@@ -55,17 +55,20 @@ constexpr int brev(int i, int bits) {
 // ------------------------------------------------------------------------
 template <int KD>
 struct Geo {
-  static_assert(KD == 8 || KD == 16 || KD == 32, "k must be 8, 16 or 32");
+  static_assert(KD == 8 || KD == 16 || KD == 32 || KD == 64, "k must be 8, 16, 32 or 64");
   static constexpr bool ROW = KD <= 16;          // an element inside one DPP row
   static constexpr int GPL = ROW ? 16 / KD : 1;  // elements per DPP row (k <= 16)
   static constexpr int G = 64 / KD;              // elements per wavefront
   static constexpr int KB = 2 * KD;              // base-case DFT size K = 2k
+  static constexpr int HI = 63 & ~(KD - 1);      // lane bits naming the element (k >= 32)
   __device__ static __forceinline__ int lane() { return (int)(threadIdx.x & 63); }
-  __device__ static __forceinline__ int digit(int l) { return ROW ? (l & 15) / GPL : (l & 31); }
-  __device__ static __forceinline__ int group(int l) { return ROW ? (l >> 4) * GPL + (l & 15) % GPL : (l >> 5); }
+  __device__ static __forceinline__ int digit(int l) { return ROW ? (l & 15) / GPL : (l & (KD - 1)); }
+  __device__ static __forceinline__ int group(int l) {
+    return ROW ? (l >> 4) * GPL + (l & 15) % GPL : (l >> ilog2(KD));
+  }
   // lane holding digit d of the same element as lane l
   __device__ static __forceinline__ int lane_of(int l, int d) {
-    return ROW ? ((l & 0x30) | (d * GPL) | ((l & 15) % GPL)) : ((l & 32) | d);
+    return ROW ? ((l & 0x30) | (d * GPL) | ((l & 15) % GPL)) : ((l & HI) | d);
   }
 };
 
@@ -90,7 +93,7 @@ __device__ __forceinline__ uint32_t dig_rot(uint32_t v) {
     return row_ror<n * Geo<KD>::GPL>(v);
   } else {
     const int l = (int)(threadIdx.x & 63);
-    return (uint32_t)__builtin_amdgcn_ds_bpermute(((l & 32) | ((l - n) & 31)) << 2, (int)v);
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(((l & Geo<KD>::HI) | ((l - n) & (KD - 1))) << 2, (int)v);
   }
 }
 
@@ -320,22 +323,29 @@ __device__ __forceinline__ L96 sub_shifted32(uint32_t l0, uint32_t l1, uint32_t 
   return L96{((uint64_t)o1 << 32) | o0, (int32_t)o2};
 }
 
+// Radix shape: r = 2^W + 2^U for U > 0, r = 2^W - 2^|U| for U < 0.
 template <int KD, int W, int U>
 struct Field {
-  static constexpr uint64_t R = (1ull << W) + (1ull << U);
-  static constexpr int SA = 64 - W;      // 2^64 = 2^SA * r - 2^SB
+  static constexpr bool NEG = U < 0;
+  static constexpr int UA = NEG ? -U : U;
+  static constexpr uint64_t R = NEG ? (1ull << W) - (1ull << UA) : (1ull << W) + (1ull << UA);
+  static constexpr int SA = 64 - W;      // 2^64 = 2^SA * r - 2^SB (U > 0)
   static constexpr int SB = 64 - W + U;
-  // SPLIT: U close to W, so a fold with 2^64 = 2^SA r - 2^SB gains only
-  // W - U bits a round.  Then r = 2^U d with d = 2^(W-U) + 1, and an integer
-  // t splits exactly as t = q r + rho, rho = (t_h mod d) 2^U + t_l in [0, r),
-  // where t_h = floor(t / 2^U), t_l = t mod 2^U and q = floor(t_h / d).
-  // Built for the k = 32 prime of Table 1, r = 2^62 + 2^56 (d = 65).
-  static constexpr bool SPLIT = U + 8 > W;
+  // SPLIT: a fold with 2^64 = 2^SA r - 2^SB gains only W - U bits a round
+  // (U close to W), or does not apply (U < 0).  Then r = 2^UA d with
+  // d = 2^(W-UA) +- 1, and an integer t splits exactly as t = q r + rho,
+  // rho = (t_h mod d) 2^UA + t_l in [0, r), where t_h = floor(t / 2^UA),
+  // t_l = t mod 2^UA and q = floor(t_h / d).  Built for the k = 32 and
+  // k = 64 primes of Table 1: r = 2^62 + 2^56 (d = 65) and r = 2^63 - 2^40
+  // (d = 2^23 - 1).
+  static constexpr bool SPLIT = NEG || U + 8 > W;
   // window of the remainder rho = t - (t >> W) r of a lazy digit: it lies in
   // (-OFF, 2^W + OFF); below 2 OFF it takes one more r, so that a carry of
   // up to 2^31 in either direction keeps the digit inside [0, 2^64)
   static constexpr uint64_t OFF = W >= 58 ? (1ull << 57) : (1ull << (W - 3));
-  static_assert(W >= 56 && W <= 63 && U >= 8 && (U + 8 <= W || (W == 62 && U == 56)), "unsupported radix shape");
+  static_assert(W >= 56 && W <= 63 &&
+                    ((U >= 8 && U + 8 <= W) || (W == 62 && U == 56) || (W == 63 && U == -40)),
+                "unsupported radix shape");
 };
 
 // SPLIT division for r = 2^56 * 65.  65 is odd and 2^12 = 1 (mod 65), so
@@ -374,14 +384,55 @@ __device__ __forceinline__ void split_qr160(uint32_t c0, uint32_t c1, uint32_t c
   T = ((uint64_t)((rem << 24) | (c1 & 0xFFFFFFu)) << 32) | c0;
 }
 
+// SPLIT division for r = 2^40 (2^23 - 1) (the k = 64 prime of Table 1).
+// d = 2^23 - 1 is odd and 2^23 = 1 (mod d): n mod d is the sum of n's 23-bit
+// chunks folded twice, and the quotient of the exact multiple n - (n mod d)
+// is its product with d^-1 mod 2^96.  C as for split_qr160, |C| < 2^134.
+__device__ __forceinline__ void split_qr160_m23(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t c4,
+                                                uint64_t& T, L96& Q) {
+  constexpr uint32_t D = (1u << 23) - 1, M23 = D;
+  // n = floor(C / 2^40) + d 2^72, in [0, 2^96)
+  const uint32_t n0 = __builtin_amdgcn_alignbit(c2, c1, 8);
+  const uint32_t n1 = __builtin_amdgcn_alignbit(c3, c2, 8);
+  const uint32_t n2 = __builtin_amdgcn_alignbit(c4, c3, 8) + (D << 8);
+  uint32_t t = (n0 & M23) + (((n0 >> 23) | (n1 << 9)) & M23) + (((n1 >> 14) | (n2 << 18)) & M23) +
+               ((n2 >> 5) & M23) + (n2 >> 28);
+  t = (t & M23) + (t >> 23);
+  t = (t & M23) + (t >> 23);
+  const uint32_t rem = (t == D) ? 0u : t;
+  unsigned b;
+  const uint32_t m0 = __builtin_subc(n0, rem, 0u, &b);
+  const uint32_t m1 = __builtin_subc(n1, 0u, b, &b);
+  const uint32_t m2 = n2 - b;
+  constexpr uint32_t I0 = 0xFF7FFFFFu, I1 = 0xFFFFBFFFu, I2 = 0xEFFFFFDFu;  // (2^23 - 1)^-1 mod 2^96
+  const uint64_t pa = (uint64_t)m0 * I0;
+  const uint64_t pb = (uint64_t)m0 * I1 + (pa >> 32);
+  const uint64_t pc = (uint64_t)m1 * I0 + (uint32_t)pb;
+  const uint32_t q2 = (uint32_t)(pb >> 32) + (uint32_t)(pc >> 32) + m0 * I2 + m1 * I1 + m2 * I0;
+  // Q = q' - 2^72
+  Q.lo = ((uint64_t)(uint32_t)pc << 32) | (uint32_t)pa;
+  Q.hi = (int32_t)(q2 - (1u << 8));
+  T = ((uint64_t)((rem << 8) | (c1 & 0xFFu)) << 32) | c0;
+}
+
 // t = q r + rho for a lazy digit, |t| < 2^84.  Non-SPLIT shapes: q = t >> W
 // and rho = t - q r, true value in (-2^57, 2^W + 2^57).  SPLIT: exact,
-// 0 <= rho < r (t_h = t >> 56 has |t_h| < 2^28; floor(n / 65) for n < 2^31
-// is n ceil(2^38 / 65) >> 38).
+// 0 <= rho < r (r = 2^56 65: t_h = t >> 56 has |t_h| < 2^28 and floor(n / 65)
+// for n < 2^31 is n ceil(2^38 / 65) >> 38).
 template <int KD, int W, int U>
 __device__ __forceinline__ void qr_split(L96 t, int64_t& q, uint64_t& rho) {
   typedef Field<KD, W, U> F;
-  if constexpr (F::SPLIT) {
+  if constexpr (F::NEG) {
+    // t_h = t >> 40, |t_h| < 2^44; n = t_h + d 2^22 in [0, 2^46) = a 2^23 + b,
+    // n = a d + (a + b) and a + b < 2^24 < 3 d
+    const int64_t th = ((int64_t)t.hi << 24) + (int64_t)(t.lo >> 40);
+    constexpr uint64_t D = (1ull << 23) - 1;
+    const uint64_t n = (uint64_t)(th + (int64_t)(D << 22));
+    const uint64_t a = n >> 23, c = a + (n & D);
+    const uint64_t e = (uint64_t)(c >= D) + (uint64_t)(c >= 2 * D);
+    q = (int64_t)(a + e) - (1ll << 22);
+    rho = ((c - e * D) << 40) | (t.lo & ((1ull << 40) - 1));
+  } else if constexpr (F::SPLIT) {
     const int32_t th = (int32_t)(((uint32_t)t.hi << 8) | (uint32_t)(t.lo >> 56));
     const uint32_t n = (uint32_t)(th + (65 << 23));
     const uint32_t qp = (uint32_t)(((uint64_t)n * 4228890877u) >> 38);
@@ -427,29 +478,49 @@ __device__ __forceinline__ RotLane<KD> rot_lane(int rot, int m) {
 }
 
 // Core.  (v0, v1): the lane's starting x digit (rotated, complemented).
+// yl(t, y0, y1, y2): the three limbs of y_t (t a compile-time constant for
+// k <= 32, an int for k = 64).
 // (s0, s1, s2): the correction sum S_m as three 32-bit words.
 // Returns the lazy product digit T_m + Q_{m-1}.
-template <int KD, int W, int U>
-__device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<KD>& y, uint32_t s0, uint32_t s1,
-                                        uint32_t s2, int m) {
+template <int KD, int W, int U, class YL>
+__device__ __forceinline__ L96 mul_core_y(uint32_t v0, uint32_t v1, YL&& yl, uint32_t s0, uint32_t s1, uint32_t s2,
+                                          int m) {
   typedef Field<KD, W, U> F;
-  constexpr int SA = F::SA, SB = F::SB;
   const uint32_t wrap = (m == 0) ? 0xFFFFFFFFu : 0u;
   uint64_t a00 = 0, a01 = 0, a02 = 0, a10 = 0, a11 = 0, a12 = 0;
-  static_for<KD>([&](auto T) {
-    constexpr int t = decltype(T)::value;
-    const uint32_t y0 = y.l[3 * t], y1 = y.l[3 * t + 1], y2 = y.l[3 * t + 2];
-    a00 += (uint64_t)v0 * y0;
-    a01 += (uint64_t)v0 * y1;
-    a02 += (uint64_t)v0 * y2;
-    a10 += (uint64_t)v1 * y0;
-    a11 += (uint64_t)v1 * y1;
-    a12 += (uint64_t)v1 * y2;
-    if constexpr (t + 1 < KD) {
+  if constexpr (KD == 64) {
+    // a run-time loop (yl takes a run-time t): 64 unrolled steps in every
+    // product of a kernel make the code too large
+#pragma unroll 4
+    for (int t = 0; t < KD; ++t) {
+      uint32_t y0, y1, y2;
+      yl(t, y0, y1, y2);
+      a00 += (uint64_t)v0 * y0;
+      a01 += (uint64_t)v0 * y1;
+      a02 += (uint64_t)v0 * y2;
+      a10 += (uint64_t)v1 * y0;
+      a11 += (uint64_t)v1 * y1;
+      a12 += (uint64_t)v1 * y2;
       v0 = dig_rot<KD, 1>(v0) ^ wrap;
       v1 = dig_rot<KD, 1>(v1) ^ wrap;
     }
-  });
+  } else {
+    static_for<KD>([&](auto T) {
+      constexpr int t = decltype(T)::value;
+      uint32_t y0, y1, y2;
+      yl(T, y0, y1, y2);
+      a00 += (uint64_t)v0 * y0;
+      a01 += (uint64_t)v0 * y1;
+      a02 += (uint64_t)v0 * y2;
+      a10 += (uint64_t)v1 * y0;
+      a11 += (uint64_t)v1 * y1;
+      a12 += (uint64_t)v1 * y2;
+      if constexpr (t + 1 < KD) {
+        v0 = dig_rot<KD, 1>(v0) ^ wrap;
+        v1 = dig_rot<KD, 1>(v1) ^ wrap;
+      }
+    });
+  }
   // Cells at 32-bit positions, C = c0 + c1 2^32 + c2 2^64 + c3 2^96 - S 2^64:
   // the accumulators sit at bit 0, 22, 44 (v0 limb) and 32, 54, 76 (v1 limb);
   // + S enters c0..c2.  Every shifted add is one v_mad_u64_u32 with a
@@ -479,10 +550,15 @@ __device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<K
   if constexpr (F::SPLIT) {
     uint64_t T;
     L96 Qs;
-    split_qr160(l0, l1, h0, h1, h2, T, Qs);
+    if constexpr (F::NEG) {
+      split_qr160_m23(l0, l1, h0, h1, h2, T, Qs);
+    } else {
+      split_qr160(l0, l1, h0, h1, h2, T, Qs);
+    }
     const L96 nqs = l96_sub(L96{0, 0}, Qs);
     return l96_add(l96(T), l96_rot<KD, 1>((m == KD - 1) ? nqs : Qs));
-  }
+  } else {
+  constexpr int SA = F::SA, SB = F::SB;
   // fold 1 (2^64 = a r - b): C = a H r + V, V = L - b H; keep V's low 64
   // bits (v0w, v1w) and Vh = V >> 64 (|Vh| < 2^45)
   uint32_t v0w, v1w, v2w, v3w;
@@ -507,6 +583,21 @@ __device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<K
   const L96 nq = l96_sub(L96{0, 0}, Q);
   const L96 qs = (m == KD - 1) ? nq : Q;
   return l96_add(Tm, l96_rot<KD, 1>(qs));
+  }
+}
+
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<KD>& y, uint32_t s0, uint32_t s1,
+                                        uint32_t s2, int m) {
+  return mul_core_y<KD, W, U>(
+      v0, v1,
+      [&](auto T, uint32_t& y0, uint32_t& y1, uint32_t& y2) {
+        constexpr int t = decltype(T)::value;
+        y0 = y.l[3 * t];
+        y1 = y.l[3 * t + 1];
+        y2 = y.l[3 * t + 2];
+      },
+      s0, s1, s2, m);
 }
 
 // Twiddle entry layout (u32 words): 3k limbs of the digits, then for
@@ -550,15 +641,42 @@ __device__ __forceinline__ void tw_limbs(const uint32_t* __restrict__ tw, YLimbs
   });
 }
 
+// Keeps the loads of one slot's product from being hoisted above the
+// previous slot's work (which only raises register pressure).
+__device__ __forceinline__ void slot_fence() { asm volatile("" ::: "memory"); }
+
+// k = 64: x * (table entry tw) for the lane's prepared x digit (v0, v1) and
+// correction words.  An element is a whole wavefront, so the entry is
+// wavefront-uniform; its 192 limbs are streamed through the column loop
+// instead of held in registers.
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_tw_stream(uint32_t v0, uint32_t v1, const uint32_t* __restrict__ tw, uint32_t s0,
+                                             uint32_t s1, uint32_t s2, int m) {
+  return mul_core_y<KD, W, U>(
+      v0, v1,
+      [&](int t, uint32_t& y0, uint32_t& y1, uint32_t& y2) {
+        y0 = tw[TwLayout<KD>::LIMBS + 3 * t];
+        y1 = tw[TwLayout<KD>::LIMBS + 3 * t + 1];
+        y2 = tw[TwLayout<KD>::LIMBS + 3 * t + 2];
+      },
+      s0, s1, s2, m);
+}
+
 // x * tw * r^rot where lane m already holds digit rl.src of x (xs).
 template <int KD, int W, int U>
 __device__ __forceinline__ L96 mul_twiddle_pre(uint64_t xs, const uint32_t* __restrict__ tw, const RotLane<KD>& rl,
                                                int m) {
-  YLimbs<KD> y;
-  tw_limbs<KD>(tw, y);
-  uint32_t s0, s1, s2;
-  tw_correction<KD>(tw, rl, s0, s1, s2);
-  return mul_core<KD, W, U>((uint32_t)xs ^ rl.mask, (uint32_t)(xs >> 32) ^ rl.mask, y, s0, s1, s2, m);
+  if constexpr (KD == 64) {
+    uint32_t s0, s1, s2;
+    tw_correction<KD>(tw, rl, s0, s1, s2);
+    return mul_tw_stream<KD, W, U>((uint32_t)xs ^ rl.mask, (uint32_t)(xs >> 32) ^ rl.mask, tw, s0, s1, s2, m);
+  } else {
+    YLimbs<KD> y;
+    tw_limbs<KD>(tw, y);
+    uint32_t s0, s1, s2;
+    tw_correction<KD>(tw, rl, s0, s1, s2);
+    return mul_core<KD, W, U>((uint32_t)xs ^ rl.mask, (uint32_t)(xs >> 32) ^ rl.mask, y, s0, s1, s2, m);
+  }
 }
 
 // x * tw * r^rot where lane m holds digit m of x (the digit is fetched from
@@ -582,43 +700,55 @@ __device__ __forceinline__ L96 mul_twiddle_uniform(uint64_t x, const uint32_t* _
   const int src = Geo<KD>::lane_of(l, rl.src);
   const uint32_t x0 = (uint32_t)__shfl((int)(uint32_t)x, src, 64) ^ rl.mask;
   const uint32_t x1 = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, 64) ^ rl.mask;
-  YLimbs<KD> y;
-  static_for<3 * KD>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    y.l[i] = tw[TwLayout<KD>::LIMBS + i];
-  });
-  uint32_t s0, s1, s2;
-  tw_correction<KD>(tw, rl, s0, s1, s2);
-  return mul_core<KD, W, U>(x0, x1, y, s0, s1, s2, m);
+  if constexpr (KD == 64) {
+    uint32_t s0, s1, s2;
+    tw_correction<KD>(tw, rl, s0, s1, s2);
+    return mul_tw_stream<KD, W, U>(x0, x1, tw, s0, s1, s2, m);
+  } else {
+    YLimbs<KD> y;
+    static_for<3 * KD>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      y.l[i] = tw[TwLayout<KD>::LIMBS + i];
+    });
+    uint32_t s0, s1, s2;
+    tw_correction<KD>(tw, rl, s0, s1, s2);
+    return mul_core<KD, W, U>(x0, x1, y, s0, s1, s2, m);
+  }
 }
 
 // x * tw where lane m holds digit m of x (no rotation) and the table entry
 // is wavefront-uniform: limbs through scalar loads, the lane's correction sum
 // S_m = suffix(m + 1) through one vector load at a fixed per-lane offset.
-// Keeps the loads of one slot's product from being hoisted above the
-// previous slot's work (which only raises register pressure).
-__device__ __forceinline__ void slot_fence() { asm volatile("" ::: "memory"); }
-
 template <int KD, int W, int U>
 __device__ __forceinline__ L96 mul_entry_uniform(uint64_t x, const uint32_t* __restrict__ tw, int m) {
   slot_fence();
-  YLimbs<KD> y;
-  static_for<3 * KD>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    y.l[i] = tw[TwLayout<KD>::LIMBS + i];
-  });
-  const uint32_t* suf = tw + TwLayout<KD>::SUF + 3 * (m + 1);
-  return mul_core<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), y, suf[0], suf[1], suf[2], m);
+  if constexpr (KD == 64) {
+    const uint32_t* suf = tw + TwLayout<KD>::SUF + 3 * (m + 1);
+    return mul_tw_stream<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), tw, suf[0], suf[1], suf[2], m);
+  } else {
+    YLimbs<KD> y;
+    static_for<3 * KD>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      y.l[i] = tw[TwLayout<KD>::LIMBS + i];
+    });
+    const uint32_t* suf = tw + TwLayout<KD>::SUF + 3 * (m + 1);
+    return mul_core<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), y, suf[0], suf[1], suf[2], m);
+  }
 }
 
 // The same with a per-group entry (vector loads of the limbs).
 template <int KD, int W, int U>
 __device__ __forceinline__ L96 mul_entry(uint64_t x, const uint32_t* __restrict__ tw, int m) {
   slot_fence();
-  YLimbs<KD> y;
-  tw_limbs<KD>(tw, y);
-  const uint32_t* suf = tw + TwLayout<KD>::SUF + 3 * (m + 1);
-  return mul_core<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), y, suf[0], suf[1], suf[2], m);
+  if constexpr (KD == 64) {
+    const uint32_t* suf = tw + TwLayout<KD>::SUF + 3 * (m + 1);
+    return mul_tw_stream<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), tw, suf[0], suf[1], suf[2], m);
+  } else {
+    YLimbs<KD> y;
+    tw_limbs<KD>(tw, y);
+    const uint32_t* suf = tw + TwLayout<KD>::SUF + 3 * (m + 1);
+    return mul_core<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), y, suf[0], suf[1], suf[2], m);
+  }
 }
 
 // x * y for two data elements: every lane of the element loads all of y's
@@ -637,6 +767,47 @@ __device__ __forceinline__ L96 mul_data(uint64_t x, const uint64_t (&yd)[KD], in
     sh += (uint32_t)(sl < add);
   });
   return mul_core<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), y, (uint32_t)sl, (uint32_t)(sl >> 32), sh, m);
+}
+
+// x * y for a data element whose digit t is y[t ys].  k <= 32 as mul_data.
+// k = 64 (the element is the wavefront, so y's address is uniform): the
+// digits are streamed and split as they are used, and S_m = total - (y_0 +
+// ... + y_m) comes from an inclusive scan of the lanes' own digits.
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_data_ptr(uint64_t x, const uint64_t* __restrict__ y, uint64_t ys, int l, int m) {
+  if constexpr (KD == 64) {
+    uint64_t pl = y[(uint64_t)m * ys];
+    uint32_t ph = 0;
+    static_for<6>([&](auto I) {
+      constexpr int d = 1 << decltype(I)::value;
+      const uint32_t a0 = (uint32_t)__shfl_up((int)(uint32_t)pl, d, 64);
+      const uint32_t a1 = (uint32_t)__shfl_up((int)(uint32_t)(pl >> 32), d, 64);
+      const uint32_t a2 = (uint32_t)__shfl_up((int)ph, d, 64);
+      if (m >= d) {
+        const uint64_t add = ((uint64_t)a1 << 32) | a0;
+        pl += add;
+        ph += a2 + (uint32_t)(pl < add);
+      }
+    });
+    const uint64_t tl = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(pl >> 32), 63, 64) << 32) |
+                        (uint32_t)__shfl((int)(uint32_t)pl, 63, 64);
+    const uint32_t th = (uint32_t)__shfl((int)ph, 63, 64);
+    const uint64_t sl = tl - pl;
+    const uint32_t sh = th - ph - (uint32_t)(tl < pl);
+    (void)l;
+    return mul_core_y<KD, W, U>(
+        (uint32_t)x, (uint32_t)(x >> 32),
+        [&](int t, uint32_t& y0, uint32_t& y1, uint32_t& y2) { split22(y[(uint64_t)t * ys], y0, y1, y2); },
+        (uint32_t)sl, (uint32_t)(sl >> 32), sh, m);
+  } else {
+    (void)l;
+    uint64_t yd[KD];
+    static_for<KD>([&](auto T) {
+      constexpr int t = decltype(T)::value;
+      yd[t] = y[(uint64_t)t * ys];
+    });
+    return mul_data<KD, W, U>(x, yd, m);
+  }
 }
 
 // ------------------------------------------------------------------------

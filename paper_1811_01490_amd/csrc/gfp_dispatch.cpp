@@ -3,24 +3,26 @@
 
 namespace gfpk {
 
-// Radix shapes compiled in: the k = 8, 16 and 32 primes of Table 1 and the
-// three test primes of section 5.3 (Table testprimes).
+// Radix shapes compiled in (k, W, U; r = 2^W + 2^U, or 2^W - 2^-U for U < 0):
+// the k = 8, 16, 32 and 64 primes of Table 1 and the three test primes of
+// section 5.3 (Table testprimes).
 #define GFP_FOR_EACH_SHAPE(X) \
-  X(8, 63, 34)                \
-  X(8, 59, 16)                \
-  X(16, 62, 36)               \
-  X(16, 58, 10)               \
-  X(32, 62, 56)               \
-  X(32, 56, 21)
+  X(8, 63, 34, 8_63_34)       \
+  X(8, 59, 16, 8_59_16)       \
+  X(16, 62, 36, 16_62_36)     \
+  X(16, 58, 10, 16_58_10)     \
+  X(32, 62, 56, 32_62_56)     \
+  X(32, 56, 21, 32_56_21)     \
+  X(64, 63, -40, 64_63_m40)
 
-#define GFP_DECLARE(K, W, U)                                                \
-  hipError_t launch_pass_##K##_##W##_##U(const PassArgs& p, hipStream_t st); \
-  hipError_t launch_elementwise_##K##_##W##_##U(const EwArgs& a, hipStream_t st);
+#define GFP_DECLARE(K, W, U, TAG)                                   \
+  hipError_t launch_pass_##TAG(const PassArgs& p, hipStream_t st); \
+  hipError_t launch_elementwise_##TAG(const EwArgs& a, hipStream_t st);
 GFP_FOR_EACH_SHAPE(GFP_DECLARE)
 #undef GFP_DECLARE
 
 bool shape_supported(int k, int w, int u) {
-#define GFP_SHAPE_CASE(K, W, U) \
+#define GFP_SHAPE_CASE(K, W, U, TAG) \
   if (k == K && w == W && u == U) return true;
   GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
 #undef GFP_SHAPE_CASE
@@ -30,16 +32,16 @@ bool shape_supported(int k, int w, int u) {
 bool span2_supported(int k) { return k == 8; }
 
 hipError_t launch_pass(int k, int w, int u, const PassArgs& p, hipStream_t st) {
-#define GFP_SHAPE_CASE(K, W, U) \
-  if (k == K && w == W && u == U) return launch_pass_##K##_##W##_##U(p, st);
+#define GFP_SHAPE_CASE(K, W, U, TAG) \
+  if (k == K && w == W && u == U) return launch_pass_##TAG(p, st);
   GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
 #undef GFP_SHAPE_CASE
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_elementwise(int k, int w, int u, const EwArgs& a, hipStream_t st) {
-#define GFP_SHAPE_CASE(K, W, U) \
-  if (k == K && w == W && u == U) return launch_elementwise_##K##_##W##_##U(a, st);
+#define GFP_SHAPE_CASE(K, W, U, TAG) \
+  if (k == K && w == W && u == U) return launch_elementwise_##TAG(a, st);
   GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
 #undef GFP_SHAPE_CASE
   return hipErrorInvalidValue;

@@ -44,7 +44,7 @@ struct DevConsts {
 struct gfp_field {
   uint32_t k = 0;
   uint64_t r = 0;
-  int w = -1, u = -1;  // r = 2^w + 2^u when the shape is compiled in
+  int w = -1, u = 0;  // r = 2^w + 2^u (or 2^w - 2^-u for u < 0); w = -1: neither form
   bool gpu_shape = false;
   Big p, pm1;
   std::unique_ptr<Mont> mont;
@@ -682,10 +682,17 @@ int gfp_field_create(uint32_t k, uint64_t r, gfp_field** out) {
   if (!f) return GFP_ENOMEM;
   f->k = k;
   f->r = r;
-  // r = 2^w + 2^u ?
+  // r = 2^w + 2^u (u > 0), or r = 2^w - 2^-u (u < 0) ?
   if (__builtin_popcountll(r) == 2) {
     f->u = __builtin_ctzll(r);
     f->w = 63 - __builtin_clzll(r);
+  } else {
+    const int lo = __builtin_ctzll(r);
+    const unsigned __int128 up = (unsigned __int128)r + ((unsigned __int128)1 << lo);
+    if ((up & (up - 1)) == 0 && up <= ((unsigned __int128)1 << 63)) {
+      f->u = -lo;
+      f->w = 63 - __builtin_clzll((uint64_t)up);
+    }
   }
   f->gpu_shape = f->w >= 0 && gfpk::shape_supported((int)k, f->w, f->u);
   Big rk(1);
@@ -893,7 +900,9 @@ struct BigintPlan {
 
 int plan_bigint(const gfp_field* f, uint64_t na, uint64_t nb, BigintPlan& p) {
   if (!f || na == 0 || nb == 0) return GFP_EINVAL;
-  if (!f->gpu_shape) return GFP_EUNSUPPORTED;
+  // chunks of W bits are digits and evaluate with r = 2^W + 2^U: not for
+  // radices 2^W - 2^U, where a W-bit chunk can exceed r
+  if (!f->gpu_shape || f->u < 0) return GFP_EUNSUPPORTED;
   const uint64_t W = (uint64_t)f->w;
   p.la = (64 * na + W - 1) / W;
   p.lb = (64 * nb + W - 1) / W;

@@ -53,7 +53,10 @@ enum { MODE_PLAIN = 0, MODE_SCALE = 1, MODE_PRODUCT = 2 };
 template <int KD, int W, int U, int MODE, bool UC = false>
 __device__ __forceinline__ L96 first_slot(uint64_t x, const uint64_t* __restrict__ y, const uint32_t* __restrict__ c,
                                           int l, int m) {
-  if constexpr (MODE == MODE_PRODUCT) {
+  if constexpr (MODE == MODE_PRODUCT && KD == 64) {
+    slot_fence();
+    x = seminorm<KD, W, U>(mul_data_ptr<KD, W, U>(x, y, 1, l, m), m);
+  } else if constexpr (MODE == MODE_PRODUCT) {
     slot_fence();
     uint64_t yd[KD];
     const ulonglong2* y2 = reinterpret_cast<const ulonglong2*>(y);
@@ -300,6 +303,105 @@ __global__ __launch_bounds__(256) void k_pass_k32(const uint64_t* __restrict__ i
         d = seminorm<KD, W, U>(v[u1], m);
       }
       if (active) out[(uint64_t)m * sd_out + (obase + u * ns) * se_out] = d;
+    });
+  });
+}
+
+// ---------------------------------------------------------------------------
+// one radix-K pass for k = 64 (K = 128): DFT_128 as DFT_16 x DFT_8 through LDS
+// ---------------------------------------------------------------------------
+// The same split as k_pass_k32 with t = t1 + 16 t2 and u = u2 + 8 u1:
+//   X[u2 + 8 u1] = sum_t1 r^(8 t1 u1) r^(t1 u2) sum_t2 x[t1 + 16 t2] r^(16 t2 u2).
+// An element is a whole wavefront, so a 256-thread workgroup takes one group
+// j.  Round A: wavefront w, for t1 = w, w + 4, w + 8, w + 12, loads slots
+// t1 + 16 t2 (t2 < 8), applies the pass twiddles, DFT_8 over t2 (root r^16),
+// multiplies output u2 by r^(t1 u2) and stores it to LDS (64 KiB).  Round B:
+// for u2 = w and w + 4, DFT_16 over t1 (root r^8); output u2 + 8 u1 goes to
+// (j - a) K + a + u Ns.
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2>
+__global__ __launch_bounds__(256) void k_pass_k64(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
+                                                  uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out,
+                                                  uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
+                                                  const uint32_t* __restrict__ tw2, int log2n, int log2ns,
+                                                  uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout) {
+  static_assert(KD == 64, "the split base case is built for k = 64");
+  typedef Geo<KD> Gm;
+  constexpr int KB = Gm::KB;
+  constexpr int LOGKB = ilog2(KB);
+  __shared__ uint64_t lds[KB * 64];  // [u2][t1][lane], 64 KiB
+  const int l = Gm::lane();
+  const int m = Gm::digit(l);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int log2nk = log2n - LOGKB;
+  const uint64_t nk = ngroups;
+  const uint64_t J = (uint64_t)blockIdx.x;  // group over all vectors (the grid covers them exactly)
+  const uint64_t vec = J >> log2nk;
+  const uint64_t j = J & (nk - 1);
+  const uint64_t ns = 1ull << log2ns;
+  const uint64_t a = j & (ns - 1);
+  in += vec * vin;
+  if constexpr (MODE == MODE_PRODUCT) in2 += vec * vin;
+  out += vec * vout;
+
+  // ---- round A (a run-time loop: four copies of 8 products are too much code)
+#pragma unroll 1
+  for (int h = 0; h < 4; ++h) {
+    const int t1 = w + 4 * h;
+    L96 v[8];
+    static_for<8>([&](auto T) {
+      constexpr int t2 = decltype(T)::value;
+      const uint64_t t = (uint64_t)(t1 + 16 * t2);
+      const uint64_t e = j + t * nk;
+      const uint64_t x = in[(uint64_t)m * sd_in + e * se_in];
+      slot_fence();
+      if constexpr (MODE != MODE_PLAIN) {
+        v[t2] = first_slot<KD, W, U, MODE>(x, in2 + e * se_in, tw, l, m);
+      } else if constexpr (T2) {
+        const int sh2 = log2n - 2 * LOGKB - log2ns;
+        v[t2] = (log2ns == 0) ? l96(x) : mul_entry<KD, W, U>(x, tw2 + ((a * t) << sh2) * TwLayout<KD>::WORDS, m);
+      } else {
+        if (log2ns == 0) {
+          v[t2] = l96(x);
+        } else {
+          const int shift = log2n - log2ns - LOGKB;
+          const uint64_t at = a * t;
+          const int rho = (int)(at >> log2ns);
+          const uint64_t c = at & (ns - 1);
+          const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
+          v[t2] = mul_twiddle<KD, W, U>(x, tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
+        }
+      }
+    });
+    dft_pow2<KD, INV, 3>(v, m);
+    static_for<8>([&](auto V) {
+      constexpr int u2 = decltype(V)::value;
+      const int e = (t1 * u2) & (2 * KD - 1);
+      const L96 y = l96_mul_rpow<KD>(v[u2], INV ? ((2 * KD - e) & (2 * KD - 1)) : e, l, m);
+      lds[(u2 * 16 + t1) * 64 + l] = seminorm<KD, W, U>(y, m);
+    });
+  }
+  __syncthreads();
+
+  // ---- round B
+  const uint64_t obase = (j - a) * KB + a;
+  static_for<2>([&](auto H) {
+    const int u2 = w + 4 * decltype(H)::value;
+    L96 v[16];
+    static_for<16>([&](auto T) {
+      constexpr int t1 = decltype(T)::value;
+      v[t1] = l96(lds[(u2 * 16 + t1) * 64 + l]);
+    });
+    dft_pow2<KD, INV, 4>(v, m);
+    static_for<16>([&](auto V) {
+      constexpr int u1 = decltype(V)::value;
+      const uint64_t u = (uint64_t)(u2 + 8 * u1);
+      uint64_t d;
+      if constexpr (LAST) {
+        d = canonicalize<KD, W, U>(v[u1], l, m);
+      } else {
+        d = seminorm<KD, W, U>(v[u1], m);
+      }
+      out[(uint64_t)m * sd_out + (obase + u * ns) * se_out] = d;
     });
   });
 }
@@ -637,12 +739,7 @@ __global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict_
     t = (OP == GFP_OP_ADD) ? l96_add(l96(xm), l96(ym)) : l96_sub(l96(xm), l96(ym));
   } else if constexpr (OP == GFP_OP_MUL || OP == GFP_OP_MUL_SCALE) {
     const uint64_t xm = x[(uint64_t)m * xsd + ee * xse];
-    uint64_t yd[KD];
-    static_for<KD>([&](auto T) {
-      constexpr int tt = decltype(T)::value;
-      yd[tt] = y[(uint64_t)tt * ysd + ee * yse];
-    });
-    t = mul_data<KD, W, U>(xm, yd, m);
+    t = mul_data_ptr<KD, W, U>(xm, y + ee * yse, ysd, l, m);
     if constexpr (OP == GFP_OP_MUL_SCALE) {
       const uint64_t sn = seminorm<KD, W, U>(t, m);
       t = mul_twiddle_pre<KD, W, U>(sn, cst, rot_lane<KD>(0, m), m);
@@ -751,6 +848,9 @@ hipError_t launch_pass_r_t(const PassArgs& p, hipStream_t st) {
     case 5:
       if constexpr (KD >= 32) return launch_pass_r_lr<KD, W, U, 5>(p, st);
       return hipErrorInvalidValue;
+    case 6:
+      if constexpr (KD >= 64) return launch_pass_r_lr<KD, W, U, 6>(p, st);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -786,6 +886,36 @@ hipError_t launch_pass_k32_t(const PassArgs& p, hipStream_t st) {
 }
 
 template <int KD, int W, int U>
+hipError_t launch_pass_k64_t(const PassArgs& p, hipStream_t st) {
+  constexpr int lk = ilog2(2 * KD);
+  if (p.log2n < lk || p.log2ns + lk > p.log2n) return hipErrorInvalidValue;
+  const uint64_t nb = p.ngroups * p.nvec;  // one group per workgroup
+  if (nb == 0) return hipSuccess;
+  if (nb > 0xFFFFFFFFull) return hipErrorInvalidValue;
+#define GFP_LAUNCH64(INV, MODE, LAST, T2)                                                                          \
+  hipLaunchKernelGGL((k_pass_k64<KD, W, U, INV, MODE, LAST, T2>), dim3((unsigned)nb), dim3(256), 0, st, p.in, p.in2, \
+                     p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.log2n, p.log2ns, p.ngroups, p.nvec, \
+                     p.vin, p.vout)
+  const bool t2 = !p.last && p.log2n - 2 * lk - p.log2ns >= 0;
+#define GFP_LAUNCH64_T(INV, MODE)                  \
+  if (p.last) GFP_LAUNCH64(INV, MODE, true, false); \
+  else if (t2) GFP_LAUNCH64(INV, MODE, false, true); \
+  else GFP_LAUNCH64(INV, MODE, false, false);
+  if (p.in2) {
+    GFP_LAUNCH64_T(true, MODE_PRODUCT)
+  } else if (p.scale) {
+    GFP_LAUNCH64_T(true, MODE_SCALE)
+  } else if (p.inverse) {
+    GFP_LAUNCH64_T(true, MODE_PLAIN)
+  } else {
+    GFP_LAUNCH64_T(false, MODE_PLAIN)
+  }
+#undef GFP_LAUNCH64_T
+#undef GFP_LAUNCH64
+  return hipGetLastError();
+}
+
+template <int KD, int W, int U>
 hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
   if (p.in2 && (!p.scale || p.sd_in != 1 || (p.se_in & 1) || (p.vin & 1) || (reinterpret_cast<uintptr_t>(p.in2) & 15)))
     return hipErrorInvalidValue;  // the product operand is read 16 bytes at a time
@@ -794,6 +924,8 @@ hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
   if (p.span != 1) return hipErrorInvalidValue;
   if constexpr (KD == 32) {
     return launch_pass_k32_t<KD, W, U>(p, st);
+  } else if constexpr (KD == 64) {
+    return launch_pass_k64_t<KD, W, U>(p, st);
   } else {
   const unsigned nb = blocks_for(p.ngroups * p.nvec, Geo<KD>::G);
   if (nb == 0) return hipSuccess;

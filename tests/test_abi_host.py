@@ -8,7 +8,7 @@ import re
 
 import pytest
 
-from oracle.field import GFPField, P8, P16, P32
+from oracle.field import GFPField, P8, P16, P32, P64
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "gfp.h")
@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("params", [P8, P16, P32, dict(k=8, r=2 ** 59 + 2 ** 16), dict(k=16, r=2 ** 58 + 2 ** 10)])
+@pytest.mark.parametrize("params", [P8, P16, P32, P64, dict(k=8, r=2 ** 59 + 2 ** 16), dict(k=16, r=2 ** 58 + 2 ** 10)])
 def test_field_create_info_and_roots(params):
     _lib()
     F = GFPField(**params)
@@ -192,6 +192,23 @@ def test_k32_field_host():
     assert f.plan(2 ** 18) == "111" and f.plan(8192) == "11" and f.plan(64) == "1"
     with pytest.raises(gfp.GFPError):
         f.set_plan(4096, "2")
+
+
+def test_k64_field_host():
+    """The k = 64 prime of Table 1 (r = 2^63 - 2^40, K = 128): roots as the
+    oracle's, sizes from K = 128 on, one radix-128 pass per launch; integer
+    products are not offered for a radix 2^W - 2^U."""
+    L = _lib()
+    f = gfp.Field(**P64)
+    F = GFPField(**P64)
+    out = (ctypes.c_uint64 * 64)()
+    for n in (128, 2 ** 14, 2 ** 20):
+        assert L.gfp_root_of_unity(f.handle, n, 0, out) == gfp.GFP_OK
+        assert [int(v) for v in out] == F.from_int(F.paper_root_of_unity(n))
+    assert f.polymul_size(1, 1) == 128 and f.polymul_size(2048, 2048) == 4096
+    assert f.plan(2 ** 14) == "11" and f.plan(2 ** 13) == "1" and f.plan(128) == "1"
+    b = ctypes.c_uint64()
+    assert L.gfp_bigint_mul_workspace_size(f.handle, 10, 10, ctypes.byref(b)) == gfp.GFP_EUNSUPPORTED
 
 
 def test_bigint_sizes():

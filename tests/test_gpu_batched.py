@@ -8,7 +8,7 @@ import pytest
 
 import gfp_inputs as gi
 from oracle import transform as T
-from oracle.field import GFPField, P8, P16, P32
+from oracle.field import GFPField, P8, P16, P32, P64
 from tests.helpers import canonical_mask, to_ints
 
 pytestmark = pytest.mark.gpu
@@ -35,7 +35,7 @@ def _batch(params, sizes, seed):
     return reqs, dev
 
 
-@pytest.mark.parametrize("params", [P8, P16, P32], ids=["k8", "k16", "k32"])
+@pytest.mark.parametrize("params", [P8, P16, P32, P64], ids=["k8", "k16", "k32", "k64"])
 def test_batched_mixed_sizes(torch_mod, params):
     import torch
 
@@ -66,10 +66,10 @@ def test_batched_mixed_sizes(torch_mod, params):
 # (256 = 16^2, plan 2) or the radix-8 pass (2048 = 8 16^2); k = 16: the
 # radix-2 pass (4096 = 2 32^2); k = 32: the radix-64 pass (4096 = 64^2).
 FUSED = [(P8, (2048, 2048), 64), (P8, (100, 100), 1024), (P8, (1000, 1000), 128), (P16, (2048, 2048), 64),
-         (P32, (2048, 2048), 64)]
+         (P32, (2048, 2048), 64), (P64, (2048, 2048), 64)]
 
 
-@pytest.mark.parametrize("params,size,count", FUSED, ids=["k8-one", "k8-pair", "k8-radix8", "k16", "k32"])
+@pytest.mark.parametrize("params,size,count", FUSED, ids=["k8-one", "k8-pair", "k8-radix8", "k16", "k32", "k64"])
 def test_fused_pointwise_product(torch_mod, params, size, count):
     """Products in a chunk of 2^18 elements take the pointwise product inside
     the inverse transform's first launch; one product alone takes the separate

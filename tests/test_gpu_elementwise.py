@@ -1,5 +1,5 @@
 """Field arithmetic kernels (section 2) against the oracle, bit-exact:
-addition, subtraction, multiplication by r^s and multiplication, on the six
+addition, subtraction, multiplication by r^s and multiplication, on the seven
 compiled radix shapes, with random operands and injected edge values."""
 
 import numpy as np
@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [dict(k=8, r=2 ** 63 + 2 ** 34), dict(k=16, r=2 ** 62 + 2 ** 36),
           dict(k=8, r=2 ** 59 + 2 ** 16), dict(k=16, r=2 ** 58 + 2 ** 10), dict(k=32, r=2 ** 62 + 2 ** 56),
-          dict(k=32, r=2 ** 56 + 2 ** 21)]
+          dict(k=32, r=2 ** 56 + 2 ** 21), dict(k=64, r=2 ** 63 - 2 ** 40)]
 
 
 @pytest.fixture(scope="module")
@@ -60,7 +60,7 @@ def test_add_sub_mul(torch_mod, params):
         assert not bad, (op, bad[:5], len(bad))
 
 
-@pytest.mark.parametrize("params", SHAPES[:2] + SHAPES[4:], ids=["k8", "k16", "k32", "k32t"])
+@pytest.mark.parametrize("params", SHAPES[:2] + SHAPES[4:], ids=["k8", "k16", "k32", "k32t", "k64"])
 def test_mul_pow_r_and_const(torch_mod, params):
     from paper_1811_01490_amd import Field, to_device, to_host
     from paper_1811_01490_amd.gfp import OP_MUL_CONST, OP_MUL_POW_R
@@ -85,9 +85,9 @@ def test_mul_pow_r_and_const(torch_mod, params):
     assert to_ints(z, r) == [(-v) % F.p for v in xi]
 
 
-@pytest.mark.parametrize("params", [SHAPES[0], SHAPES[4]], ids=["k8", "k32"])
+@pytest.mark.parametrize("params", [SHAPES[0], SHAPES[4], SHAPES[6]], ids=["k8", "k32", "k64"])
 def test_mul_large_random(torch_mod, params):
-    """200k random products on the k = 8 and k = 32 workload primes."""
+    """200k random products on the k = 8, 32 and 64 workload primes."""
     from paper_1811_01490_amd import Field, to_device, to_host
     from paper_1811_01490_amd.gfp import OP_MUL
 

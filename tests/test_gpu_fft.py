@@ -10,13 +10,13 @@ import pytest
 
 import gfp_inputs as gi
 from oracle import transform as T
-from oracle.field import GFPField, P8, P16, P32
+from oracle.field import GFPField, P8, P16, P32, P64
 from tests.helpers import canonical_mask, to_ints
 
 pytestmark = pytest.mark.gpu
 
 SHAPES = {"k8": P8, "k16": P16, "k8t": dict(k=8, r=2 ** 59 + 2 ** 16), "k16t": dict(k=16, r=2 ** 58 + 2 ** 10),
-          "k32": P32, "k32t": dict(k=32, r=2 ** 56 + 2 ** 21)}
+          "k32": P32, "k32t": dict(k=32, r=2 ** 56 + 2 ** 21), "k64": P64}
 
 
 @pytest.fixture(scope="module")
@@ -44,7 +44,10 @@ CASES = [("k8", 16), ("k8", 256), ("k8", 4096), ("k16", 32), ("k16", 1024),
          # two passes (the last with rotated twiddles); radix-2 + two passes
          # (the middle one from the w^(K i) table)
          ("k32", 64), ("k32", 128), ("k32", 2048), ("k32", 4096), ("k32", 8192),
-         ("k32t", 64), ("k32t", 4096), ("k32t", 8192)]
+         ("k32t", 64), ("k32t", 4096), ("k32t", 8192),
+         # k = 64 (K = 128): one pass; radix-2 + one pass; radix-64 + one
+         # pass; two passes; radix-2 + two passes
+         ("k64", 128), ("k64", 256), ("k64", 8192), ("k64", 16384), ("k64", 32768)]
 
 
 @pytest.mark.parametrize("name,N", CASES)
@@ -120,7 +123,8 @@ def test_in_place_and_padded_ld(torch_mod):
 
 
 @pytest.mark.parametrize("name,N", [("k8", 65536), ("k16", 32768), ("k8", 2 ** 17), ("k8", 2 ** 19),
-                                    ("k16", 2 ** 19), ("k16", 2 ** 16), ("k32", 2 ** 16), ("k32", 2 ** 17)])
+                                    ("k16", 2 ** 19), ("k16", 2 ** 16), ("k32", 2 ** 16), ("k32", 2 ** 17),
+                                    ("k64", 2 ** 16), ("k64", 2 ** 17)])
 def test_round_trip_mid(torch_mod, name, N):
     from paper_1811_01490_amd import to_device, to_host
 

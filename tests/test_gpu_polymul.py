@@ -9,7 +9,7 @@ import pytest
 
 import gfp_inputs as gi
 from oracle import transform as T
-from oracle.field import GFPField, P8, P16, P32
+from oracle.field import GFPField, P8, P16, P32, P64
 from tests.helpers import canonical_mask, to_ints
 
 pytestmark = pytest.mark.gpu
@@ -46,7 +46,7 @@ def test_degree_2048_schoolbook(torch_mod):
     assert not bad, (bad[:8], len(bad))
 
 
-@pytest.mark.parametrize("params", [P8, P16, P32], ids=["k8", "k16", "k32"])
+@pytest.mark.parametrize("params", [P8, P16, P32, P64], ids=["k8", "k16", "k32", "k64"])
 @pytest.mark.parametrize("la,lb", [(1, 1), (1, 17), (3, 5), (9, 8), (8, 9), (16, 1), (100, 157), (300, 1), (513, 512)])
 def test_ragged_schoolbook(torch_mod, params, la, lb):
     F, a, b, c = _run(params, la, lb, gi.BASE_SEED + la * 1000 + lb, edge=0.2)

@@ -9,7 +9,7 @@ import random
 
 import pytest
 
-from oracle.field import GFPField, P8, P16, P32, v2
+from oracle.field import GFPField, P8, P16, P32, P64, v2
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -76,7 +76,7 @@ def test_paper_mul_exhaustive(r, k):
             assert F.paper_mul(enc[a], enc[b]) == enc[a * b % F.p], (a, b)
 
 
-@pytest.mark.parametrize("params", [P8, P16, P32, dict(k=8, r=2 ** 59 + 2 ** 16), dict(k=16, r=2 ** 58 + 2 ** 10)])
+@pytest.mark.parametrize("params", [P8, P16, P32, P64, dict(k=8, r=2 ** 59 + 2 ** 16), dict(k=16, r=2 ** 58 + 2 ** 10)])
 def test_paper_algorithms_random_large(params):
     F = GFPField(**params)
     g = random.Random(7)
@@ -113,8 +113,8 @@ def test_negacyclic_column_bound():
         assert cols[F.k - 1] == F.k * (F.r - 1) ** 2  # the all-positive column
 
 
-@pytest.mark.parametrize("params", [P8, P16, P32, dict(k=8, r=2 ** 59 + 2 ** 16), dict(k=16, r=2 ** 58 + 2 ** 10),
-                                    dict(k=8, r=4), dict(k=4, r=4)])
+@pytest.mark.parametrize("params", [P8, P16, P32, P64, dict(k=8, r=2 ** 59 + 2 ** 16),
+                                    dict(k=16, r=2 ** 58 + 2 ** 10), dict(k=8, r=4), dict(k=4, r=4)])
 def test_field_structure(params):
     """r^k = -1, r^(2k) = 1 and r has order exactly 2k (section 2)."""
     F = GFPField(**params)
@@ -131,10 +131,11 @@ def test_workload_valuations():
     assert GFPField(**P8).max_log2_n == 272
     assert GFPField(**P16).max_log2_n == 576
     assert GFPField(**P32).max_log2_n == 1792
+    assert GFPField(**P64).max_log2_n == 2560
 
 
 @pytest.mark.parametrize("params,N", [(P8, 16), (P8, 256), (P8, 4096), (P8, 2 ** 20), (P16, 32), (P16, 1024), (P16, 2 ** 20),
-                                      (P32, 64), (P32, 4096), (P32, 2 ** 18),
+                                      (P32, 64), (P32, 4096), (P32, 2 ** 18), (P64, 128), (P64, 2 ** 14),
                                       (dict(k=8, r=4), 16), (dict(k=8, r=4), 256), (dict(k=4, r=4), 8)])
 def test_root_of_unity(params, N):
     """Alg. 1: w^(N/2k) = r, w^(N/2) = -1, w^N = 1 (w primitive)."""
