@@ -356,6 +356,52 @@ def bigint_leg(torch, dev, words: int, reps: int):
             "input_bits_per_s": round(2 * 64 * words / (ms * 1e-3), 1)}
 
 
+# The paper's element multiplication timings (Table multiplication, FFT-based
+# and GMP columns, serial CPU, machine unstated, printed in units of 10^-6 s)
+# for the Table 1 primes.
+PAPER_MUL = {8: (1303.38, 224.03), 16: (2602.56, 471.45), 32: (5500.56, 1282.36), 64: (10656.10, 3032.44)}
+ELEMENT_PRIMES = [(8, 2 ** 63 + 2 ** 34, "2^63+2^34"), (16, 2 ** 62 + 2 ** 36, "2^62+2^36"),
+                  (32, 2 ** 62 + 2 ** 56, "2^62+2^56"), (64, 2 ** 63 - 2 ** 40, "2^63-2^40")]
+
+
+def element_leg(torch, dev, n: int, reps: int):
+    """Element products z = x y on n uniform random elements of each Table 1
+    prime, by the two multipliers (the schoolbook columns the transforms use,
+    and the FFT-based product of section 3.3), operands resident in HBM; time
+    per launch with HIP events, results compared."""
+    import gfp_inputs as gi
+    from paper_1811_01490_amd import Field, to_device
+    from paper_1811_01490_amd.gfp import OP_MUL, OP_MUL_NTT
+
+    rows = []
+    for k, r, label in ELEMENT_PRIMES:
+        f = Field(k, r)
+        x = to_device(gi.uniform_digits(k, r, n, gi.BASE_SEED + 7, 0), dev)
+        y = to_device(gi.uniform_digits(k, r, n, gi.BASE_SEED + 7, 1), dev)
+        z = {op: torch.empty_like(x) for op in (OP_MUL, OP_MUL_NTT)}
+        row = {"k": k, "r": label, "elements": n}
+        for op, name in ((OP_MUL, "schoolbook"), (OP_MUL_NTT, "fft_based")):
+            for _ in range(3):
+                f.elementwise(op, x, y, z=z[op])
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                f.elementwise(op, x, y, z=z[op])
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / reps * 1e3
+            row[name + "_us"] = round(us, 2)
+            row[name + "_products_per_s"] = round(n / (us * 1e-6), 1)
+        row["identical"] = bool(torch.equal(z[OP_MUL], z[OP_MUL_NTT]))
+        row["fft_based_over_schoolbook"] = round(row["fft_based_us"] / row["schoolbook_us"], 2)
+        row["paper_fft_based"], row["paper_gmp"] = PAPER_MUL[k]
+        rows.append(row)
+        f.close()
+    return {"workload": "element products over the Table 1 primes, uniform random operands (seed 1811014907)",
+            "paper_units": "as printed in the paper's Table multiplication (10^-6 s scale, serial CPU)", "rows": rows}
+
+
 # The paper's FFT timings (Table fftoverprimefield, FFT-based column, serial
 # CPU, machine unstated, units inferred as ms) for its test primes (Table
 # testprimes).
@@ -418,6 +464,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-bigint", action="store_true")
     ap.add_argument("--no-paper-context", action="store_true")
+    ap.add_argument("--no-element", action="store_true")
+    ap.add_argument("--element-log2", type=int, default=20)
     ap.add_argument("--bigint-words", type=int, default=2 ** 18)
     ap.add_argument("--served-requests", type=int, default=10000)
     ap.add_argument("--served-loads", default="0.5,0.7,0.9",
@@ -562,6 +610,8 @@ def main():
         out["bigint"] = bigint_leg(torch, dev, args.bigint_words, 20)
     if not args.no_paper_context:
         out["paper_context"] = paper_context_leg(torch, dev)
+    if not args.no_element:
+        out["element_products"] = element_leg(torch, dev, 1 << args.element_log2, 20)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
     print(json.dumps(out), flush=True)

@@ -62,6 +62,7 @@ extern "C" {
 #define GFP_OP_MUL_POW_R 3 /* z = x * r^s (section 2.3), y unused */
 #define GFP_OP_MUL_CONST 4 /* z = x * c * r^s, c = host digits c_host */
 #define GFP_OP_MUL_SCALE 5 /* z = x * y * c, c = host digits c_host */
+#define GFP_OP_MUL_NTT 6   /* z = x * y by the FFT-based product (section 3.3) */
 
 typedef struct gfp_field gfp_field;
 
@@ -195,7 +196,10 @@ int gfp_polymul_batched(const gfp_field* f, uint32_t n, const gfp_polymul_desc* 
  * (y unused for GFP_OP_MUL_POW_R and GFP_OP_MUL_CONST); z may equal x or y.
  * s: the exponent for GFP_OP_MUL_POW_R / GFP_OP_MUL_CONST (any integer,
  * taken mod 2k).  c_host: k host digits of the constant c for
- * GFP_OP_MUL_CONST and GFP_OP_MUL_SCALE, else ignored. */
+ * GFP_OP_MUL_CONST and GFP_OP_MUL_SCALE, else ignored.  GFP_OP_MUL and
+ * GFP_OP_MUL_NTT give the same products by two algorithms: the schoolbook
+ * column product the transforms use, and the FFT-based multiplication of
+ * section 3.3 (negacyclic convolutions modulo three word primes, CRT). */
 int gfp_elementwise(const gfp_field* f, int op, const uint64_t* x, uint64_t ld_x, const uint64_t* y, uint64_t ld_y,
                     uint64_t* z, uint64_t ld_z, uint64_t n, int64_t s, const uint64_t* c_host, void* stream);
 

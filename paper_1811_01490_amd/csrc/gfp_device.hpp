@@ -477,6 +477,52 @@ __device__ __forceinline__ RotLane<KD> rot_lane(int rot, int m) {
   return r;
 }
 
+// Column C = (l0, l1, h0, h1, h2) (signed 160-bit, h2 the top word) of lane
+// m as C = Q r + T; returns the lazy digit T_m + Q_{m-1} (lane 0 takes
+// -Q_{k-1}, since r^k = -1).
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 column_tail(uint32_t l0, uint32_t l1, uint32_t h0, uint32_t h1, uint32_t h2, int m) {
+  typedef Field<KD, W, U> F;
+  if constexpr (F::SPLIT) {
+    uint64_t T;
+    L96 Qs;
+    if constexpr (F::NEG) {
+      split_qr160_m23(l0, l1, h0, h1, h2, T, Qs);
+    } else {
+      split_qr160(l0, l1, h0, h1, h2, T, Qs);
+    }
+    const L96 nqs = l96_sub(L96{0, 0}, Qs);
+    return l96_add(l96(T), l96_rot<KD, 1>((m == KD - 1) ? nqs : Qs));
+  } else {
+  constexpr int SA = F::SA, SB = F::SB;
+  unsigned cy;
+  // fold 1 (2^64 = a r - b): C = a H r + V, V = L - b H; keep V's low 64
+  // bits (v0w, v1w) and Vh = V >> 64 (|Vh| < 2^45)
+  uint32_t v0w, v1w, v2w, v3w;
+  sub_shifted96<SB>(l0, l1, h0, h1, h2, v0w, v1w, v2w, v3w);
+  // fold 2: V = a Vh r + W, W = Vl - b Vh; Wh = W >> 64 (|Wh| < 2^20)
+  uint32_t w0w, w1w, w2w;
+  sub_shifted64<SB>(v0w, v1w, v2w, v3w, w0w, w1w, w2w);
+  // fold 3: T = Wl - b Wh, |T| < 2^65
+  L96 Tm = sub_shifted32<SB>(w0w, w1w, w2w);
+  // Q = a (H + Vh + Wh)
+  const uint32_t vs = (uint32_t)((int32_t)v3w >> 31), ws = (uint32_t)((int32_t)w2w >> 31);
+  uint32_t g0 = __builtin_addc(h0, v2w, 0u, &cy);
+  uint32_t g1 = __builtin_addc(h1, v3w, cy, &cy);
+  uint32_t g2 = h2 + vs + cy;
+  g0 = __builtin_addc(g0, w2w, 0u, &cy);
+  g1 = __builtin_addc(g1, ws, cy, &cy);
+  g2 = g2 + ws + cy;
+  L96 Q;
+  Q.lo = ((uint64_t)g1 << 32 | g0) << SA;
+  Q.hi = (int32_t)((g2 << SA) | (g1 >> (32 - SA)));
+  // Q_{m-1} into lane m; lane 0 takes -Q_{k-1}
+  const L96 nq = l96_sub(L96{0, 0}, Q);
+  const L96 qs = (m == KD - 1) ? nq : Q;
+  return l96_add(Tm, l96_rot<KD, 1>(qs));
+  }
+}
+
 // Core.  (v0, v1): the lane's starting x digit (rotated, complemented).
 // yl(t, y0, y1, y2): the three limbs of y_t (t a compile-time constant for
 // k <= 32, an int for k = 64).
@@ -485,7 +531,6 @@ __device__ __forceinline__ RotLane<KD> rot_lane(int rot, int m) {
 template <int KD, int W, int U, class YL>
 __device__ __forceinline__ L96 mul_core_y(uint32_t v0, uint32_t v1, YL&& yl, uint32_t s0, uint32_t s1, uint32_t s2,
                                           int m) {
-  typedef Field<KD, W, U> F;
   const uint32_t wrap = (m == 0) ? 0xFFFFFFFFu : 0u;
   uint64_t a00 = 0, a01 = 0, a02 = 0, a10 = 0, a11 = 0, a12 = 0;
   if constexpr (KD == 64) {
@@ -547,43 +592,7 @@ __device__ __forceinline__ L96 mul_core_y(uint32_t v0, uint32_t v1, YL&& yl, uin
   h0 = __builtin_subc(h0, s0, 0u, &cy);
   h1 = __builtin_subc(h1, s1, cy, &cy);
   h2 = h2 - s2 - cy;
-  if constexpr (F::SPLIT) {
-    uint64_t T;
-    L96 Qs;
-    if constexpr (F::NEG) {
-      split_qr160_m23(l0, l1, h0, h1, h2, T, Qs);
-    } else {
-      split_qr160(l0, l1, h0, h1, h2, T, Qs);
-    }
-    const L96 nqs = l96_sub(L96{0, 0}, Qs);
-    return l96_add(l96(T), l96_rot<KD, 1>((m == KD - 1) ? nqs : Qs));
-  } else {
-  constexpr int SA = F::SA, SB = F::SB;
-  // fold 1 (2^64 = a r - b): C = a H r + V, V = L - b H; keep V's low 64
-  // bits (v0w, v1w) and Vh = V >> 64 (|Vh| < 2^45)
-  uint32_t v0w, v1w, v2w, v3w;
-  sub_shifted96<SB>(l0, l1, h0, h1, h2, v0w, v1w, v2w, v3w);
-  // fold 2: V = a Vh r + W, W = Vl - b Vh; Wh = W >> 64 (|Wh| < 2^20)
-  uint32_t w0w, w1w, w2w;
-  sub_shifted64<SB>(v0w, v1w, v2w, v3w, w0w, w1w, w2w);
-  // fold 3: T = Wl - b Wh, |T| < 2^65
-  L96 Tm = sub_shifted32<SB>(w0w, w1w, w2w);
-  // Q = a (H + Vh + Wh)
-  const uint32_t vs = (uint32_t)((int32_t)v3w >> 31), ws = (uint32_t)((int32_t)w2w >> 31);
-  uint32_t g0 = __builtin_addc(h0, v2w, 0u, &cy);
-  uint32_t g1 = __builtin_addc(h1, v3w, cy, &cy);
-  uint32_t g2 = h2 + vs + cy;
-  g0 = __builtin_addc(g0, w2w, 0u, &cy);
-  g1 = __builtin_addc(g1, ws, cy, &cy);
-  g2 = g2 + ws + cy;
-  L96 Q;
-  Q.lo = ((uint64_t)g1 << 32 | g0) << SA;
-  Q.hi = (int32_t)((g2 << SA) | (g1 >> (32 - SA)));
-  // Q_{m-1} into lane m; lane 0 takes -Q_{k-1}
-  const L96 nq = l96_sub(L96{0, 0}, Q);
-  const L96 qs = (m == KD - 1) ? nq : Q;
-  return l96_add(Tm, l96_rot<KD, 1>(qs));
-  }
+  return column_tail<KD, W, U>(l0, l1, h0, h1, h2, m);
 }
 
 template <int KD, int W, int U>
@@ -808,6 +817,114 @@ __device__ __forceinline__ L96 mul_data_ptr(uint64_t x, const uint64_t* __restri
     });
     return mul_data<KD, W, U>(x, yd, m);
   }
+}
+
+// ------------------------------------------------------------------------
+// The FFT-based element product (section 3.3)
+// ------------------------------------------------------------------------
+// x y mod p through the negacyclic convolution of the digit vectors: for
+// each of three word primes q (q < 2^62, 2k | q - 1) the columns u_m mod q
+// are A' InverseDFT(DFT(A x) DFT(A y)) with A = (1, theta, ..., theta^(k-1)),
+// theta a primitive 2k-th root mod q (the negacyclic convolution algorithm of
+// section 3.3); the three residues give u_m exactly by the CRT (|u_m| <
+// k 2^128 < q1 q2 q3 / 2, so three primes where the paper's two 61-bit primes
+// bound k r^2 below 2^121), and u_m goes through the same fold into radix r
+// as the schoolbook columns.  One lane per coefficient: the length-k DFTs
+// are radix-2 butterflies between lanes (decimation in frequency forward,
+// bit-reversed spectrum, decimation in time back).  Arithmetic mod q is
+// Montgomery with 2^64; table constants are stored in Montgomery form.
+//
+// Table (u64 words, built on the host per field and device):
+//   [0..2] q_i, [3..5] -q_i^-1 mod 2^64, [6] q1^-1 mod q2, [7] q1 mod q3,
+//   [8] (q1 q2)^-1 mod q3 (the three in Montgomery form), [9..10] q1 q2,
+//   [11..13] Q = q1 q2 q3, [14..16] (Q - 1) / 2, then per prime i at
+//   NTT_HEAD + 3k i: theta^m (k), theta^-m k^-1 2^64 (k), w^j and w^-j
+//   (k / 2 each), w = theta^2.
+constexpr int NTT_HEAD = 20;
+
+__device__ __forceinline__ uint64_t mont_mul(uint64_t a, uint64_t b, uint64_t q, uint64_t qn) {
+  // a b < q 2^64; returns a b 2^-64 mod q in [0, q)
+  const u128 t = (u128)a * b;
+  const uint64_t mm = (uint64_t)t * qn;
+  const u128 u = t + (u128)mm * q;  // < 2^65 q < 2^127, low 64 bits zero
+  const uint64_t r = (uint64_t)(u >> 64);
+  return r >= q ? r - q : r;
+}
+__device__ __forceinline__ uint64_t add_q(uint64_t a, uint64_t b, uint64_t q) {
+  const uint64_t s = a + b;
+  return s >= q ? s - q : s;
+}
+__device__ __forceinline__ uint64_t sub_q(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
+
+template <int KD>
+__device__ __forceinline__ uint64_t lane_xchg(uint64_t v, int src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_ntt(uint64_t x, uint64_t y, const uint64_t* __restrict__ tb, int l, int m) {
+  constexpr int LK = ilog2(KD);
+  uint64_t u[3];
+  static_for<3>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const uint64_t q = tb[i], qn = tb[3 + i];
+    const uint64_t* b = tb + NTT_HEAD + 3 * KD * i;
+    // A x, A y (x, y < 2^64 and theta^m < q: the products stay below q 2^64)
+    uint64_t xv = mont_mul(x, b[m], q, qn);
+    uint64_t yv = mont_mul(y, b[m], q, qn);
+    // forward DFTs: half sizes k/2, ..., 1; the upper lane of a pair takes
+    // (a - b) w^(j k / (2h)), the lower a + b
+    static_for<LK>([&](auto S) {
+      constexpr int h = KD >> (decltype(S)::value + 1);
+      const int src = Geo<KD>::lane_of(l, m ^ h);
+      const bool up = (m & h) != 0;
+      const uint64_t w = b[2 * KD + (m & (h - 1)) * (KD / (2 * h))];
+      const uint64_t px = lane_xchg<KD>(xv, src), py = lane_xchg<KD>(yv, src);
+      xv = up ? mont_mul(sub_q(px, xv, q), w, q, qn) : add_q(xv, px, q);
+      yv = up ? mont_mul(sub_q(py, yv, q), w, q, qn) : add_q(yv, py, q);
+    });
+    uint64_t uv = mont_mul(xv, yv, q, qn);  // carries a factor 2^-64
+    // inverse DFT: half sizes 1, ..., k/2; the upper lane first takes b w^-j
+    static_for<LK>([&](auto S) {
+      constexpr int h = 1 << decltype(S)::value;
+      const int src = Geo<KD>::lane_of(l, m ^ h);
+      const bool up = (m & h) != 0;
+      const uint64_t w = b[2 * KD + KD / 2 + (m & (h - 1)) * (KD / (2 * h))];
+      const uint64_t bw = up ? mont_mul(uv, w, q, qn) : uv;
+      const uint64_t pu = lane_xchg<KD>(bw, src);
+      uv = up ? sub_q(pu, bw, q) : add_q(bw, pu, q);
+    });
+    // theta^-m / k, and the 2^64 of the pointwise product
+    u[i] = mont_mul(uv, b[KD + m], q, qn);
+  });
+  // CRT (Garner): u = v1 + q1 v2 + q1 q2 v3, then into (-Q/2, Q/2]
+  const uint64_t q1 = tb[0], q2 = tb[1], q3 = tb[2];
+  const uint64_t v1 = u[0];
+  const uint64_t v1b = v1 >= q2 ? v1 - q2 : v1;
+  const uint64_t v2 = mont_mul(sub_q(u[1], v1b, q2), tb[6], q2, tb[4]);
+  const uint64_t v1c = v1 >= q3 ? v1 - q3 : v1;
+  const uint64_t t3 = sub_q(sub_q(u[2], v1c, q3), mont_mul(v2, tb[7], q3, tb[5]), q3);
+  const uint64_t v3 = mont_mul(t3, tb[8], q3, tb[5]);
+  const u128 a = (u128)q1 * v2 + v1;                  // < 2^125
+  const u128 blo = (u128)tb[9] * v3, bhi = (u128)tb[10] * v3;
+  const u128 w0 = (u128)(uint64_t)a + (uint64_t)blo;
+  const u128 w1 = (a >> 64) + (blo >> 64) + (uint64_t)bhi + (w0 >> 64);
+  const uint64_t z0 = (uint64_t)w0, z1 = (uint64_t)w1;
+  const uint64_t z2 = (uint64_t)(bhi >> 64) + (uint64_t)(w1 >> 64);
+  // z > (Q - 1) / 2 ?  then z - Q (two's complement; the true value fits)
+  const bool big = (z2 != tb[16]) ? (z2 > tb[16]) : (z1 != tb[15]) ? (z1 > tb[15]) : (z0 > tb[14]);
+  uint64_t c0 = z0, c1 = z1, c2 = z2;
+  if (big) {
+    const u128 d0 = (u128)z0 - tb[11];
+    const u128 d1 = (u128)z1 - tb[12] - (uint64_t)((d0 >> 64) != 0);
+    c0 = (uint64_t)d0;
+    c1 = (uint64_t)d1;
+    c2 = z2 - tb[13] - (uint64_t)((d1 >> 64) != 0);
+  }
+  return column_tail<KD, W, U>((uint32_t)c0, (uint32_t)(c0 >> 32), (uint32_t)c1, (uint32_t)(c1 >> 32),
+                               (uint32_t)c2, m);
 }
 
 // ------------------------------------------------------------------------

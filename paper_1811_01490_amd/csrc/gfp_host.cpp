@@ -37,6 +37,7 @@ struct DevTables {
 
 struct DevConsts {
   uint32_t* one = nullptr;  // one entry: 1
+  uint64_t* ntt = nullptr;  // constants of the FFT-based element product
 };
 
 }  // namespace
@@ -274,7 +275,7 @@ int get_one(gfp_field* f, const uint32_t** out) {
   if (he != hipSuccess) return hip_status(he);
   std::lock_guard<std::mutex> g(f->mu);
   auto it = f->consts.find(dev);
-  if (it != f->consts.end()) {
+  if (it != f->consts.end() && it->second.one) {
     *out = it->second.one;
     return GFP_OK;
   }
@@ -282,11 +283,123 @@ int get_one(gfp_field* f, const uint32_t** out) {
   dg[0] = 1;
   std::vector<uint32_t> host(gfpk::tw_words((int)f->k));
   make_entry(f->k, dg.data(), host.data());
-  DevConsts c;
-  int rc = upload(host, &c.one);
+  uint32_t* one = nullptr;
+  int rc = upload(host, &one);
   if (rc != GFP_OK) return rc;
-  f->consts[dev] = c;
-  *out = c.one;
+  f->consts[dev].one = one;
+  *out = one;
+  return GFP_OK;
+}
+
+// ---- constants of the FFT-based element product (section 3.3) ----------------
+// Three word primes q < 2^62 with q = 1 (mod 128), so that every 2k <= 128
+// divides q - 1; a primitive 2k-th root theta = g^((q-1)/2k) from the
+// smallest quadratic non-residue g; Montgomery form with 2^64; CRT words.
+// The layout is the one the device code reads (NTT_HEAD = 20 header words).
+typedef unsigned __int128 u128h;
+uint64_t mulm(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128h)a * b % q); }
+uint64_t powm(uint64_t a, uint64_t e, uint64_t q) {
+  uint64_t r = 1 % q;
+  for (a %= q; e; e >>= 1, a = mulm(a, a, q))
+    if (e & 1) r = mulm(r, a, q);
+  return r;
+}
+bool prime64(uint64_t n) {  // deterministic Miller-Rabin for n < 2^64
+  if (n < 2) return false;
+  for (uint64_t p : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull, 17ull, 19ull, 23ull, 29ull, 31ull, 37ull})
+    if (n % p == 0) return n == p;
+  uint64_t d = n - 1;
+  int s = 0;
+  while (!(d & 1)) d >>= 1, ++s;
+  for (uint64_t a : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull, 17ull, 19ull, 23ull, 29ull, 31ull, 37ull}) {
+    uint64_t x = powm(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int i = 1; i < s && comp; ++i) {
+      x = mulm(x, x, n);
+      if (x == n - 1) comp = false;
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+std::vector<uint64_t> ntt_constants(uint32_t k) {
+  uint64_t q[3];
+  int found = 0;
+  for (uint64_t c = (1ull << 62) - 127; found < 3; c -= 128)  // c = 1 (mod 128)
+    if (prime64(c)) q[found++] = c;
+  std::vector<uint64_t> t(20 + 9 * k, 0);
+  auto mont = [](uint64_t a, uint64_t qq) { return (uint64_t)(((u128h)(a % qq) << 64) % qq); };
+  for (int i = 0; i < 3; ++i) {
+    const uint64_t qq = q[i];
+    uint64_t inv = 1;  // q^-1 mod 2^64 by Newton iteration
+    for (int it = 0; it < 7; ++it) inv *= 2 - qq * inv;
+    t[i] = qq;
+    t[3 + i] = 0 - inv;
+    uint64_t g = 2;
+    while (powm(g, (qq - 1) / 2, qq) != qq - 1) ++g;
+    const uint64_t th = powm(g, (qq - 1) / (2 * k), qq), thi = powm(th, qq - 2, qq);
+    const uint64_t om = mulm(th, th, qq), omi = mulm(thi, thi, qq);
+    const uint64_t kinv = powm(k, qq - 2, qq);
+    const uint64_t r128 = mulm(mont(1, qq), mont(1, qq), qq);  // 2^128 mod q
+    uint64_t* b = t.data() + 20 + 3 * k * i;
+    for (uint32_t m = 0; m < k; ++m) {
+      b[m] = mont(powm(th, m, qq), qq);
+      b[k + m] = mulm(mulm(powm(thi, m, qq), kinv, qq), r128, qq);
+    }
+    for (uint32_t j = 0; j < k / 2; ++j) {
+      b[2 * k + j] = mont(powm(om, j, qq), qq);
+      b[2 * k + k / 2 + j] = mont(powm(omi, j, qq), qq);
+    }
+  }
+  t[6] = mont(powm(q[0] % q[1], q[1] - 2, q[1]), q[1]);
+  t[7] = mont(q[0] % q[2], q[2]);
+  t[8] = mont(powm(mulm(q[0] % q[2], q[1] % q[2], q[2]), q[2] - 2, q[2]), q[2]);
+  const u128h q12 = (u128h)q[0] * q[1];
+  t[9] = (uint64_t)q12;
+  t[10] = (uint64_t)(q12 >> 64);
+  // Q = q12 q3 and (Q - 1) / 2, 192-bit
+  const u128h lo = (u128h)t[9] * q[2], hi = (u128h)t[10] * q[2] + (uint64_t)(lo >> 64);
+  t[11] = (uint64_t)lo;
+  t[12] = (uint64_t)hi;
+  t[13] = (uint64_t)(hi >> 64);
+  const uint64_t m0 = t[11] - 1;  // Q is odd: Q - 1 has no borrow
+  t[14] = (m0 >> 1) | (t[12] << 63);
+  t[15] = (t[12] >> 1) | (t[13] << 63);
+  t[16] = t[13] >> 1;
+  return t;
+}
+
+int get_ntt(gfp_field* f, const uint64_t** out) {
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return hip_status(he);
+  {
+    std::lock_guard<std::mutex> g(f->mu);
+    auto it = f->consts.find(dev);
+    if (it != f->consts.end() && it->second.ntt) {
+      *out = it->second.ntt;
+      return GFP_OK;
+    }
+  }
+  const std::vector<uint64_t> t = ntt_constants(f->k);
+  void* p = nullptr;
+  he = hipMalloc(&p, t.size() * 8);
+  if (he != hipSuccess) return hip_status(he);
+  he = hipMemcpyAsync(p, t.data(), t.size() * 8, hipMemcpyHostToDevice, hipStreamPerThread);
+  if (he == hipSuccess) he = hipStreamSynchronize(hipStreamPerThread);
+  if (he != hipSuccess) {
+    (void)hipFree(p);
+    return hip_status(he);
+  }
+  std::lock_guard<std::mutex> g(f->mu);
+  DevConsts& c = f->consts[dev];
+  if (c.ntt) {
+    (void)hipFree(p);
+  } else {
+    c.ntt = (uint64_t*)p;
+  }
+  *out = c.ntt;
   return GFP_OK;
 }
 
@@ -748,6 +861,7 @@ int gfp_field_destroy(gfp_field* f) {
   for (auto& kv : f->consts) {
     (void)hipSetDevice(kv.first);
     (void)hipFree(kv.second.one);
+    (void)hipFree(kv.second.ntt);
   }
   for (auto& kv : f->graphs) (void)hipGraphExecDestroy(kv.second.exec);
   if (!f->tables.empty() || !f->consts.empty()) (void)hipSetDevice(dev);
@@ -1062,8 +1176,9 @@ int gfp_elementwise(const gfp_field* cf, int op, const uint64_t* x, uint64_t ld_
   gfp_field* f = const_cast<gfp_field*>(cf);
   if (!f || !x || !z) return GFP_EINVAL;
   if (!f->gpu_shape) return GFP_EUNSUPPORTED;
-  if (op < GFP_OP_ADD || op > GFP_OP_MUL_SCALE) return GFP_EINVAL;
-  const bool needs_y = (op == GFP_OP_ADD || op == GFP_OP_SUB || op == GFP_OP_MUL || op == GFP_OP_MUL_SCALE);
+  if (op < GFP_OP_ADD || op > GFP_OP_MUL_NTT) return GFP_EINVAL;
+  const bool needs_y = (op == GFP_OP_ADD || op == GFP_OP_SUB || op == GFP_OP_MUL || op == GFP_OP_MUL_SCALE ||
+                        op == GFP_OP_MUL_NTT);
   const bool needs_c = (op == GFP_OP_MUL_CONST || op == GFP_OP_MUL_SCALE);
   if (needs_y && !y) return GFP_EINVAL;
   if (needs_c && !c_host) return GFP_EINVAL;
@@ -1094,6 +1209,11 @@ int gfp_elementwise(const gfp_field* cf, int op, const uint64_t* x, uint64_t ld_
   } else if (op == GFP_OP_MUL_POW_R) {
     int rc = get_one(f, &cst);
     if (rc != GFP_OK) return rc;
+  } else if (op == GFP_OP_MUL_NTT) {
+    const uint64_t* t = nullptr;
+    int rc = get_ntt(f, &t);
+    if (rc != GFP_OK) return rc;
+    cst = reinterpret_cast<const uint32_t*>(t);
   }
   gfpk::EwArgs a;
   a.op = op;

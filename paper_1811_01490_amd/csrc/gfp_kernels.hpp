@@ -744,6 +744,11 @@ __global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict_
       const uint64_t sn = seminorm<KD, W, U>(t, m);
       t = mul_twiddle_pre<KD, W, U>(sn, cst, rot_lane<KD>(0, m), m);
     }
+  } else if constexpr (OP == GFP_OP_MUL_NTT) {
+    // the FFT-based product: each lane needs only its own digits
+    const uint64_t xm = x[(uint64_t)m * xsd + ee * xse];
+    const uint64_t ym = y[(uint64_t)m * ysd + ee * yse];
+    t = mul_ntt<KD, W, U>(xm, ym, reinterpret_cast<const uint64_t*>(cst), l, m);
   } else {  // GFP_OP_MUL_CONST: x * c * r^s; GFP_OP_MUL_POW_R: the same with c = 1
     const RotLane<KD> rl = rot_lane<KD>((int)(((s % (2 * KD)) + 2 * KD) % (2 * KD)), m);
     const uint64_t xs = x[(uint64_t)rl.src * xsd + ee * xse];
@@ -974,6 +979,7 @@ hipError_t launch_elementwise_t(const EwArgs& a, hipStream_t st) {
     case GFP_OP_MUL_POW_R: GFP_LAUNCH_EW(GFP_OP_MUL_POW_R); break;
     case GFP_OP_MUL_CONST: GFP_LAUNCH_EW(GFP_OP_MUL_CONST); break;
     case GFP_OP_MUL_SCALE: GFP_LAUNCH_EW(GFP_OP_MUL_SCALE); break;
+    case GFP_OP_MUL_NTT: GFP_LAUNCH_EW(GFP_OP_MUL_NTT); break;
     default: return hipErrorInvalidValue;
   }
 #undef GFP_LAUNCH_EW

@@ -28,7 +28,7 @@ GFP_ENOTPRIME = 6
 GFP_ECANCELED = 7
 GFP_EPENDING = 8
 
-OP_ADD, OP_SUB, OP_MUL, OP_MUL_POW_R, OP_MUL_CONST, OP_MUL_SCALE = range(6)
+OP_ADD, OP_SUB, OP_MUL, OP_MUL_POW_R, OP_MUL_CONST, OP_MUL_SCALE, OP_MUL_NTT = range(7)
 BATCH_GRAPH = 1
 LAYOUT_DIGIT_MAJOR, LAYOUT_ELEMENT_MAJOR = 0, 1
 

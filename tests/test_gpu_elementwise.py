@@ -1,6 +1,7 @@
 """Field arithmetic kernels (section 2) against the oracle, bit-exact:
-addition, subtraction, multiplication by r^s and multiplication, on the seven
-compiled radix shapes, with random operands and injected edge values."""
+addition, subtraction, multiplication by r^s and multiplication (schoolbook
+and FFT-based), on the seven compiled radix shapes, with random operands and
+injected edge values."""
 
 import numpy as np
 import pytest
@@ -102,6 +103,27 @@ def test_mul_large_random(torch_mod, params):
     assert canonical_mask(z, r).all()
     bad = [i for i in range(n) if zi[i] != xi[i] * yi[i] % F.p]
     assert not bad, bad[:5]
+
+
+@pytest.mark.parametrize("params", SHAPES, ids=lambda p: "k%d" % p["k"] + ("r%x" % p["r"])[:6])
+def test_mul_ntt(torch_mod, params):
+    """The FFT-based product (section 3.3: negacyclic convolutions modulo word
+    primes, CRT) gives x y mod p, the same as the schoolbook product, on
+    random operands and every pair of edge values."""
+    from paper_1811_01490_amd import Field, to_device, to_host
+    from paper_1811_01490_amd.gfp import OP_MUL, OP_MUL_NTT
+
+    k, r = params["k"], params["r"]
+    F = GFPField(k, r)
+    n = 3001
+    x, y = _operands(params, n, gi.BASE_SEED + 81)
+    f = Field(k, r)
+    dx, dy = to_device(x), to_device(y)
+    z = to_host(f.elementwise(OP_MUL_NTT, dx, dy))
+    assert canonical_mask(z, r).all()
+    xi, yi = to_ints(x, r), to_ints(y, r)
+    assert to_ints(z, r) == [a * b % F.p for a, b in zip(xi, yi)]
+    assert np.array_equal(z, to_host(f.elementwise(OP_MUL, dx, dy)))
 
 
 def test_check_canonical(torch_mod):
