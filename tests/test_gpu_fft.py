@@ -156,3 +156,37 @@ def test_full_size_sampled(torch_mod, name, N):
         assert got == T.horner(xi, pow(w, i, F.p), F.p), i
     back = to_host(f.fft_inverse(y))
     assert np.array_equal(back, x)
+
+
+def _digit_sums(x: np.ndarray, sel) -> list:
+    """Exact sums of the digits x[d, sel] as Python integers (32-bit halves
+    summed in uint64, which cannot overflow for 2^25 terms)."""
+    v = x[:, sel]
+    lo = (v & np.uint64(0xFFFFFFFF)).sum(axis=1, dtype=np.uint64)
+    hi = (v >> np.uint64(32)).sum(axis=1, dtype=np.uint64)
+    return [int(a) + (int(b) << 32) for a, b in zip(lo, hi)]
+
+
+@pytest.mark.parametrize("name", ["k8", "k16"])
+def test_maximum_size(torch_mod, name):
+    """The largest transform the library takes, N = 2^25: round trip exact,
+    and the two outputs any size fixes by definition, Y_0 = sum x_i and
+    Y_(N/2) = sum (-1)^i x_i (w^(N/2) = -1), from exact digit sums."""
+    import torch
+
+    from paper_1811_01490_amd import to_host
+
+    F, f = _field(name)
+    k, r, N = F.k, F.r, 2 ** 25
+    x = gi.uniform_digits(k, r, N, gi.BASE_SEED + 25, 0)
+    dx = torch.from_numpy(x.view(np.int64)).cuda()
+    y = f.fft_forward(dx)
+    yh = to_host(y[:, [0, N // 2]].contiguous())
+    ev, od = _digit_sums(x, slice(0, N, 2)), _digit_sums(x, slice(1, N, 2))
+    tot = sum((e + o) * r ** d for d, (e, o) in enumerate(zip(ev, od))) % F.p
+    alt = sum((e - o) * r ** d for d, (e, o) in enumerate(zip(ev, od))) % F.p
+    got = to_ints(yh, r)
+    assert got == [tot, alt]
+    back = f.fft_inverse(y)
+    del y
+    assert torch.equal(back, dx)
