@@ -18,7 +18,7 @@ import pytest
 
 import gfp_inputs as gi
 from oracle import transform as T
-from oracle.field import GFPField, P8, P16
+from oracle.field import GFPField, P8, P16, P32, P64
 from tests.helpers import canonical_mask, to_ints
 
 pytestmark = pytest.mark.gpu
@@ -38,7 +38,7 @@ def torch_mod():
 def fields(torch_mod):
     from paper_1811_01490_amd import Field
 
-    return {8: Field(**P8), 16: Field(**P16)}
+    return {8: Field(**P8), 16: Field(**P16), 32: Field(**P32), 64: Field(**P64)}
 
 
 @pytest.fixture(scope="module")
@@ -145,6 +145,30 @@ def test_arrivals_during_a_batch_use_another_slot(torch_mod, fields, sleep_cycle
     _check_alone(f, da, db, c)
     for x, cc in zip(small, cs):
         _check_alone(f, x[2], x[3], cc)
+
+
+def test_wide_primes_in_one_stream(torch_mod, fields):
+    """Requests over the k = 8, 16, 32 and 64 primes interleaved in one
+    request stream: every result equals the same product alone."""
+    import torch
+
+    from paper_1811_01490_amd import Server
+
+    g = gi.rng(SEED, 7)
+    plist = [P8, P16, P32, P64]
+    reqs = []
+    for i in range(24):
+        params = plist[i % 4]
+        la, lb = int(2 ** g.uniform(0, 10)), int(2 ** g.uniform(0, 10))
+        a, b, da, db = _operands(params, la, lb, 700 + i)
+        reqs.append((params, da, db, _out(torch, params["k"], la + lb - 1)))
+    torch.cuda.synchronize()
+    with Server(workspace_bytes=2 << 30, slots=2, max_batch=16) as srv:
+        tickets = [srv.submit(fields[p["k"]], da, db, c) for p, da, db, c in reqs]
+        res = [srv.wait(t) for t in tickets]
+    assert all(r["status"] == 0 for r in res)
+    for params, da, db, c in reqs:
+        _check_alone(fields[params["k"]], da, db, c)
 
 
 def test_budget_limits_batch_and_rejects_oversize(torch_mod, fields, sleep_cycles):
