@@ -127,7 +127,8 @@ int gfp_fft_inverse(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t 
  * twiddles), transformed by DFT_K at r (r^-1) and written to
  * y[(j - a) K + a + t Ns] (section 1.1, eq. CTCT; section 4.1).  The radix-R
  * stage does the same with K replaced by R, Ns = 1 and DFT_R at r^(K/R).
- * Stage 0 of the inverse also multiplies by 1/n.  Running s = 0..S-1 with
+ * Stage 0 of the inverse also multiplies by 1/n; for k >= 32 and n > K,
+ * stage 1 does instead, through twiddle tables scaled by 1/n.  Running s = 0..S-1 with
  * y of one pass as x of the next is the full transform.  Outputs of
  * s < S-1 are not canonical: every digit is in [0, 2^64) and the value is
  * congruent mod p (the next pass accepts this); s = S-1 writes the

@@ -33,7 +33,17 @@ struct DevTables {
   uint32_t* fwd2 = nullptr;  // n/K entries: w^(K j) (n >= K^2)
   uint32_t* inv2 = nullptr;  // n/K entries: w^-(K j)
   uint32_t* ninv = nullptr;  // one entry: 1/n
+  // k >= 32 and n > K: inv and inv2 times 1/n, so that the inverse's second
+  // launch (a radix-K pass with Ns > 1: every slot is multiplied by a table
+  // entry) also applies 1/n, instead of an extra product per element in the
+  // first launch
+  uint32_t* inv_s = nullptr;
+  uint32_t* inv2_s = nullptr;
 };
+
+// Whether the inverse of size 2^log2n takes its 1/n from the scaled tables
+// (see DevTables) rather than in its first launch.
+bool scale_in_tables(const gfp_field* f, int log2n);
 
 struct DevConsts {
   uint32_t* one = nullptr;  // one entry: 1
@@ -76,6 +86,10 @@ namespace {
 int log2_exact(uint64_t n) {
   if (n == 0 || (n & (n - 1))) return -1;
   return __builtin_ctzll(n);
+}
+
+bool scale_in_tables(const gfp_field* f, int log2n) {
+  return f->k >= 32 && log2n > log2_exact(2ull * f->k);
 }
 
 // Miller-Rabin to a fixed base set (host-side sanity check of p).
@@ -150,7 +164,10 @@ Big root_mont(const gfp_field* f, uint64_t n, bool inverse) {
 }
 
 // host table of w^(sign j), j < cnt, in entry layout
-void build_table(const gfp_field* f, const Big& wm, uint64_t cnt, std::vector<uint32_t>& out) {
+// Entries scale w^j, j < cnt (wm = w and sm = scale in Montgomery form;
+// sm == nullptr: scale 1).
+void build_table(const gfp_field* f, const Big& wm, uint64_t cnt, std::vector<uint32_t>& out,
+                 const Big* sm = nullptr) {
   const int words = gfpk::tw_words((int)f->k);
   out.assign(cnt * words, 0);
   unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -163,6 +180,7 @@ void build_table(const gfp_field* f, const Big& wm, uint64_t cnt, std::vector<ui
     th.emplace_back([&, lo, hi]() {
       const Mont& M = *f->mont;
       Big acc = M.pow(wm, Big(lo));
+      if (sm) acc = M.mmul(acc, *sm);
       std::vector<uint64_t> dg(f->k);
       for (uint64_t j = lo; j < hi; ++j) {
         to_digits(f, M.from(acc), dg.data());
@@ -223,6 +241,8 @@ int get_tables(gfp_field* f, uint64_t n, const DevTables** out) {
   const uint64_t cnt = n / (2ull * f->k);
   DevTables t;
   std::vector<uint32_t> host;
+  const Mont& M = *f->mont;
+  const Big ninv_m = M.pow(M.to(Big(n)), gfp::sub(f->p, Big(2)));  // 1/n, Montgomery form
   build_table(f, root_mont(f, n, false), cnt, host);
   int rc = upload(host, &t.fwd);
   if (rc == GFP_OK) {
@@ -238,10 +258,17 @@ int get_tables(gfp_field* f, uint64_t n, const DevTables** out) {
       rc = upload(host, &t.inv2);
     }
   }
+  if (rc == GFP_OK && scale_in_tables(f, log2_exact(n))) {
+    build_table(f, root_mont(f, n, true), cnt, host, &ninv_m);
+    rc = upload(host, &t.inv_s);
+    if (rc == GFP_OK && n >= 4ull * f->k * f->k) {
+      build_table(f, root_mont(f, n / (2ull * f->k), true), cnt, host, &ninv_m);
+      rc = upload(host, &t.inv2_s);
+    }
+  }
   if (rc == GFP_OK) {
     // 1/n = n^(p-2)
-    const Mont& M = *f->mont;
-    Big ninv = M.from(M.pow(M.to(Big(n)), gfp::sub(f->p, Big(2))));
+    Big ninv = M.from(ninv_m);
     std::vector<uint64_t> dg(f->k);
     to_digits(f, ninv, dg.data());
     host.assign(gfpk::tw_words((int)f->k), 0);
@@ -254,6 +281,8 @@ int get_tables(gfp_field* f, uint64_t n, const DevTables** out) {
     (void)hipFree(t.fwd2);
     (void)hipFree(t.inv2);
     (void)hipFree(t.ninv);
+    (void)hipFree(t.inv_s);
+    (void)hipFree(t.inv2_s);
     return rc;
   }
   std::lock_guard<std::mutex> g(f->mu);
@@ -264,6 +293,8 @@ int get_tables(gfp_field* f, uint64_t n, const DevTables** out) {
     (void)hipFree(t.fwd2);
     (void)hipFree(t.inv2);
     (void)hipFree(t.ninv);
+    (void)hipFree(t.inv_s);
+    (void)hipFree(t.inv2_s);
   }
   *out = &ins.first->second;
   return GFP_OK;
@@ -534,7 +565,8 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
   codes.insert(codes.end(), plan.begin(), plan.end());
   const int nl = (int)codes.size();
   if (nl == 1 && X.p == Y.p) return GFP_EINVAL;  // a single launch cannot run in place
-  if (X2 && (!inverse || X.sd != 1)) return GFP_EINVAL;
+  const bool scale_tab = inverse && scale_in_tables(f, log2n);
+  if (X2 && (!inverse || X.sd != 1 || scale_tab)) return GFP_EINVAL;
   VecView src = X;
   int s = 0;  // radix-K passes done
   for (int i = 0; i < nl; ++i) {
@@ -557,11 +589,15 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
     p.log2n = log2n;
     p.ngroups = n >> lk;
     p.inverse = inverse;
-    p.scale = inverse && i == 0;
+    p.scale = inverse && i == 0 && !scale_tab;
     p.in2 = (i == 0) ? X2 : nullptr;
     p.tw = p.scale ? t->ninv : (inverse ? t->inv : t->fwd);
     p.tw1 = inverse ? t->inv : t->fwd;
     p.tw2 = inverse ? t->inv2 : t->fwd2;
+    if (scale_tab && i == 1) {  // 1/n rides on this launch's twiddle tables
+      p.tw = t->inv_s;
+      p.tw2 = t->inv2_s;
+    }
     p.last = (i == nl - 1) && canonical;
     p.nvec = nvec;
     p.vin = src.vs;
@@ -677,7 +713,7 @@ int polymul_chunk(gfp_field* f, int log2n, int e, const PolyReq* r, uint64_t C, 
   const VecView em{A, k, 1, vw}, fm{F, k, 1, vw};
   if (rc == GFP_OK) rc = run_transform(f, log2n, e, false, em, fm, 2 * C, false, W1, W2, st);
   if (rc != GFP_OK) return rc;
-  if (C * n >= kFuseProductElems) {
+  if (C * n >= kFuseProductElems && !scale_in_tables(f, log2n)) {
     // inverse of the pointwise products F[i] F[C + i], formed in its first
     // launch, into A (free once the forward transforms are done)
     rc = run_transform(f, log2n, e, true, fm, em, C, true, W1, W2, st, F + C * vw);
@@ -857,6 +893,8 @@ int gfp_field_destroy(gfp_field* f) {
     (void)hipFree(kv.second.fwd2);
     (void)hipFree(kv.second.inv2);
     (void)hipFree(kv.second.ninv);
+    (void)hipFree(kv.second.inv_s);
+    (void)hipFree(kv.second.inv2_s);
   }
   for (auto& kv : f->consts) {
     (void)hipSetDevice(kv.first);
@@ -941,10 +979,15 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   p.radix_log2 = radix_r ? lr : 0;
   p.ngroups = n >> lk;
   p.inverse = inverse != 0;
-  p.scale = p.inverse && s == 0;
+  const bool scale_tab = p.inverse && scale_in_tables(f, log2n);
+  p.scale = p.inverse && s == 0 && !scale_tab;
   p.tw = p.scale ? t->ninv : (p.inverse ? t->inv : t->fwd);
   p.tw1 = p.inverse ? t->inv : t->fwd;
   p.tw2 = p.inverse ? t->inv2 : t->fwd2;
+  if (scale_tab && s == 1) {
+    p.tw = t->inv_s;
+    p.tw2 = t->inv2_s;
+  }
   p.span = span;
   p.wide = wide;
   p.last = (s + span - 1 == total - 1);

@@ -64,7 +64,8 @@ def test_batched_mixed_sizes(torch_mod, params):
 # (prime, operand sizes, count): every chunk has 2^18 elements.  k = 8: the
 # inverse's first launch is one pass (4096 = 16^3, plan 12), a fused pair
 # (256 = 16^2, plan 2) or the radix-8 pass (2048 = 8 16^2); k = 16: the
-# radix-2 pass (4096 = 2 32^2); k = 32: the radix-64 pass (4096 = 64^2).
+# radix-2 pass (4096 = 2 32^2).  k = 32, 64: the inverse takes 1/n from its
+# second launch's tables, so the product stays a launch of its own.
 FUSED = [(P8, (2048, 2048), 64), (P8, (100, 100), 1024), (P8, (1000, 1000), 128), (P16, (2048, 2048), 64),
          (P32, (2048, 2048), 64), (P64, (2048, 2048), 64)]
 
