@@ -64,13 +64,15 @@ def test_batched_mixed_sizes(torch_mod, params):
 # (prime, operand sizes, count): every chunk has 2^18 elements.  k = 8: the
 # inverse's first launch is one pass (4096 = 16^3, plan 12), a fused pair
 # (256 = 16^2, plan 2) or the radix-8 pass (2048 = 8 16^2); k = 16: the
-# radix-2 pass (4096 = 2 32^2).  k = 32, 64: the inverse takes 1/n from its
-# second launch's tables, so the product stays a launch of its own.
+# radix-2 pass (4096 = 2 32^2).  k = 32, 64: with more than one launch the
+# inverse takes 1/n from its second launch's tables and the product stays a
+# launch of its own (4096); a transform of size K is one fused launch.
 FUSED = [(P8, (2048, 2048), 64), (P8, (100, 100), 1024), (P8, (1000, 1000), 128), (P16, (2048, 2048), 64),
-         (P32, (2048, 2048), 64), (P64, (2048, 2048), 64)]
+         (P32, (2048, 2048), 64), (P64, (2048, 2048), 64), (P32, (32, 33), 4096), (P64, (64, 65), 2048)]
 
 
-@pytest.mark.parametrize("params,size,count", FUSED, ids=["k8-one", "k8-pair", "k8-radix8", "k16", "k32", "k64"])
+@pytest.mark.parametrize("params,size,count", FUSED,
+                         ids=["k8-one", "k8-pair", "k8-radix8", "k16", "k32", "k64", "k32-one", "k64-one"])
 def test_fused_pointwise_product(torch_mod, params, size, count):
     """Products in a chunk of 2^18 elements take the pointwise product inside
     the inverse transform's first launch; one product alone takes the separate
