@@ -3,9 +3,9 @@
 // of two, so an integer product is a polynomial product followed by the
 // evaluation, i.e. carries).
 //
-// An integer of n 64-bit words is cut into chunks of W bits (r = 2^W + 2^U,
-// so a chunk is below r and is one radix-r digit: no radix conversion on the
-// way in).  The product's coefficients C_m = sum a_i b_(m-i) < L 2^(2W) are
+// An integer of n 64-bit words is cut into chunks of CW bits, CW = W for
+// r = 2^W + 2^U and CW = W - 1 for r = 2^W - 2^U, so a chunk is below r and
+// is one radix-r digit: no radix conversion on the way in.  The product's coefficients C_m = sum a_i b_(m-i) < L 2^(2W) are
 // far below p, so their canonical digits give C_m = d0 + d1 r + d2 r^2 + d3 r^3
 // exactly.  Output word w sums the 64-bit slices of every C_m 2^(W m) that
 // overlaps it into lo_w + 2^64 hi_w; the carries between words are resolved
@@ -18,7 +18,8 @@ namespace gfpk {
 
 constexpr int kScanThreads = 1024;  // words per scan block
 
-// coefficient i of a = bits [W i, W i + W) (digit 0); digits 1..k-1 are 0
+// coefficient i of a = bits [W i, W i + W) (digit 0; W here is the chunk
+// width); digits 1..k-1 are 0
 __global__ __launch_bounds__(256) void k_bigint_split(const uint64_t* __restrict__ a, uint64_t na,
                                                       uint64_t* __restrict__ A, uint64_t la, uint32_t k, uint32_t W) {
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -36,36 +37,50 @@ __global__ __launch_bounds__(256) void k_bigint_split(const uint64_t* __restrict
   A[i] = v & ((1ull << W) - 1);
 }
 
-// v (5 words) = v r + d, r = 2^W + 2^U; the caller keeps v below 2^320
-__device__ __forceinline__ void mul_r_add(uint64_t (&v)[5], uint64_t d, uint32_t W, uint32_t U) {
+// v (5 words) = v r + d, r = 2^W + 2^U (U > 0) or 2^W - 2^-U (U < 0); the
+// caller keeps v r below 2^320
+__device__ __forceinline__ void mul_r_add(uint64_t (&v)[5], uint64_t d, uint32_t W, int U) {
+  const uint32_t ua = (uint32_t)(U < 0 ? -U : U);
   uint64_t hw[5], hu[5];
   hw[0] = v[0] << W;
-  hu[0] = v[0] << U;
+  hu[0] = v[0] << ua;
 #pragma unroll
   for (int i = 1; i < 5; ++i) {
     hw[i] = (v[i] << W) | (v[i - 1] >> (64 - W));
-    hu[i] = (v[i] << U) | (v[i - 1] >> (64 - U));
+    hu[i] = (v[i] << ua) | (v[i - 1] >> (64 - ua));
   }
-  unsigned __int128 c = (unsigned __int128)d;
+  if (U > 0) {
+    unsigned __int128 c = (unsigned __int128)d;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    c += (unsigned __int128)hw[i] + hu[i];
-    v[i] = (uint64_t)c;
-    c >>= 64;
+    for (int i = 0; i < 5; ++i) {
+      c += (unsigned __int128)hw[i] + hu[i];
+      v[i] = (uint64_t)c;
+      c >>= 64;
+    }
+  } else {
+    // v 2^W - v 2^ua + d >= 0: add d, subtract with borrow
+    __int128 c = (__int128)d;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      c += (__int128)hw[i] - (__int128)hu[i];
+      v[i] = (uint64_t)c;
+      c >>= 64;  // arithmetic: -1, 0 or +1
+    }
   }
 }
 
 // word w of sum_m C_m 2^(W m) as lo_w + 2^64 hi_w (hi_w small)
-__global__ __launch_bounds__(256) void k_bigint_combine(const uint64_t* __restrict__ C, uint64_t lc, uint32_t W,
-                                                        uint32_t U, uint64_t nw, uint64_t* __restrict__ lo,
+// (CW: chunk width; W, U: the radix)
+__global__ __launch_bounds__(256) void k_bigint_combine(const uint64_t* __restrict__ C, uint64_t lc, uint32_t CW,
+                                                        uint32_t W, int U, uint64_t nw, uint64_t* __restrict__ lo,
                                                         uint64_t* __restrict__ hi) {
   const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nw) return;
-  // C_m 2^(W m) spans bits [W m, W m + 320): it meets word w when
-  // W m < 64 w + 64 and W m + 320 > 64 w
-  const uint64_t top = (64 * w + 63) / W;
+  // C_m 2^(CW m) spans bits [CW m, CW m + 320): it meets word w when
+  // CW m < 64 w + 64 and CW m + 320 > 64 w
+  const uint64_t top = (64 * w + 63) / CW;
   const uint64_t m_hi = top < lc - 1 ? top : lc - 1;
-  const uint64_t m_lo = (64 * w >= 320) ? (64 * w - 320) / W : 0;
+  const uint64_t m_lo = (64 * w >= 320) ? (64 * w - 320) / CW : 0;
   unsigned __int128 acc = 0;
   for (uint64_t m = m_lo; m <= m_hi; ++m) {
     uint64_t v[5] = {0, 0, 0, 0, 0};
@@ -73,7 +88,7 @@ __global__ __launch_bounds__(256) void k_bigint_combine(const uint64_t* __restri
     mul_r_add(v, C[2 * lc + m], W, U);
     mul_r_add(v, C[1 * lc + m], W, U);
     mul_r_add(v, C[0 * lc + m], W, U);
-    const int64_t s = (int64_t)((uint64_t)W * m) - (int64_t)(64 * w);  // bit 0 of C_m relative to word w
+    const int64_t s = (int64_t)((uint64_t)CW * m) - (int64_t)(64 * w);  // bit 0 of C_m relative to word w
     uint64_t slice;
     if (s >= 64 || s <= -320) {
       slice = 0;
@@ -212,10 +227,10 @@ hipError_t launch_bigint_split(const uint64_t* a, uint64_t na, uint64_t* A, uint
   return hipGetLastError();
 }
 
-hipError_t launch_bigint_combine(const uint64_t* C, uint64_t lc, int W, int U, uint64_t nw, uint64_t* lo,
+hipError_t launch_bigint_combine(const uint64_t* C, uint64_t lc, int CW, int W, int U, uint64_t nw, uint64_t* lo,
                                  uint64_t* hi, hipStream_t st) {
-  hipLaunchKernelGGL(k_bigint_combine, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, C, lc, (uint32_t)W,
-                     (uint32_t)U, nw, lo, hi);
+  hipLaunchKernelGGL(k_bigint_combine, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, C, lc, (uint32_t)CW,
+                     (uint32_t)W, U, nw, lo, hi);
   return hipGetLastError();
 }
 

@@ -1048,6 +1048,7 @@ int gfp_polymul(const gfp_field* cf, const uint64_t* a, uint64_t la, uint64_t ld
 namespace {
 
 struct BigintPlan {
+  uint64_t cw;  // chunk width: W for r = 2^W + 2^U, W - 1 for r = 2^W - 2^U
   uint64_t la, lb, lc, nw, N;
   int log2n, e;
   // workspace offsets in words
@@ -1057,10 +1058,11 @@ struct BigintPlan {
 
 int plan_bigint(const gfp_field* f, uint64_t na, uint64_t nb, BigintPlan& p) {
   if (!f || na == 0 || nb == 0) return GFP_EINVAL;
-  // chunks of W bits are digits and evaluate with r = 2^W + 2^U: not for
-  // radices 2^W - 2^U, where a W-bit chunk can exceed r
-  if (!f->gpu_shape || f->u < 0) return GFP_EUNSUPPORTED;
-  const uint64_t W = (uint64_t)f->w;
+  if (!f->gpu_shape) return GFP_EUNSUPPORTED;
+  // chunks must be digits (below r): W bits for r = 2^W + 2^U, W - 1 bits
+  // for r = 2^W - 2^U
+  const uint64_t W = (uint64_t)(f->u < 0 ? f->w - 1 : f->w);
+  p.cw = W;
   p.la = (64 * na + W - 1) / W;
   p.lb = (64 * nb + W - 1) / W;
   p.lc = p.la + p.lb - 1;
@@ -1112,8 +1114,8 @@ int gfp_bigint_mul(const gfp_field* cf, const uint64_t* a, uint64_t na, const ui
   uint64_t* A = w + p.oA;
   uint64_t* B = w + p.oB;
   uint64_t* C = w + p.oC;
-  hipError_t he = gfpk::launch_bigint_split(a, na, A, p.la, k, f->w, st);
-  if (he == hipSuccess) he = gfpk::launch_bigint_split(b, nb, B, p.lb, k, f->w, st);
+  hipError_t he = gfpk::launch_bigint_split(a, na, A, p.la, k, (int)p.cw, st);
+  if (he == hipSuccess) he = gfpk::launch_bigint_split(b, nb, B, p.lb, k, (int)p.cw, st);
   if (he != hipSuccess) return hip_status(he);
   PolyReq q{A, p.la, p.la, B, p.lb, p.lb, C, p.lc};
   rc = polymul_chunk(f, p.log2n, p.e, &q, 1, w + p.oPoly, st);
@@ -1121,7 +1123,7 @@ int gfp_bigint_mul(const gfp_field* cf, const uint64_t* a, uint64_t na, const ui
   uint8_t* flags = (uint8_t*)(w + p.oBytes);
   uint8_t* agg = flags + p.nw;
   uint8_t* cin = agg + gfpk::bigint_scan_blocks(p.nw);
-  he = gfpk::launch_bigint_combine(C, p.lc, f->w, f->u, p.nw, w + p.oLo, w + p.oHi, st);
+  he = gfpk::launch_bigint_combine(C, p.lc, (int)p.cw, f->w, f->u, p.nw, w + p.oLo, w + p.oHi, st);
   if (he == hipSuccess) he = gfpk::launch_bigint_carry(w + p.oLo, w + p.oHi, p.nw, c, flags, agg, cin, st);
   return hip_status(he);
 }

@@ -197,7 +197,7 @@ def test_k32_field_host():
 def test_k64_field_host():
     """The k = 64 prime of Table 1 (r = 2^63 - 2^40, K = 128): roots as the
     oracle's, sizes from K = 128 on, one radix-128 pass per launch; integer
-    products are not offered for a radix 2^W - 2^U."""
+    products cut 62-bit chunks (a 63-bit chunk could exceed r)."""
     L = _lib()
     f = gfp.Field(**P64)
     F = GFPField(**P64)
@@ -208,7 +208,12 @@ def test_k64_field_host():
     assert f.polymul_size(1, 1) == 128 and f.polymul_size(2048, 2048) == 4096
     assert f.plan(2 ** 14) == "11" and f.plan(2 ** 13) == "1" and f.plan(128) == "1"
     b = ctypes.c_uint64()
-    assert L.gfp_bigint_mul_workspace_size(f.handle, 10, 10, ctypes.byref(b)) == gfp.GFP_EUNSUPPORTED
+    assert L.gfp_bigint_mul_workspace_size(f.handle, 10, 10, ctypes.byref(b)) == gfp.GFP_OK
+    # 62-bit chunks: 10 words = 11 coefficients each, 21 product coefficients,
+    # transform size 128 (K); workspace at least the polynomial product's
+    w = ctypes.c_uint64()
+    assert L.gfp_polymul_workspace_size(f.handle, 11, 11, ctypes.byref(w)) == gfp.GFP_OK
+    assert b.value >= w.value
 
 
 def test_bigint_sizes():

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = {"k8": (8, 2 ** 63 + 2 ** 34), "k16": (16, 2 ** 62 + 2 ** 36),
           "k8t": (8, 2 ** 59 + 2 ** 16), "k16t": (16, 2 ** 58 + 2 ** 10), "k32": (32, 2 ** 62 + 2 ** 56),
-          "k32t": (32, 2 ** 56 + 2 ** 21)}
+          "k32t": (32, 2 ** 56 + 2 ** 21), "k64": (64, 2 ** 63 - 2 ** 40)}
 
 
 @pytest.fixture(scope="module")
