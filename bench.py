@@ -348,11 +348,14 @@ def bigint_leg(torch, dev, words: int, reps: int):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    n = f.polymul_size((64 * words + 62) // 63, (64 * words + 62) // 63)
+    # the library's coefficient width: the product's coefficients must stay below p
+    bits = min(448, (K_DIG * 63 - 2 - (64 * words - 1).bit_length()) // 2)
+    la = (64 * words + bits - 1) // bits
+    n = f.polymul_size(la, la)
     f.close()
-    return {"workload": "product of two uniform random %d-bit integers (seed 1811014905), 63-bit coefficients over "
-                        "p = (2^63+2^34)^8+1" % (64 * words),
-            "words": words, "transform_size": n, "ms": round(ms, 4),
+    return {"workload": "product of two uniform random %d-bit integers (seed 1811014905), %d-bit coefficients over "
+                        "p = (2^63+2^34)^8+1" % (64 * words, bits),
+            "words": words, "coefficient_bits": bits, "transform_size": n, "ms": round(ms, 4),
             "input_bits_per_s": round(2 * 64 * words / (ms * 1e-3), 1)}
 
 

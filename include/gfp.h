@@ -211,16 +211,15 @@ int gfp_elementwise(const gfp_field* f, int op, const uint64_t* x, uint64_t ld_x
  * the application the paper starts from (section 1) -- an integer is a
  * polynomial evaluated at a power of two, so the product is a polynomial
  * product over Z/pZ (section 3.3, Alg. Fast Convolution) followed by the
- * evaluation.  The integers are cut into W-bit coefficients (r = 2^W + 2^U;
- * W - 1 bits for r = 2^W - 2^U, so each is one radix-r digit); the
- * coefficients of the product stay below min(la, lb) 2^(2W) < p, so their
- * canonical digits give them exactly; they
+ * evaluation.  The integers are cut into b-bit coefficients, b as large as
+ * the field allows (the product's coefficients, below min(la, lb) 2^(2b),
+ * must stay below p: b = min(448, (k W' - 2 - ceil(log2(64 min(na, nb)))) / 2)
+ * with r > 2^W'), each converted to k radix-r digits on the device; the
+ * canonical digits of the product's coefficients give them exactly; they
  * are converted back to binary, added at their bit offsets and the carries
- * resolved by a carry-lookahead scan, all on the device.  One coefficient
- * carries W of the k W bits an element holds: a denser packing would need a
- * radix conversion of every coefficient.  Sizes: la + lb - 1 coefficients
- * (la = ceil(64 na / W)) within the transform limit.  Workspace as for the
- * transforms (gfp_bigint_mul_workspace_size bytes, or NULL). */
+ * resolved by a carry-lookahead scan, all on the device.  Sizes:
+ * la + lb - 1 coefficients (la = ceil(64 na / b)) within the transform limit.
+ * Workspace: gfp_bigint_mul_workspace_size bytes, or NULL. */
 int gfp_bigint_mul_workspace_size(const gfp_field* f, uint64_t na, uint64_t nb, uint64_t* bytes);
 int gfp_bigint_mul(const gfp_field* f, const uint64_t* a, uint64_t na, const uint64_t* b, uint64_t nb, uint64_t* c,
                    void* workspace, uint64_t ws_bytes, void* stream);

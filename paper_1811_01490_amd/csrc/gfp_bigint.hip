@@ -3,101 +3,163 @@
 // of two, so an integer product is a polynomial product followed by the
 // evaluation, i.e. carries).
 //
-// An integer of n 64-bit words is cut into chunks of CW bits, CW = W for
-// r = 2^W + 2^U and CW = W - 1 for r = 2^W - 2^U, so a chunk is below r and
-// is one radix-r digit: no radix conversion on the way in.  The product's coefficients C_m = sum a_i b_(m-i) < L 2^(2W) are
-// far below p, so their canonical digits give C_m = d0 + d1 r + d2 r^2 + d3 r^3
-// exactly.  Output word w sums the 64-bit slices of every C_m 2^(W m) that
-// overlaps it into lo_w + 2^64 hi_w; the carries between words are resolved
-// by a carry-lookahead scan: word w holds c'_w = lo_w + hi_(w-1) mod 2^64,
-// generates a carry when that sum overflowed and propagates one when
-// c'_w = 2^64 - 1.
+// An integer of n 64-bit words is cut into chunks of b bits, b as large as
+// the field allows: the product's coefficients C_m < min(la, lb) 2^(2b) must
+// stay below p (about 2^(k W)), so b is about (k W - log2 min(la, lb)) / 2,
+// at most 448.  Each chunk is converted to k radix-r digits by division
+// (r = 2^U' d with d = 2^D +- 1).  The canonical digits of the product's
+// coefficients give each C_m exactly; it is evaluated back to binary
+// (Horner with r: shifts and adds), and output word w sums the 64-bit slices
+// of every C_m 2^(b m) that overlaps it into lo_w + 2^64 hi_w; the carries
+// between words are resolved by a carry-lookahead scan: word w holds
+// c'_w = lo_w + hi_(w-1) mod 2^64, generates a carry when that sum overflowed
+// and propagates one when c'_w = 2^64 - 1.
+#include "gfp_device.hpp"
 #include "gfp_internal.hpp"
 
 namespace gfpk {
 
 constexpr int kScanThreads = 1024;  // words per scan block
 
-// coefficient i of a = bits [W i, W i + W) (digit 0; W here is the chunk
-// width); digits 1..k-1 are 0
+constexpr int kChunkWords = 7;  // chunk bits b <= 448
+constexpr int kEvalWords = 16;  // product coefficients < 2^(2b + 64) <= 2^960
+
+// x := x / r, returning x mod r, for r = 2^ua d (ua < 64, d < 2^49): the low
+// ua bits are the low part of the remainder, and x >> ua is divided by d by
+// long division in 15-bit pieces from the top (a remainder below 2^49 times
+// 2^15 stays within 64 bits).
+__device__ __forceinline__ uint64_t divmod_r(uint64_t (&x)[kChunkWords], uint32_t ua, uint64_t d) {
+  const uint64_t lo = x[0] & ((1ull << ua) - 1);
+  uint64_t y[kChunkWords];
+  static_for<kChunkWords>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    y[j] = (x[j] >> ua) | ((j + 1 < kChunkWords) ? (x[j + 1 < kChunkWords ? j + 1 : j] << (64 - ua)) : 0ull);
+    x[j] = 0;
+  });
+  constexpr int P = (64 * kChunkWords + 14) / 15;
+  uint64_t rem = 0;
+  static_for<P>([&](auto Q) {
+    constexpr int pc = P - 1 - decltype(Q)::value;  // piece index, from the top
+    constexpr int bit = 15 * pc, w0 = bit / 64, sh = bit % 64;
+    uint64_t piece = y[w0] >> sh;
+    if constexpr (sh > 64 - 15 && w0 + 1 < kChunkWords) piece |= y[w0 + 1] << (64 - sh);
+    piece &= 0x7FFF;
+    const uint64_t cur = (rem << 15) | piece;
+    const uint64_t qd = cur / d;
+    rem = cur - qd * d;
+    x[w0] |= qd << sh;
+    if constexpr (sh > 64 - 15 && w0 + 1 < kChunkWords) x[w0 + 1] |= qd >> (64 - sh);
+  });
+  return lo | (rem << ua);
+}
+
+// coefficient i of a = bits [b i, b i + b), converted to k radix-r digits
+// (digit-major: A[d la + i]); the chunk is below 2^b < r^k
 __global__ __launch_bounds__(256) void k_bigint_split(const uint64_t* __restrict__ a, uint64_t na,
-                                                      uint64_t* __restrict__ A, uint64_t la, uint32_t k, uint32_t W) {
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= la * k) return;
-  const uint64_t d = t / la, i = t - d * la;
-  if (d != 0) {
-    A[t] = 0;
-    return;
-  }
-  const uint64_t bit = (uint64_t)W * i;
+                                                      uint64_t* __restrict__ A, uint64_t la, uint32_t k, uint32_t b,
+                                                      uint32_t ua, uint64_t d) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= la) return;
+  const uint64_t bit = (uint64_t)b * i;
   const uint64_t w = bit >> 6;
   const uint32_t s = (uint32_t)(bit & 63);
-  uint64_t v = a[w] >> s;
-  if (s != 0 && w + 1 < na) v |= a[w + 1] << (64 - s);
-  A[i] = v & ((1ull << W) - 1);
+  const uint32_t nwb = (b + 63) / 64;
+  uint64_t x[kChunkWords];
+  static_for<kChunkWords>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    uint64_t v = 0;
+    if ((uint32_t)j < nwb) {
+      v = (w + j < na) ? a[w + j] >> s : 0ull;
+      if (s != 0 && w + j + 1 < na) v |= a[w + j + 1] << (64 - s);
+      const uint32_t top = b - 64 * j;  // bits of the chunk in this word
+      if (top < 64) v &= (1ull << top) - 1;
+    }
+    x[j] = v;
+  });
+  for (uint32_t dg = 0; dg < k; ++dg) {
+    uint64_t nz = 0;
+    static_for<kChunkWords>([&](auto J) { nz |= x[decltype(J)::value]; });
+    A[(uint64_t)dg * la + i] = nz ? divmod_r(x, ua, d) : 0ull;
+  }
 }
 
-// v (5 words) = v r + d, r = 2^W + 2^U (U > 0) or 2^W - 2^-U (U < 0); the
-// caller keeps v r below 2^320
-__device__ __forceinline__ void mul_r_add(uint64_t (&v)[5], uint64_t d, uint32_t W, int U) {
+// v (kEvalWords words) = v r + dg, r = 2^W + 2^U (U > 0) or 2^W - 2^-U
+// (U < 0); the caller keeps v r below 2^(64 kEvalWords)
+__device__ __forceinline__ void mul_r_add(uint64_t (&v)[kEvalWords], uint64_t dg, uint32_t W, int U) {
   const uint32_t ua = (uint32_t)(U < 0 ? -U : U);
-  uint64_t hw[5], hu[5];
-  hw[0] = v[0] << W;
-  hu[0] = v[0] << ua;
-#pragma unroll
-  for (int i = 1; i < 5; ++i) {
-    hw[i] = (v[i] << W) | (v[i - 1] >> (64 - W));
-    hu[i] = (v[i] << ua) | (v[i - 1] >> (64 - ua));
-  }
   if (U > 0) {
-    unsigned __int128 c = (unsigned __int128)d;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      c += (unsigned __int128)hw[i] + hu[i];
-      v[i] = (uint64_t)c;
+    unsigned __int128 c = (unsigned __int128)dg;
+    uint64_t pw = 0, pu = 0;  // the word below, before this step
+    static_for<kEvalWords>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      const uint64_t cur = v[j];
+      const uint64_t hw = (cur << W) | (j ? pw >> (64 - W) : 0ull);
+      const uint64_t hu = (cur << ua) | (j ? pu >> (64 - ua) : 0ull);
+      pw = cur;
+      pu = cur;
+      c += (unsigned __int128)hw + hu;
+      v[j] = (uint64_t)c;
       c >>= 64;
-    }
+    });
   } else {
-    // v 2^W - v 2^ua + d >= 0: add d, subtract with borrow
-    __int128 c = (__int128)d;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      c += (__int128)hw[i] - (__int128)hu[i];
-      v[i] = (uint64_t)c;
+    // v 2^W - v 2^ua + dg >= 0: add dg, subtract with borrow
+    __int128 c = (__int128)dg;
+    uint64_t pw = 0;
+    static_for<kEvalWords>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      const uint64_t cur = v[j];
+      const uint64_t hw = (cur << W) | (j ? pw >> (64 - W) : 0ull);
+      const uint64_t hu = (cur << ua) | (j ? pw >> (64 - ua) : 0ull);
+      pw = cur;
+      c += (__int128)hw - (__int128)hu;
+      v[j] = (uint64_t)c;
       c >>= 64;  // arithmetic: -1, 0 or +1
-    }
+    });
   }
 }
 
-// word w of sum_m C_m 2^(W m) as lo_w + 2^64 hi_w (hi_w small)
-// (CW: chunk width; W, U: the radix)
-__global__ __launch_bounds__(256) void k_bigint_combine(const uint64_t* __restrict__ C, uint64_t lc, uint32_t CW,
-                                                        uint32_t W, int U, uint64_t nw, uint64_t* __restrict__ lo,
-                                                        uint64_t* __restrict__ hi) {
+// E[m] (kEvalWords words) = C_m as a binary integer, from its k canonical
+// digits (Horner from the top nonzero digit)
+__global__ __launch_bounds__(256) void k_bigint_eval(const uint64_t* __restrict__ C, uint64_t lc, uint32_t k,
+                                                     uint32_t W, int U, uint64_t* __restrict__ E) {
+  const uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= lc) return;
+  int top = (int)k - 1;
+  while (top > 0 && C[(uint64_t)top * lc + m] == 0) --top;
+  uint64_t v[kEvalWords];
+  static_for<kEvalWords>([&](auto J) { v[decltype(J)::value] = 0; });
+  for (int dg = top; dg >= 0; --dg) mul_r_add(v, C[(uint64_t)dg * lc + m], W, U);
+  static_for<kEvalWords>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    E[m * kEvalWords + j] = v[j];
+  });
+}
+
+// word w of sum_m C_m 2^(b m) as lo_w + 2^64 hi_w (hi_w small)
+__global__ __launch_bounds__(256) void k_bigint_gather(const uint64_t* __restrict__ E, uint64_t lc, uint32_t b,
+                                                       uint64_t nw, uint64_t* __restrict__ lo,
+                                                       uint64_t* __restrict__ hi) {
   const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nw) return;
-  // C_m 2^(CW m) spans bits [CW m, CW m + 320): it meets word w when
-  // CW m < 64 w + 64 and CW m + 320 > 64 w
-  const uint64_t top = (64 * w + 63) / CW;
+  // C_m 2^(b m) spans bits [b m, b m + 64 kEvalWords): it meets word w when
+  // b m < 64 w + 64 and b m + 64 kEvalWords > 64 w
+  const uint64_t span = 64ull * kEvalWords;
+  const uint64_t top = (64 * w + 63) / b;
   const uint64_t m_hi = top < lc - 1 ? top : lc - 1;
-  const uint64_t m_lo = (64 * w >= 320) ? (64 * w - 320) / CW : 0;
+  const uint64_t m_lo = (64 * w >= span) ? (64 * w - span) / b : 0;
   unsigned __int128 acc = 0;
   for (uint64_t m = m_lo; m <= m_hi; ++m) {
-    uint64_t v[5] = {0, 0, 0, 0, 0};
-    mul_r_add(v, C[3 * lc + m], W, U);
-    mul_r_add(v, C[2 * lc + m], W, U);
-    mul_r_add(v, C[1 * lc + m], W, U);
-    mul_r_add(v, C[0 * lc + m], W, U);
-    const int64_t s = (int64_t)((uint64_t)CW * m) - (int64_t)(64 * w);  // bit 0 of C_m relative to word w
+    const uint64_t* v = E + m * kEvalWords;
+    const int64_t s = (int64_t)((uint64_t)b * m) - (int64_t)(64 * w);  // bit 0 of C_m relative to word w
     uint64_t slice;
-    if (s >= 64 || s <= -320) {
+    if (s >= 64 || s <= -(int64_t)span) {
       slice = 0;
     } else if (s >= 0) {
       slice = v[0] << s;
     } else {
-      const uint32_t off = (uint32_t)(-s);
-      const uint32_t q = off >> 6, sh = off & 63;
-      const uint64_t x0 = v[q], x1 = (q + 1 < 5) ? v[q + 1] : 0;
+      const uint64_t off = (uint64_t)(-s);
+      const uint64_t q = off >> 6, sh = off & 63;
+      const uint64_t x0 = v[q], x1 = (q + 1 < kEvalWords) ? v[q + 1] : 0;
       slice = sh ? ((x0 >> sh) | (x1 << (64 - sh))) : x0;
     }
     acc += slice;
@@ -219,20 +281,28 @@ __global__ __launch_bounds__(kScanThreads) void k_carry_apply(uint64_t* __restri
   if (w < nw && ci) c[w] += 1;
 }
 
-hipError_t launch_bigint_split(const uint64_t* a, uint64_t na, uint64_t* A, uint64_t la, int k, int W,
-                               hipStream_t st) {
-  const uint64_t tot = la * (uint64_t)k;
-  hipLaunchKernelGGL(k_bigint_split, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a, na, A, la,
-                     (uint32_t)k, (uint32_t)W);
+hipError_t launch_bigint_split(const uint64_t* a, uint64_t na, uint64_t* A, uint64_t la, int k, int b, int ua,
+                               uint64_t d, hipStream_t st) {
+  if (b < 1 || b > 64 * kChunkWords || ua < 1 || ua > 63 || d >= (1ull << 49)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bigint_split, dim3((unsigned)((la + 255) / 256)), dim3(256), 0, st, a, na, A, la, (uint32_t)k,
+                     (uint32_t)b, (uint32_t)ua, d);
   return hipGetLastError();
 }
 
-hipError_t launch_bigint_combine(const uint64_t* C, uint64_t lc, int CW, int W, int U, uint64_t nw, uint64_t* lo,
-                                 uint64_t* hi, hipStream_t st) {
-  hipLaunchKernelGGL(k_bigint_combine, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, C, lc, (uint32_t)CW,
-                     (uint32_t)W, U, nw, lo, hi);
+hipError_t launch_bigint_combine(const uint64_t* C, uint64_t lc, int k, int b, int W, int U, uint64_t nw, uint64_t* E,
+                                 uint64_t* lo, uint64_t* hi, hipStream_t st) {
+  if (b < 1 || lc == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bigint_eval, dim3((unsigned)((lc + 255) / 256)), dim3(256), 0, st, C, lc, (uint32_t)k,
+                     (uint32_t)W, U, E);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bigint_gather, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, E, lc, (uint32_t)b, nw, lo,
+                     hi);
   return hipGetLastError();
 }
+
+uint64_t bigint_eval_words() { return kEvalWords; }
+int bigint_max_chunk_bits() { return 64 * kChunkWords; }
 
 uint64_t bigint_scan_blocks(uint64_t nw) { return (nw + kScanThreads - 1) / kScanThreads; }
 

@@ -1048,36 +1048,45 @@ int gfp_polymul(const gfp_field* cf, const uint64_t* a, uint64_t la, uint64_t ld
 namespace {
 
 struct BigintPlan {
-  uint64_t cw;  // chunk width: W for r = 2^W + 2^U, W - 1 for r = 2^W - 2^U
+  uint64_t b;   // chunk bits
+  int ua;       // r = 2^ua d, d = 2^(w - ua) +- 1
+  uint64_t d;
   uint64_t la, lb, lc, nw, N;
   int log2n, e;
   // workspace offsets in words
-  uint64_t oA, oB, oC, oPoly, oLo, oHi, oBytes;
+  uint64_t oA, oB, oC, oPoly, oE, oLo, oHi, oBytes;
   uint64_t words;
 };
 
 int plan_bigint(const gfp_field* f, uint64_t na, uint64_t nb, BigintPlan& p) {
   if (!f || na == 0 || nb == 0) return GFP_EINVAL;
   if (!f->gpu_shape) return GFP_EUNSUPPORTED;
-  // chunks must be digits (below r): W bits for r = 2^W + 2^U, W - 1 bits
-  // for r = 2^W - 2^U
-  const uint64_t W = (uint64_t)(f->u < 0 ? f->w - 1 : f->w);
-  p.cw = W;
-  p.la = (64 * na + W - 1) / W;
-  p.lb = (64 * nb + W - 1) / W;
+  // r = 2^ua d with d = 2^(w - ua) + 1 (u > 0) or 2^(w - ua) - 1 (u < 0)
+  p.ua = f->u < 0 ? -f->u : f->u;
+  p.d = (1ull << (f->w - p.ua)) + (f->u < 0 ? -1ll : 1ll);
+  // r > 2^we; the coefficients of the product, C_m < min(la, lb) 2^(2b) with
+  // min(la, lb) <= 64 min(na, nb), must stay below p > r^k > 2^(k we)
+  const uint64_t we = (uint64_t)(f->u < 0 ? f->w - 1 : f->w);
+  uint64_t lg = 1;
+  while ((1ull << lg) < 64 * std::min(na, nb)) ++lg;
+  const int64_t room = (int64_t)(f->k * we) - 2 - (int64_t)lg;
+  if (room < 2) return GFP_EUNSUPPORTED;
+  p.b = std::min<uint64_t>((uint64_t)(room / 2), (uint64_t)gfpk::bigint_max_chunk_bits());
+  if (2 * p.b + lg + 64 > 64 * gfpk::bigint_eval_words()) return GFP_EUNSUPPORTED;
+  p.la = (64 * na + p.b - 1) / p.b;
+  p.lb = (64 * nb + p.b - 1) / p.b;
   p.lc = p.la + p.lb - 1;
   p.nw = na + nb;
   int rc = gfp_polymul_size(f, p.la, p.lb, &p.N);
   if (rc != GFP_OK) return rc;
-  // C_m < min(la, lb) 2^(2W) must stay below r^4 (four digits are read) and p
-  if ((2 * W + 26) > 4 * W || (2 * W + 26) > (uint64_t)f->k * W) return GFP_EUNSUPPORTED;
   check_size(f, p.N, &p.log2n, &p.e);
   const uint64_t k = f->k;
   p.oA = 0;
   p.oB = p.oA + k * p.la;
   p.oC = p.oB + k * p.lb;
   p.oPoly = p.oC + k * p.lc;
-  p.oLo = p.oPoly + chunk_words(p.N, k, 1);
+  p.oE = p.oPoly + chunk_words(p.N, k, 1);
+  p.oLo = p.oE + p.lc * gfpk::bigint_eval_words();
   p.oHi = p.oLo + p.nw;
   p.oBytes = p.oHi + p.nw;  // flags (nw bytes), block aggregates and carries (2 bytes per block)
   const uint64_t nbk = gfpk::bigint_scan_blocks(p.nw);
@@ -1114,8 +1123,8 @@ int gfp_bigint_mul(const gfp_field* cf, const uint64_t* a, uint64_t na, const ui
   uint64_t* A = w + p.oA;
   uint64_t* B = w + p.oB;
   uint64_t* C = w + p.oC;
-  hipError_t he = gfpk::launch_bigint_split(a, na, A, p.la, k, (int)p.cw, st);
-  if (he == hipSuccess) he = gfpk::launch_bigint_split(b, nb, B, p.lb, k, (int)p.cw, st);
+  hipError_t he = gfpk::launch_bigint_split(a, na, A, p.la, k, (int)p.b, p.ua, p.d, st);
+  if (he == hipSuccess) he = gfpk::launch_bigint_split(b, nb, B, p.lb, k, (int)p.b, p.ua, p.d, st);
   if (he != hipSuccess) return hip_status(he);
   PolyReq q{A, p.la, p.la, B, p.lb, p.lb, C, p.lc};
   rc = polymul_chunk(f, p.log2n, p.e, &q, 1, w + p.oPoly, st);
@@ -1123,7 +1132,7 @@ int gfp_bigint_mul(const gfp_field* cf, const uint64_t* a, uint64_t na, const ui
   uint8_t* flags = (uint8_t*)(w + p.oBytes);
   uint8_t* agg = flags + p.nw;
   uint8_t* cin = agg + gfpk::bigint_scan_blocks(p.nw);
-  he = gfpk::launch_bigint_combine(C, p.lc, (int)p.cw, f->w, f->u, p.nw, w + p.oLo, w + p.oHi, st);
+  he = gfpk::launch_bigint_combine(C, p.lc, k, (int)p.b, f->w, f->u, p.nw, w + p.oE, w + p.oLo, w + p.oHi, st);
   if (he == hipSuccess) he = gfpk::launch_bigint_carry(w + p.oLo, w + p.oHi, p.nw, c, flags, agg, cin, st);
   return hip_status(he);
 }

@@ -77,9 +77,12 @@ hipError_t launch_unpad(int k, const CopyDesc* host_d, uint32_t nvec, const uint
                         uint64_t maxlen, hipStream_t st);
 
 // integer products (gfp_bigint.hip)
-hipError_t launch_bigint_split(const uint64_t* a, uint64_t na, uint64_t* A, uint64_t la, int k, int W, hipStream_t st);
-hipError_t launch_bigint_combine(const uint64_t* C, uint64_t lc, int CW, int W, int U, uint64_t nw, uint64_t* lo,
-                                 uint64_t* hi, hipStream_t st);
+hipError_t launch_bigint_split(const uint64_t* a, uint64_t na, uint64_t* A, uint64_t la, int k, int b, int ua,
+                               uint64_t d, hipStream_t st);
+hipError_t launch_bigint_combine(const uint64_t* C, uint64_t lc, int k, int b, int W, int U, uint64_t nw, uint64_t* E,
+                                 uint64_t* lo, uint64_t* hi, hipStream_t st);
+uint64_t bigint_eval_words();    // words per evaluated product coefficient
+int bigint_max_chunk_bits();
 uint64_t bigint_scan_blocks(uint64_t nw);
 hipError_t launch_bigint_carry(const uint64_t* lo, const uint64_t* hi, uint64_t nw, uint64_t* c, uint8_t* flags,
                                uint8_t* agg, uint8_t* cin, hipStream_t st);

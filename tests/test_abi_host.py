@@ -197,7 +197,7 @@ def test_k32_field_host():
 def test_k64_field_host():
     """The k = 64 prime of Table 1 (r = 2^63 - 2^40, K = 128): roots as the
     oracle's, sizes from K = 128 on, one radix-128 pass per launch; integer
-    products cut 62-bit chunks (a 63-bit chunk could exceed r)."""
+    products are offered."""
     L = _lib()
     f = gfp.Field(**P64)
     F = GFPField(**P64)
@@ -209,10 +209,10 @@ def test_k64_field_host():
     assert f.plan(2 ** 14) == "11" and f.plan(2 ** 13) == "1" and f.plan(128) == "1"
     b = ctypes.c_uint64()
     assert L.gfp_bigint_mul_workspace_size(f.handle, 10, 10, ctypes.byref(b)) == gfp.GFP_OK
-    # 62-bit chunks: 10 words = 11 coefficients each, 21 product coefficients,
-    # transform size 128 (K); workspace at least the polynomial product's
+    # 448-bit chunks: 10 words = 2 coefficients each, transform size 128 (K);
+    # workspace at least the polynomial product's
     w = ctypes.c_uint64()
-    assert L.gfp_polymul_workspace_size(f.handle, 11, 11, ctypes.byref(w)) == gfp.GFP_OK
+    assert L.gfp_polymul_workspace_size(f.handle, 2, 2, ctypes.byref(w)) == gfp.GFP_OK
     assert b.value >= w.value
 
 
@@ -227,10 +227,12 @@ def test_bigint_sizes():
     small = f.bigint_mul_workspace_size(10, 10)
     big = f.bigint_mul_workspace_size(2 ** 16, 2 ** 16)
     assert 0 < small < big
-    # la + lb - 1 = 2 ceil(64 2^18 / 63) - 1 > 2^19: transform size 2^20, products above 2^25 refused
+    # b = (8 63 - 2 - 24) / 2 = 239-bit coefficients for 2^18 words: la = 70198,
+    # transform size 2^18; 2^26 words (b = 234) need more than 2^25 points
     assert f.bigint_mul_workspace_size(2 ** 18, 2 ** 18) > big
+    f.bigint_mul_workspace_size(2 ** 25, 2 ** 25)
     with pytest.raises(gfp.GFPError):
-        f.bigint_mul_workspace_size(2 ** 25, 2 ** 25)
+        f.bigint_mul_workspace_size(2 ** 26, 2 ** 26)
 
 
 def test_plan_cache_round_trip(tmp_path):
