@@ -190,3 +190,34 @@ def test_maximum_size(torch_mod, name):
     back = f.fft_inverse(y)
     del y
     assert torch.equal(back, dx)
+
+
+@pytest.mark.parametrize("name,N", [("k32", 4096), ("k32", 8192), ("k64", 16384), ("k64", 8192), ("k8", 8192)])
+def test_stages_compose(torch_mod, name, N):
+    """gfp_fft_pass stage by stage (element-major between stages) gives
+    exactly gfp_fft_forward and gfp_fft_inverse, wherever 1/n is applied."""
+    import torch
+
+    from paper_1811_01490_amd import to_device, to_host
+
+    F, f = _field(name)
+    k, r = F.k, F.r
+    x = gi.operand(k, r, N, gi.BASE_SEED + 41, 0, edge_frac=0.02)
+    dx = to_device(x)
+    K = 2 * k
+    e, t = 0, 1
+    while t * K <= N:
+        t *= K
+        e += 1
+    stages = e + (1 if t < N else 0)
+    for inverse in (False, True):
+        bufs = [torch.empty(N * k, dtype=torch.int64, device="cuda") for _ in range(2)]
+        out = torch.empty_like(dx)
+        src = dx
+        for s in range(stages):
+            last = s == stages - 1
+            dst = out if last else bufs[s % 2]
+            f.fft_pass(s, src, dst, N, inverse=inverse, in_element_major=s > 0, out_element_major=not last)
+            src = dst
+        want = f.fft_inverse(dx) if inverse else f.fft_forward(dx)
+        assert np.array_equal(to_host(out), to_host(want)), (name, N, inverse)

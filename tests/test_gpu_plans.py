@@ -149,3 +149,5 @@ def test_tuner_picks_a_valid_plan(torch_mod):
     assert plan_em in compositions(4, 16) and f.plan(N, nvec=2, layout=1) == plan_em
     plan16, _ = Field(**P16).tune(32768, nvec=2, layout=1)
     assert plan16 == "111"  # no fused pair for k = 16
+    plan32, _ = Field(k=32, r=2 ** 62 + 2 ** 56).tune(2 ** 18)
+    assert plan32 == "111"  # one pass per launch for k = 32
