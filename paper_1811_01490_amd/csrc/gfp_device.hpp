@@ -91,6 +91,10 @@ __device__ __forceinline__ uint32_t dig_rot(uint32_t v) {
     return v;
   } else if constexpr (Geo<KD>::ROW) {
     return row_ror<n * Geo<KD>::GPL>(v);
+  } else if constexpr (KD == 64 && n == 1) {
+    // one element spans the whole wavefront: a one-lane rotation is a single
+    // DPP wave_ror:1 (lane i reads lane i - 1 mod 64), no LDS crossbar trip
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x13C, 0xF, 0xF, false);
   } else {
     const int l = (int)(threadIdx.x & 63);
     return (uint32_t)__builtin_amdgcn_ds_bpermute(((l & Geo<KD>::HI) | ((l - n) & (KD - 1))) << 2, (int)v);
