@@ -70,6 +70,11 @@ struct Geo {
   __device__ static __forceinline__ int lane_of(int l, int d) {
     return ROW ? ((l & 0x30) | (d * GPL) | ((l & 15) % GPL)) : ((l & HI) | d);
   }
+  // Shorter product tail (add_carried_q, undefined-old rotations, one SGPR
+  // constant per shifted add).  k = 16 keeps the longer forms: its uniform-
+  // twiddle passes sit at the 128-VGPR (4 wavefronts per SIMD) limit, which
+  // the shorter forms' register allocation exceeds.
+  static constexpr bool LEAN = KD != 16;
 };
 
 // DPP row rotate: lane i of a row takes the value of lane (i - N) mod 16.
@@ -79,6 +84,19 @@ __device__ __forceinline__ uint32_t row_ror(uint32_t v) {
     return v;
   } else {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x120 + (N & 15), 0xF, 0xF, false);
+  }
+}
+
+// row_ror for a result used as is: every lane of a rotation reads a valid
+// lane, so the DPP "old" operand is never taken and is left undefined (no
+// register to clear first).  row_ror keeps old = 0, which lets the compiler
+// fold a rotation into the DPP form of the xor that follows it.
+template <int N>
+__device__ __forceinline__ uint32_t row_ror_u(uint32_t v) {
+  if constexpr ((N & 15) == 0) {
+    return v;
+  } else {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x120 + (N & 15), 0xF, 0xF, false);
   }
 }
 
@@ -98,6 +116,21 @@ __device__ __forceinline__ uint32_t dig_rot(uint32_t v) {
   } else {
     const int l = (int)(threadIdx.x & 63);
     return (uint32_t)__builtin_amdgcn_ds_bpermute(((l & Geo<KD>::HI) | ((l - n) & (KD - 1))) << 2, (int)v);
+  }
+}
+
+// dig_rot with the undefined-old forms (Geo::LEAN shapes).
+template <int KD, int N>
+__device__ __forceinline__ uint32_t dig_rot_u(uint32_t v) {
+  constexpr int n = N & (KD - 1);
+  if constexpr (!Geo<KD>::LEAN || n == 0) {
+    return dig_rot<KD, N>(v);
+  } else if constexpr (Geo<KD>::ROW) {
+    return row_ror_u<n * Geo<KD>::GPL>(v);
+  } else if constexpr (KD == 64 && n == 1) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xF, 0xF, false);
+  } else {
+    return dig_rot<KD, N>(v);
   }
 }
 
@@ -125,8 +158,8 @@ __device__ __forceinline__ L96 l96_sub(L96 a, L96 b) {
 __device__ __forceinline__ L96 l96_sel(bool c, L96 a, L96 b) { return L96{c ? a.lo : b.lo, c ? a.hi : b.hi}; }
 template <int KD, int N>
 __device__ __forceinline__ L96 l96_rot(L96 a) {
-  uint32_t w0 = dig_rot<KD, N>((uint32_t)a.lo), w1 = dig_rot<KD, N>((uint32_t)(a.lo >> 32));
-  uint32_t w2 = dig_rot<KD, N>((uint32_t)a.hi);
+  uint32_t w0 = dig_rot_u<KD, N>((uint32_t)a.lo), w1 = dig_rot_u<KD, N>((uint32_t)(a.lo >> 32));
+  uint32_t w2 = dig_rot_u<KD, N>((uint32_t)a.hi);
   return L96{((uint64_t)w1 << 32) | w0, (int32_t)w2};
 }
 // a r^e for a run-time exponent 0 <= e < 2k (r^k = -1): lane m takes digit
@@ -244,6 +277,15 @@ __device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32
 __device__ __forceinline__ uint32_t sgpr_const(uint32_t c) {
   uint32_t v;
   asm("s_mov_b32 %0, %1" : "=s"(v) : "i"(c));
+  return v;
+}
+// The same as a value of its own (ID tells the copies apart), so that the
+// compiler cannot merge x*c + y*c into (x + y)*c: that 64-bit add of two
+// zero-extended words costs more than the second v_mad_u64_u32.
+template <int ID>
+__device__ __forceinline__ uint32_t sgpr_const_n(uint32_t c) {
+  uint32_t v;
+  asm("s_mov_b32 %0, %1 ; %2" : "=s"(v) : "i"(c), "i"(ID));
   return v;
 }
 __device__ __forceinline__ uint64_t mad32(uint32_t x, uint32_t c, uint64_t acc) { return (uint64_t)x * c + acc; }
@@ -481,6 +523,27 @@ __device__ __forceinline__ RotLane<KD> rot_lane(int rot, int m) {
   return r;
 }
 
+// T + Q_{m-1} in lane m and T - Q_{k-1} in lane 0 (r^k = -1).  Geo::LEAN
+// shapes negate as ~Q + 1: the complement rides on the rotation (one DPP xor
+// per word) and the +1 enters as the carry into the low word.
+template <int KD>
+__device__ __forceinline__ L96 add_carried_q(L96 T, L96 Q, int m) {
+  if constexpr (Geo<KD>::LEAN) {
+    const uint32_t wrap = (m == 0) ? 0xFFFFFFFFu : 0u;
+    const uint32_t q0 = dig_rot<KD, 1>((uint32_t)Q.lo) ^ wrap;
+    const uint32_t q1 = dig_rot<KD, 1>((uint32_t)(Q.lo >> 32)) ^ wrap;
+    const uint32_t q2 = dig_rot<KD, 1>((uint32_t)Q.hi) ^ wrap;
+    unsigned c;
+    const uint32_t o0 = __builtin_addc((uint32_t)T.lo, q0, (unsigned)(m == 0), &c);
+    const uint32_t o1 = __builtin_addc((uint32_t)(T.lo >> 32), q1, c, &c);
+    const uint32_t o2 = (uint32_t)T.hi + q2 + c;
+    return L96{((uint64_t)o1 << 32) | o0, (int32_t)o2};
+  } else {
+    const L96 nq = l96_sub(L96{0, 0}, Q);
+    return l96_add(T, l96_rot<KD, 1>((m == KD - 1) ? nq : Q));
+  }
+}
+
 // Column C = (l0, l1, h0, h1, h2) (signed 160-bit, h2 the top word) of lane
 // m as C = Q r + T; returns the lazy digit T_m + Q_{m-1} (lane 0 takes
 // -Q_{k-1}, since r^k = -1).
@@ -495,8 +558,7 @@ __device__ __forceinline__ L96 column_tail(uint32_t l0, uint32_t l1, uint32_t h0
     } else {
       split_qr160(l0, l1, h0, h1, h2, T, Qs);
     }
-    const L96 nqs = l96_sub(L96{0, 0}, Qs);
-    return l96_add(l96(T), l96_rot<KD, 1>((m == KD - 1) ? nqs : Qs));
+    return add_carried_q<KD>(l96(T), Qs, m);
   } else {
   constexpr int SA = F::SA, SB = F::SB;
   unsigned cy;
@@ -520,10 +582,7 @@ __device__ __forceinline__ L96 column_tail(uint32_t l0, uint32_t l1, uint32_t h0
   L96 Q;
   Q.lo = ((uint64_t)g1 << 32 | g0) << SA;
   Q.hi = (int32_t)((g2 << SA) | (g1 >> (32 - SA)));
-  // Q_{m-1} into lane m; lane 0 takes -Q_{k-1}
-  const L96 nq = l96_sub(L96{0, 0}, Q);
-  const L96 qs = (m == KD - 1) ? nq : Q;
-  return l96_add(Tm, l96_rot<KD, 1>(qs));
+  return add_carried_q<KD>(Tm, Q, m);
   }
 }
 
@@ -575,17 +634,18 @@ __device__ __forceinline__ L96 mul_core_y(uint32_t v0, uint32_t v1, YL&& yl, uin
   // + S enters c0..c2.  Every shifted add is one v_mad_u64_u32 with a
   // power-of-two multiplier held in an SGPR.  c0, c1 < 2^59, c2 < 2^49,
   // c3 < 2^38.
+  constexpr bool LEAN = Geo<KD>::LEAN;
   const uint32_t K22 = sgpr_const(1u << 22), K12 = sgpr_const(1u << 12), ONE = sgpr_const(1u);
-  uint64_t c0 = mad32(lo32(a01), K22, a00);
+  uint64_t c0 = mad32(lo32(a01), LEAN ? sgpr_const_n<0>(1u << 22) : K22, a00);
   c0 = mad32(s0, ONE, c0);
-  uint64_t c1 = mad32(hi32(a01), K22, a10);
-  c1 = mad32(lo32(a02), K12, c1);
-  c1 = mad32(lo32(a11), K22, c1);
+  uint64_t c1 = mad32(hi32(a01), LEAN ? sgpr_const_n<1>(1u << 22) : K22, a10);
+  c1 = mad32(lo32(a02), LEAN ? sgpr_const_n<2>(1u << 12) : K12, c1);
+  c1 = mad32(lo32(a11), LEAN ? sgpr_const_n<3>(1u << 22) : K22, c1);
   c1 = mad32(s1, ONE, c1);
-  uint64_t c2 = mad32(hi32(a02), K12, (uint64_t)s2);
-  c2 = mad32(hi32(a11), K22, c2);
-  c2 = mad32(lo32(a12), K12, c2);
-  const uint64_t c3 = mad32(hi32(a12), K12, 0ull);
+  uint64_t c2 = mad32(hi32(a02), LEAN ? sgpr_const_n<4>(1u << 12) : K12, (uint64_t)s2);
+  c2 = mad32(hi32(a11), LEAN ? sgpr_const_n<5>(1u << 22) : K22, c2);
+  c2 = mad32(lo32(a12), LEAN ? sgpr_const_n<6>(1u << 12) : K12, c2);
+  const uint64_t c3 = mad32(hi32(a12), LEAN ? sgpr_const_n<7>(1u << 12) : K12, 0ull);
   // C = L + H 2^64, L = (l0, l1), H = (h0, h1, h2) signed 96-bit, |H| < 2^71
   unsigned cy;
   const uint32_t l0 = lo32(c0);
