@@ -71,9 +71,11 @@ struct Geo {
     return ROW ? ((l & 0x30) | (d * GPL) | ((l & 15) % GPL)) : ((l & HI) | d);
   }
   // Shorter product tail (add_carried_q, undefined-old rotations, one SGPR
-  // constant per shifted add).  k = 16 keeps the longer forms: its uniform-
-  // twiddle passes sit at the 128-VGPR (4 wavefronts per SIMD) limit, which
-  // the shorter forms' register allocation exceeds.
+  // constant per shifted add): the default of the LN template parameter
+  // below.  k = 16 keeps the longer forms by default: its uniform-twiddle
+  // passes sit at the 128-VGPR (4 wavefronts per SIMD) limit, which the
+  // shorter forms' register allocation exceeds; its per-group passes take
+  // the shorter forms (LN = true, set by the kernel).
   static constexpr bool LEAN = KD != 16;
 };
 
@@ -119,11 +121,11 @@ __device__ __forceinline__ uint32_t dig_rot(uint32_t v) {
   }
 }
 
-// dig_rot with the undefined-old forms (Geo::LEAN shapes).
-template <int KD, int N>
+// dig_rot with the undefined-old forms (LN).
+template <int KD, int N, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ uint32_t dig_rot_u(uint32_t v) {
   constexpr int n = N & (KD - 1);
-  if constexpr (!Geo<KD>::LEAN || n == 0) {
+  if constexpr (!LN || n == 0) {
     return dig_rot<KD, N>(v);
   } else if constexpr (Geo<KD>::ROW) {
     return row_ror_u<n * Geo<KD>::GPL>(v);
@@ -156,10 +158,10 @@ __device__ __forceinline__ L96 l96_sub(L96 a, L96 b) {
   return c;
 }
 __device__ __forceinline__ L96 l96_sel(bool c, L96 a, L96 b) { return L96{c ? a.lo : b.lo, c ? a.hi : b.hi}; }
-template <int KD, int N>
+template <int KD, int N, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ L96 l96_rot(L96 a) {
-  uint32_t w0 = dig_rot_u<KD, N>((uint32_t)a.lo), w1 = dig_rot_u<KD, N>((uint32_t)(a.lo >> 32));
-  uint32_t w2 = dig_rot_u<KD, N>((uint32_t)a.hi);
+  uint32_t w0 = dig_rot_u<KD, N, LN>((uint32_t)a.lo), w1 = dig_rot_u<KD, N, LN>((uint32_t)(a.lo >> 32));
+  uint32_t w2 = dig_rot_u<KD, N, LN>((uint32_t)a.hi);
   return L96{((uint64_t)w1 << 32) | w0, (int32_t)w2};
 }
 // a r^e for a run-time exponent 0 <= e < 2k (r^k = -1): lane m takes digit
@@ -190,7 +192,7 @@ __device__ __forceinline__ i128 l96_to_i128(L96 a) { return ((i128)a.hi << 64) +
 // wrapped lanes (digit m < i) negated; the negation is folded into the
 // butterfly by swapping its two outputs in those lanes.
 // ------------------------------------------------------------------------
-template <int KD, bool INV, int EXP>
+template <int KD, bool INV, int EXP, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ void bfly(L96& a, L96& b, int m) {
   if constexpr (EXP == 0) {
     L96 s = l96_add(a, b), d = l96_sub(a, b);
@@ -200,7 +202,7 @@ __device__ __forceinline__ void bfly(L96& a, L96& b, int m) {
     // forward: r^EXP = rotate by EXP, negate digits m < EXP.
     // inverse: r^-EXP = -r^(KD-EXP) = rotate by KD-EXP, negate digits m >= KD-EXP.
     constexpr int ROT = INV ? (KD - EXP) : EXP;
-    L96 bp = l96_rot<KD, ROT>(b);
+    L96 bp = l96_rot<KD, ROT, LN>(b);
     bool f = INV ? (m >= ROT) : (m < ROT);
     L96 s = l96_add(a, bp), d = l96_sub(a, bp);
     a = l96_sel(f, d, s);
@@ -212,7 +214,7 @@ __device__ __forceinline__ void bfly(L96& a, L96& b, int m) {
 // since r has order K = 2k): the first LP levels of the same network.  At
 // level half-size H the butterfly j uses (r^(K/P))^(j P/(2H)) = r^(j K/(2H)),
 // the exponent DFT_K uses at that level.
-template <int KD, bool INV, int LP>
+template <int KD, bool INV, int LP, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ void dft_pow2(L96 (&v)[1 << LP], int m) {
   constexpr int KB = 2 * KD;
   constexpr int P = 1 << LP;
@@ -228,7 +230,7 @@ __device__ __forceinline__ void dft_pow2(L96 (&v)[1 << LP], int m) {
       constexpr int blk = decltype(B)::value / H, j = decltype(B)::value % H;
       constexpr int i0 = blk * 2 * H + j;
       constexpr int e = j * (KB / (2 * H));  // exponent of r, 0 <= e < KD
-      bfly<KD, INV, e>(a[i0], a[i0 + H], m);
+      bfly<KD, INV, e, LN>(a[i0], a[i0 + H], m);
     });
   });
   static_for<P>([&](auto I) {
@@ -237,9 +239,9 @@ __device__ __forceinline__ void dft_pow2(L96 (&v)[1 << LP], int m) {
   });
 }
 
-template <int KD, bool INV>
+template <int KD, bool INV, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ void dft_base(L96 (&v)[2 * KD], int m) {
-  dft_pow2<KD, INV, ilog2(2 * KD)>(v, m);
+  dft_pow2<KD, INV, ilog2(2 * KD), LN>(v, m);
 }
 
 // ------------------------------------------------------------------------
@@ -523,12 +525,12 @@ __device__ __forceinline__ RotLane<KD> rot_lane(int rot, int m) {
   return r;
 }
 
-// T + Q_{m-1} in lane m and T - Q_{k-1} in lane 0 (r^k = -1).  Geo::LEAN
-// shapes negate as ~Q + 1: the complement rides on the rotation (one DPP xor
-// per word) and the +1 enters as the carry into the low word.
-template <int KD>
+// T + Q_{m-1} in lane m and T - Q_{k-1} in lane 0 (r^k = -1).  With LN the
+// negation is ~Q + 1: the complement rides on the rotation (one DPP xor per
+// word) and the +1 enters as the carry into the low word.
+template <int KD, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ L96 add_carried_q(L96 T, L96 Q, int m) {
-  if constexpr (Geo<KD>::LEAN) {
+  if constexpr (LN) {
     const uint32_t wrap = (m == 0) ? 0xFFFFFFFFu : 0u;
     const uint32_t q0 = dig_rot<KD, 1>((uint32_t)Q.lo) ^ wrap;
     const uint32_t q1 = dig_rot<KD, 1>((uint32_t)(Q.lo >> 32)) ^ wrap;
@@ -547,7 +549,7 @@ __device__ __forceinline__ L96 add_carried_q(L96 T, L96 Q, int m) {
 // Column C = (l0, l1, h0, h1, h2) (signed 160-bit, h2 the top word) of lane
 // m as C = Q r + T; returns the lazy digit T_m + Q_{m-1} (lane 0 takes
 // -Q_{k-1}, since r^k = -1).
-template <int KD, int W, int U>
+template <int KD, int W, int U, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ L96 column_tail(uint32_t l0, uint32_t l1, uint32_t h0, uint32_t h1, uint32_t h2, int m) {
   typedef Field<KD, W, U> F;
   if constexpr (F::SPLIT) {
@@ -558,7 +560,7 @@ __device__ __forceinline__ L96 column_tail(uint32_t l0, uint32_t l1, uint32_t h0
     } else {
       split_qr160(l0, l1, h0, h1, h2, T, Qs);
     }
-    return add_carried_q<KD>(l96(T), Qs, m);
+    return add_carried_q<KD, LN>(l96(T), Qs, m);
   } else {
   constexpr int SA = F::SA, SB = F::SB;
   unsigned cy;
@@ -582,7 +584,7 @@ __device__ __forceinline__ L96 column_tail(uint32_t l0, uint32_t l1, uint32_t h0
   L96 Q;
   Q.lo = ((uint64_t)g1 << 32 | g0) << SA;
   Q.hi = (int32_t)((g2 << SA) | (g1 >> (32 - SA)));
-  return add_carried_q<KD>(Tm, Q, m);
+  return add_carried_q<KD, LN>(Tm, Q, m);
   }
 }
 
@@ -591,7 +593,7 @@ __device__ __forceinline__ L96 column_tail(uint32_t l0, uint32_t l1, uint32_t h0
 // k <= 32, an int for k = 64).
 // (s0, s1, s2): the correction sum S_m as three 32-bit words.
 // Returns the lazy product digit T_m + Q_{m-1}.
-template <int KD, int W, int U, class YL>
+template <int KD, int W, int U, bool LN = Geo<KD>::LEAN, class YL>
 __device__ __forceinline__ L96 mul_core_y(uint32_t v0, uint32_t v1, YL&& yl, uint32_t s0, uint32_t s1, uint32_t s2,
                                           int m) {
   const uint32_t wrap = (m == 0) ? 0xFFFFFFFFu : 0u;
@@ -634,7 +636,7 @@ __device__ __forceinline__ L96 mul_core_y(uint32_t v0, uint32_t v1, YL&& yl, uin
   // + S enters c0..c2.  Every shifted add is one v_mad_u64_u32 with a
   // power-of-two multiplier held in an SGPR.  c0, c1 < 2^59, c2 < 2^49,
   // c3 < 2^38.
-  constexpr bool LEAN = Geo<KD>::LEAN;
+  constexpr bool LEAN = LN;
   const uint32_t K22 = sgpr_const(1u << 22), K12 = sgpr_const(1u << 12), ONE = sgpr_const(1u);
   uint64_t c0 = mad32(lo32(a01), LEAN ? sgpr_const_n<0>(1u << 22) : K22, a00);
   c0 = mad32(s0, ONE, c0);
@@ -656,13 +658,13 @@ __device__ __forceinline__ L96 mul_core_y(uint32_t v0, uint32_t v1, YL&& yl, uin
   h0 = __builtin_subc(h0, s0, 0u, &cy);
   h1 = __builtin_subc(h1, s1, cy, &cy);
   h2 = h2 - s2 - cy;
-  return column_tail<KD, W, U>(l0, l1, h0, h1, h2, m);
+  return column_tail<KD, W, U, LN>(l0, l1, h0, h1, h2, m);
 }
 
-template <int KD, int W, int U>
+template <int KD, int W, int U, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ L96 mul_core(uint32_t v0, uint32_t v1, const YLimbs<KD>& y, uint32_t s0, uint32_t s1,
                                         uint32_t s2, int m) {
-  return mul_core_y<KD, W, U>(
+  return mul_core_y<KD, W, U, LN>(
       v0, v1,
       [&](auto T, uint32_t& y0, uint32_t& y1, uint32_t& y2) {
         constexpr int t = decltype(T)::value;
@@ -736,7 +738,7 @@ __device__ __forceinline__ L96 mul_tw_stream(uint32_t v0, uint32_t v1, const uin
 }
 
 // x * tw * r^rot where lane m already holds digit rl.src of x (xs).
-template <int KD, int W, int U>
+template <int KD, int W, int U, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ L96 mul_twiddle_pre(uint64_t xs, const uint32_t* __restrict__ tw, const RotLane<KD>& rl,
                                                int m) {
   if constexpr (KD == 64) {
@@ -748,19 +750,19 @@ __device__ __forceinline__ L96 mul_twiddle_pre(uint64_t xs, const uint32_t* __re
     tw_limbs<KD>(tw, y);
     uint32_t s0, s1, s2;
     tw_correction<KD>(tw, rl, s0, s1, s2);
-    return mul_core<KD, W, U>((uint32_t)xs ^ rl.mask, (uint32_t)(xs >> 32) ^ rl.mask, y, s0, s1, s2, m);
+    return mul_core<KD, W, U, LN>((uint32_t)xs ^ rl.mask, (uint32_t)(xs >> 32) ^ rl.mask, y, s0, s1, s2, m);
   }
 }
 
 // x * tw * r^rot where lane m holds digit m of x (the digit is fetched from
 // the lane holding digit (m - rot) mod k with a cross-lane permute).
-template <int KD, int W, int U>
+template <int KD, int W, int U, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ L96 mul_twiddle(uint64_t x, const uint32_t* __restrict__ tw, int rot, int l, int m) {
   const RotLane<KD> rl = rot_lane<KD>(rot, m);
   const int src = Geo<KD>::lane_of(l, rl.src);
   const uint32_t x0 = (uint32_t)__shfl((int)(uint32_t)x, src, 64);
   const uint32_t x1 = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, 64);
-  return mul_twiddle_pre<KD, W, U>(((uint64_t)x1 << 32) | x0, tw, rl, m);
+  return mul_twiddle_pre<KD, W, U, LN>(((uint64_t)x1 << 32) | x0, tw, rl, m);
 }
 
 // Same with a wavefront-uniform twiddle entry and rotation: the limbs are
@@ -810,7 +812,7 @@ __device__ __forceinline__ L96 mul_entry_uniform(uint64_t x, const uint32_t* __r
 }
 
 // The same with a per-group entry (vector loads of the limbs).
-template <int KD, int W, int U>
+template <int KD, int W, int U, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ L96 mul_entry(uint64_t x, const uint32_t* __restrict__ tw, int m) {
   slot_fence();
   if constexpr (KD == 64) {
@@ -820,7 +822,7 @@ __device__ __forceinline__ L96 mul_entry(uint64_t x, const uint32_t* __restrict_
     YLimbs<KD> y;
     tw_limbs<KD>(tw, y);
     const uint32_t* suf = tw + TwLayout<KD>::SUF + 3 * (m + 1);
-    return mul_core<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), y, suf[0], suf[1], suf[2], m);
+    return mul_core<KD, W, U, LN>((uint32_t)x, (uint32_t)(x >> 32), y, suf[0], suf[1], suf[2], m);
   }
 }
 

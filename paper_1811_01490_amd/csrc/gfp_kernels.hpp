@@ -82,13 +82,17 @@ __device__ __forceinline__ L96 first_slot(uint64_t x, const uint64_t* __restrict
 // Used when every a has at least G groups (all passes but the last).
 // T2: the twiddles come from the table of w^(K i) without rotations (every
 // pass but the last); otherwise from the table of w^j with r^rho rotations.
+// k = 16 per-group passes: the shorter product tail (LN) and at most 2
+// wavefronts per SIMD expected, so the scheduler keeps their instruction-level
+// parallelism (with fewer registers it aims at 3 and runs slower).
 template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T2>
-__global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
-                                              uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
-                                              const uint32_t* __restrict__ tw, const uint32_t* __restrict__ tw2,
-                                              int log2n, int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin,
-                                              uint64_t vout) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16 && !UNIF ? 2 : 8))) void k_pass(
+    const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2, uint64_t se_in, uint64_t sd_in,
+    uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
+    const uint32_t* __restrict__ tw2, int log2n, int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin,
+    uint64_t vout) {
   typedef Geo<KD> Gm;
+  constexpr bool LN = Gm::LEAN || !UNIF;
   constexpr int KB = Gm::KB;
   constexpr int LOGKB = ilog2(KB);
   const int l = Gm::lane();
@@ -166,7 +170,7 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, c
         if constexpr (UNIF) {
           v[t] = mul_entry_uniform<KD, W, U>(x[t], e, m);
         } else {
-          v[t] = mul_entry<KD, W, U>(x[t], e, m);
+          v[t] = mul_entry<KD, W, U, LN>(x[t], e, m);
         }
       });
     } else {
@@ -180,13 +184,13 @@ __global__ __launch_bounds__(256) void k_pass(const uint64_t* __restrict__ in, c
         if constexpr (UNIF) {
           v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
         } else {
-          v[t] = mul_twiddle<KD, W, U>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
+          v[t] = mul_twiddle<KD, W, U, LN>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
         }
       });
     }
   }
 
-  dft_base<KD, INV>(v, m);
+  dft_base<KD, INV, LN>(v, m);
 
   const uint64_t obase = (jj - a) * KB + a;
   static_for<KB>([&](auto T) {
