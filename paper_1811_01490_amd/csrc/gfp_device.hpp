@@ -190,9 +190,12 @@ __device__ __forceinline__ i128 l96_to_i128(L96 a) { return ((i128)a.hi << 64) +
 // output in natural order.  Butterfly (a, b) at exponent i: b' = b r^{+-i},
 // outputs a + b', a - b'.  b r^i is the row rotation by i digits with the
 // wrapped lanes (digit m < i) negated; the negation is folded into the
-// butterfly by swapping its two outputs in those lanes.
+// butterfly: by swapping its two outputs in those lanes, or (CB) by adding
+// the complement of the rotated word with a carry-in of 1.  CB is chosen per
+// kernel: it pays where its rotations fold into DPP xors (the fused pairs,
+// k = 32, 64) and not in the k = 8 last pass or the k = 16 passes.
 // ------------------------------------------------------------------------
-template <int KD, bool INV, int EXP, bool LN = Geo<KD>::LEAN>
+template <int KD, bool INV, int EXP, bool LN = Geo<KD>::LEAN, bool CB = Geo<KD>::LEAN>
 __device__ __forceinline__ void bfly(L96& a, L96& b, int m) {
   if constexpr (EXP == 0) {
     L96 s = l96_add(a, b), d = l96_sub(a, b);
@@ -202,11 +205,31 @@ __device__ __forceinline__ void bfly(L96& a, L96& b, int m) {
     // forward: r^EXP = rotate by EXP, negate digits m < EXP.
     // inverse: r^-EXP = -r^(KD-EXP) = rotate by KD-EXP, negate digits m >= KD-EXP.
     constexpr int ROT = INV ? (KD - EXP) : EXP;
-    L96 bp = l96_rot<KD, ROT, LN>(b);
-    bool f = INV ? (m >= ROT) : (m < ROT);
-    L96 s = l96_add(a, bp), d = l96_sub(a, bp);
-    a = l96_sel(f, d, s);
-    b = l96_sel(f, s, d);
+    const bool f = INV ? (m >= ROT) : (m < ROT);
+    if constexpr (CB) {
+      // in the negated lanes b' = ~bp + 1 = -bp: the complement rides on the
+      // rotation (DPP xor) and the 1 enters as the carry of a + b' and the
+      // borrow of a - b', so a + b' = a - bp and a - b' = a + bp (mod 2^96)
+      const uint32_t M = f ? 0xFFFFFFFFu : 0u;
+      const uint32_t b0 = dig_rot<KD, ROT>((uint32_t)b.lo) ^ M;
+      const uint32_t b1 = dig_rot<KD, ROT>((uint32_t)(b.lo >> 32)) ^ M;
+      const uint32_t b2 = dig_rot<KD, ROT>((uint32_t)b.hi) ^ M;
+      const uint32_t a0 = (uint32_t)a.lo, a1 = (uint32_t)(a.lo >> 32), a2 = (uint32_t)a.hi;
+      unsigned c, w;
+      const uint32_t s0 = __builtin_addc(a0, b0, (unsigned)f, &c);
+      const uint32_t s1 = __builtin_addc(a1, b1, c, &c);
+      const uint32_t s2 = a2 + b2 + c;
+      const uint32_t d0 = __builtin_subc(a0, b0, (unsigned)f, &w);
+      const uint32_t d1 = __builtin_subc(a1, b1, w, &w);
+      const uint32_t d2 = a2 - b2 - w;
+      a = L96{((uint64_t)s1 << 32) | s0, (int32_t)s2};
+      b = L96{((uint64_t)d1 << 32) | d0, (int32_t)d2};
+    } else {
+      L96 bp = l96_rot<KD, ROT, LN>(b);
+      L96 s = l96_add(a, bp), d = l96_sub(a, bp);
+      a = l96_sel(f, d, s);
+      b = l96_sel(f, s, d);
+    }
   }
 }
 
@@ -214,7 +237,7 @@ __device__ __forceinline__ void bfly(L96& a, L96& b, int m) {
 // since r has order K = 2k): the first LP levels of the same network.  At
 // level half-size H the butterfly j uses (r^(K/P))^(j P/(2H)) = r^(j K/(2H)),
 // the exponent DFT_K uses at that level.
-template <int KD, bool INV, int LP, bool LN = Geo<KD>::LEAN>
+template <int KD, bool INV, int LP, bool LN = Geo<KD>::LEAN, bool CB = Geo<KD>::LEAN>
 __device__ __forceinline__ void dft_pow2(L96 (&v)[1 << LP], int m) {
   constexpr int KB = 2 * KD;
   constexpr int P = 1 << LP;
@@ -230,7 +253,7 @@ __device__ __forceinline__ void dft_pow2(L96 (&v)[1 << LP], int m) {
       constexpr int blk = decltype(B)::value / H, j = decltype(B)::value % H;
       constexpr int i0 = blk * 2 * H + j;
       constexpr int e = j * (KB / (2 * H));  // exponent of r, 0 <= e < KD
-      bfly<KD, INV, e, LN>(a[i0], a[i0 + H], m);
+      bfly<KD, INV, e, LN, CB>(a[i0], a[i0 + H], m);
     });
   });
   static_for<P>([&](auto I) {
@@ -239,9 +262,9 @@ __device__ __forceinline__ void dft_pow2(L96 (&v)[1 << LP], int m) {
   });
 }
 
-template <int KD, bool INV, bool LN = Geo<KD>::LEAN>
+template <int KD, bool INV, bool LN = Geo<KD>::LEAN, bool CB = Geo<KD>::LEAN>
 __device__ __forceinline__ void dft_base(L96 (&v)[2 * KD], int m) {
-  dft_pow2<KD, INV, ilog2(2 * KD), LN>(v, m);
+  dft_pow2<KD, INV, ilog2(2 * KD), LN, CB>(v, m);
 }
 
 // ------------------------------------------------------------------------
