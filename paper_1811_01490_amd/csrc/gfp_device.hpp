@@ -193,7 +193,8 @@ __device__ __forceinline__ i128 l96_to_i128(L96 a) { return ((i128)a.hi << 64) +
 // butterfly: by swapping its two outputs in those lanes, or (CB) by adding
 // the complement of the rotated word with a carry-in of 1.  CB is chosen per
 // kernel: it pays where its rotations fold into DPP xors (the fused pairs,
-// k = 32, 64) and not in the k = 8 last pass or the k = 16 passes.
+// the k = 16 uniform-twiddle passes, k = 32, 64) and not in the k = 8 last
+// pass or the k = 16 per-group passes.
 // ------------------------------------------------------------------------
 template <int KD, bool INV, int EXP, bool LN = Geo<KD>::LEAN, bool CB = Geo<KD>::LEAN>
 __device__ __forceinline__ void bfly(L96& a, L96& b, int m) {

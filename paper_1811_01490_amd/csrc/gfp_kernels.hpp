@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16
     }
   }
 
-  dft_base<KD, INV, LN, LN && KD != 16 && !LAST>(v, m);
+  dft_base<KD, INV, LN, (LN && KD != 16 && !LAST) || (KD == 16 && UNIF)>(v, m);
 
   const uint64_t obase = (jj - a) * KB + a;
   static_for<KB>([&](auto T) {
