@@ -14,10 +14,10 @@ Two kinds of code live here:
   what the parity tests compare against;
 * the paper's own element algorithms, taken step by step from the text
   (``paper_add`` = Alg. 2 of section 2.2, ``paper_sub`` = the subtraction
-  the text names but never prints, ``paper_mul_pow_r`` = the cyclic shift of
-  section 2.3, ``paper_mul`` = Alg. 3 of section 2.4 with the column formula
-  and (l, h, c) split of section 3.1.1, ``paper_root_of_unity`` = Alg. 1 of
-  section 2.1).  They work on digit vectors with unbounded Python integers,
+  the text names but never prints, ``paper_mul_pow_r`` = the signed
+  cyclic shift of section 2.3, ``paper_mul`` = Alg. 3 of section 2.4 with
+  the column formula and (l, h, c) split of section 3.1.1,
+  ``paper_root_of_unity`` = Alg. 1 of section 2.1).  They work on digit vectors with unbounded Python integers,
   so the 64-bit overflow the printed C would hit for r > 2^63 cannot occur
   here.  Tests pin them to the plain definitions.
 """
@@ -166,35 +166,25 @@ class GFPField:
         return self.paper_add(x, self.paper_neg(y))
 
     def paper_mul_pow_r(self, x, s: int) -> list:
-        """x * r^s by cyclic shift (section 2.3).
+        """x * r^s (section 2.3: multiplying by a power of r is a cyclic shift
+        of the digits in which every digit that passes r^(k-1) changes sign,
+        because r^k = -1).
 
-        s is taken mod 2k; s = k is negation; k < s < 2k is -(x r^(s-k)).
-        For 0 < s < k the digits shift up by s; the s digits pushed past
-        r^(k-1) come back at the bottom with a minus sign (r^k = -1):
-        x r^s = b - a with b = (0,..,0, x_0, .., x_{k-1-s}) and
-        a = (x_{k-s}, .., x_{k-1}, 0, .., 0).  If x_{k-1} = r (x = p - 1) the
-        wrapped digit r is rewritten as a carry, as the printed listing does."""
+        Written from that identity: r has order 2k, so only s mod 2k
+        matters; r^s = (-1)^e r^t with s = e k + t, 0 <= t < k.  Digit i of x
+        then lands at position (i + t) mod k, with sign -1 when i + t >= k,
+        and the whole vector takes the sign (-1)^e.  The signed digits are
+        summed as an integer and brought back to the canonical encoding by
+        from_int, so the p - 1 encoding (top digit r) needs no special case:
+        its digit r simply moves like any other digit."""
         k, r = self.k, self.r
-        s %= 2 * k
-        x = [int(d) for d in x]
-        if s == 0:
-            return list(x)
-        if s == k:
-            return self.paper_neg(x)
-        if s > k:
-            x = self.paper_neg(x)
-            s -= k
-        b = [0] * k
-        a = [0] * k
-        for i in range(k - s):
-            b[i + s] = x[i]
-        for i in range(k - s, k):
-            a[i - (k - s)] = x[i]
-        if x[k - 1] == r:
-            # the wrapped top digit r at position s-1 equals 1 at position s
-            a[s - 1] -= r
-            a[s] += 1
-        return self.paper_sub(b, a)
+        e, t = divmod(s % (2 * k), k)
+        signed = [0] * k
+        for i, d in enumerate(int(v) for v in x):
+            pos = i + t
+            signed[pos % k] += -d if pos >= k else d
+        value = sum(d * r ** j for j, d in enumerate(signed))
+        return self.from_int(-value if e else value)
 
     def paper_negacyclic_columns(self, x, y) -> list:
         """u_m = sum_{i+j=m} x_i y_j - sum_{i+j=k+m} x_i y_j, 0 <= m < k:
