@@ -14,8 +14,9 @@ Extra objects:
                 32-bit VALU peak (256 CU x 64 lanes x 2.4 GHz).
   hbm           the whole transform against the HBM roofline: algorithmic
                 bytes (read + write the vector once) / transform time.
-  cpu_baseline  the CPU oracle (radix-2 NTT on Python integers) timed on a
-                bounded sample of the same workload on this host.
+  cpu_baseline  the CPU oracle (multithreaded C++ radix-2 transform with
+                schoolbook multiprecision arithmetic) timed on this host on
+                the full workloads, median of 3.
 """
 
 from __future__ import annotations
@@ -78,33 +79,81 @@ def traffic_from_profiles(kernel_key: str):
     return ent.get("bytes_per_launch") if ent else None
 
 
-def cpu_baseline(sample_log2: int):
-    """The oracle's radix-2 NTT (Python integers, one thread) on a 2^sample
-    prefix-sized instance of the workload, scaled to N = 2^20 by N log2 N."""
+def cpu_baseline(reps: int = 3):
+    """The CPU oracle timed on this host: the multithreaded C++ radix-2
+    transform of oracle/cpu_ntt.cpp (schoolbook multiprecision Montgomery
+    arithmetic mod p, std::thread over the host's CPUs, twiddle powers and
+    digit conversions included in every call), median of `reps` runs, on the
+    full workloads: transform size 4096 product of two degree < 2048 factors
+    (k = 8); forward and inverse transforms of 2^20 coefficients and the
+    product of two degree < 2^19 factors (k = 8); the same product over the
+    k = 16 prime.  Also the Python definitional oracle (schoolbook product,
+    one thread) on the degree < 2048 product, for context.  value = the k = 8
+    forward transform rate, the headline workload."""
+    import statistics
+
     import gfp_inputs as gi
+    from oracle import cpu_ntt
     from oracle import transform as T
     from oracle.field import GFPField
 
-    F = GFPField(K_DIG, R)
-    n = 2 ** sample_log2
-    x = gi.uniform_digits(K_DIG, R, n, gi.BASE_SEED + 1, 0)
-    obj = x.astype(object)
-    vals = obj[K_DIG - 1].copy()
-    for d in range(K_DIG - 2, -1, -1):
-        vals = vals * R + obj[d]
-    vals = [int(v) for v in vals]
-    w = F.paper_root_of_unity(n)
+    threads = cpu_ntt.default_threads()
+    cpu_ntt.build()
+
+    def med(fn):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts), ts
+
+    out = {}
+    F8, F16 = GFPField(K_DIG, R), GFPField(16, R16)
+    N = 2 ** LOG2N
+    # headline: k = 8 forward and inverse transforms of 2^20 coefficients
+    x = gi.uniform_digits(K_DIG, R, N, gi.BASE_SEED + 1, 0)
+    w = F8.paper_root_of_unity(N)
+    wi = pow(w, F8.p - 2, F8.p)
+    t_fwd, ts_fwd = med(lambda: cpu_ntt.transform(K_DIG, R, x, w, threads=threads))
+    t_inv, _ = med(lambda: cpu_ntt.transform(K_DIG, R, x, wi, inverse=True, threads=threads))
+    out["k8_forward_2^20_s"] = round(t_fwd, 4)
+    out["k8_forward_2^20_runs_s"] = [round(v, 4) for v in ts_fwd]
+    out["k8_inverse_2^20_s"] = round(t_inv, 4)
+    # products of two degree < 2^19 factors (transform size 2^20), k = 8 and 16
+    for name, F, seed in (("k8", F8, gi.BASE_SEED + 1), ("k16", F16, gi.BASE_SEED + 2)):
+        a = gi.uniform_digits(F.k, F.r, N // 2, seed, 0)
+        b = gi.uniform_digits(F.k, F.r, N // 2, seed, 1)
+        wf = F.paper_root_of_unity(N)
+        wfi = pow(wf, F.p - 2, F.p)
+        t, _ = med(lambda: cpu_ntt.polymul(F.k, F.r, a, b, N, wf, wfi, threads=threads))
+        out["%s_polymul_2^19x2^19_s" % name] = round(t, 4)
+    # transform size 4096 product, k = 8
+    a = gi.uniform_digits(K_DIG, R, 2048, gi.BASE_SEED + 0, 0)
+    b = gi.uniform_digits(K_DIG, R, 2048, gi.BASE_SEED + 0, 1)
+    w12 = F8.paper_root_of_unity(4096)
+    t, _ = med(lambda: cpu_ntt.polymul(K_DIG, R, a, b, 4096, w12, pow(w12, F8.p - 2, F8.p), threads=threads))
+    out["k8_polymul_2048x2048_s"] = round(t, 5)
+    # Python definitional oracle (schoolbook, one thread), same product
+    def ints(v):
+        obj = v.astype(object)
+        acc = obj[K_DIG - 1].copy()
+        for d in range(K_DIG - 2, -1, -1):
+            acc = acc * R + obj[d]
+        return [int(t_) for t_ in acc]
+    ai, bi = ints(a), ints(b)
     t0 = time.perf_counter()
-    T.ntt(vals, w, F.p)
-    dt = time.perf_counter() - t0
-    full = dt * (2 ** LOG2N * LOG2N) / (n * sample_log2)
+    T.polymul(ai, bi, F8.p)
+    out["python_schoolbook_2048x2048_s"] = round(time.perf_counter() - t0, 3)
     return {
-        "value": round(2 ** LOG2N / full, 1),
+        "value": round(N / t_fwd, 1),
         "unit": "coeffs/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": "oracle radix-2 NTT (Python integers, 1 thread) of 2^%d uniform coefficients over the same prime, "
-                  "%.2f s; scaled to N = 2^20 by the N log2 N butterfly count" % (sample_log2, dt),
+        "sample": "C++ oracle (oracle/cpu_ntt.cpp: radix-2 transform, schoolbook Montgomery arithmetic mod p, "
+                  "%d threads) on the full workloads, median of %d runs each; value = the k = 8 forward "
+                  "transform of 2^20 coefficients (%.3f s)" % (threads, reps, t_fwd),
+        "workloads": out,
         "cpu_model": _cpu_model(),
         "host_cpus": os.cpu_count(),
     }
@@ -459,8 +508,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=300,
                     help="untimed steps first; the first call also builds the twiddle tables on the host, and the "
                          "GPU clock needs tens of ms of work to come back up after that idle time")
+    ap.add_argument("--warmup-s", type=float, default=0.5,
+                    help="keep warming up until this many seconds of transforms have run")
     ap.add_argument("--pass-reps", type=int, default=50)
-    ap.add_argument("--cpu-sample-log2", type=int, default=19)
+    ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=3)
@@ -505,9 +556,18 @@ def main():
     # scales the counters of the FFT kernels to bytes
     y.copy_(x)
     torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        f.fft_forward(x, y=y, workspace=ws)
+    # warm-up: the requested steps, then more until the GPU has been busy for
+    # at least --warmup-s seconds (the first call builds the twiddle tables on
+    # the host while the GPU idles, and the clock needs tens of ms of work to
+    # come back up), so that a short --warmup still times the steady state
+    f.fft_forward(x, y=y, workspace=ws)
     torch.cuda.synchronize()
+    warm_steps, tw0 = 1, time.perf_counter()
+    while warm_steps < args.warmup or time.perf_counter() - tw0 < args.warmup_s:
+        for _ in range(20):
+            f.fft_forward(x, y=y, workspace=ws)
+        warm_steps += 20
+        torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_wall0 = time.perf_counter()
     ev0.record(stream)
@@ -568,6 +628,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_steps_run": warm_steps,
         "ms_per_step": round(ms, 5),
         "higher_is_better": True,
         "scaling": "weak",
@@ -616,7 +677,7 @@ def main():
     if not args.no_element:
         out["element_products"] = element_leg(torch, dev, 1 << args.element_log2, 20)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_reps)
     print(json.dumps(out), flush=True)
 
 

@@ -8,6 +8,9 @@ Plain definitions first:
                Convolution (section 3.3), (1/n) DFT at w^-1.
 * ``polymul``  c_m = sum_{i+j=m} a_i b_j mod p (schoolbook).
 * ``horner``   f(z) mod p.
+* ``poly_eval`` the same value as a sum of blocks of B coefficients,
+               f(z) = sum_b (z^B)^b sum_{i<B} c_{bB+i} z^i, one reduction
+               per block (faster for long vectors; pinned against horner).
 
 Then, for sizes where the O(N^2) definition is too slow:
 
@@ -112,6 +115,25 @@ def horner(coeffs, z: int, p: int) -> int:
     acc = 0
     for c in reversed(coeffs):
         acc = (acc * z + c) % p
+    return acc
+
+
+def poly_eval(coeffs, z: int, p: int, block: int = 1024) -> int:
+    """f(z) mod p for f = sum_i c_i z^i, by blocks: the powers z^0 .. z^(B-1)
+    are formed once, each block of B coefficients is a plain sum of products
+    (reduced once), and the blocks are combined from the top with z^B."""
+    n = len(coeffs)
+    if n == 0:
+        return 0
+    width = min(block, n)
+    powers = [1] * width
+    for i in range(1, width):
+        powers[i] = powers[i - 1] * z % p
+    z_block = powers[-1] * z % p
+    acc = 0
+    for start in range(((n - 1) // block) * block, -1, -block):
+        part = sum(c * w for c, w in zip(coeffs[start:start + block], powers))
+        acc = (acc * z_block + part) % p
     return acc
 
 

@@ -134,26 +134,43 @@ def test_round_trip_mid(torch_mod, name, N):
     assert np.array_equal(back, x)
 
 
-@pytest.mark.parametrize("name,N", [("k8", 2 ** 20), ("k16", 2 ** 20), ("k8", 2 ** 19), ("k32", 2 ** 18)])
+def _golden(kind, key):
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sampled_fullsize.json")
+    with open(path) as fh:
+        return json.load(fh)[kind][key]
+
+
+@pytest.mark.parametrize("name,N", [("k8", 2 ** 20), ("k16", 2 ** 20), ("k8", 2 ** 19), ("k32", 2 ** 18),
+                                    ("k64", 2 ** 20)])
 def test_full_size_sampled(torch_mod, name, N):
-    """N = 2^20 (16^5 for k = 8, 32^4 for k = 16), 2^19 = 8 16^4 and, for
-    k = 32, the largest size of the paper's FFT table, 64^3 = 2^18: sampled
-    outputs by Horner, round trip exact."""
+    """N = 2^20 (16^5 for k = 8, 32^4 for k = 16, 64 128^2 for k = 64),
+    2^19 = 8 16^4 and, for k = 32, the largest size of the paper's FFT
+    table, 64^3 = 2^18: 32 seeded outputs plus Y_0, Y_1, Y_(N/2), Y_(N-1)
+    against Y_i = X(w^i) (expected values written by the oracle into
+    tests/golden/sampled_fullsize.json from the same seeded input), Y_0 and
+    Y_(N/2) also against exact digit sums, round trip exact."""
     from paper_1811_01490_amd import to_device, to_host
 
     F, f = _field(name)
-    seed = gi.BASE_SEED + {"k8": 1, "k16": 2, "k32": 3}[name]
-    x = gi.operand(F.k, F.r, N, seed, 0, edge_frac=0.001)
+    g = _golden("fft", "%s-%d" % (name, N))
+    assert (g["k"], g["r"], g["n"]) == (F.k, F.r, N)
+    x = gi.operand(F.k, F.r, N, g["seed"], g["stream"], edge_frac=g["edge_frac"])
     dx = to_device(x)
     y = f.fft_forward(dx)
     yh = to_host(y)
     assert canonical_mask(yh, F.r).all()
-    xi = to_ints(x, F.r)
-    w = F.paper_root_of_unity(N)
-    idx = gi.sample_indices(N, 12, seed, 0, must=(0, 1, N // 2, N - 1))
+    idx = g["indices"]
+    assert len(idx) >= 36 and {0, 1, N // 2, N - 1} <= set(idx)
     yv = to_ints(yh[:, idx], F.r)
-    for i, got in zip(idx, yv):
-        assert got == T.horner(xi, pow(w, i, F.p), F.p), i
+    for i, got, want in zip(idx, yv, g["values"]):
+        assert got == int(want, 16), i
+    ev, od = _digit_sums(x, slice(0, N, 2)), _digit_sums(x, slice(1, N, 2))
+    tot = sum((e + o) * F.r ** d for d, (e, o) in enumerate(zip(ev, od))) % F.p
+    alt = sum((e - o) * F.r ** d for d, (e, o) in enumerate(zip(ev, od))) % F.p
+    assert to_ints(yh[:, [0, N // 2]], F.r) == [tot, alt]
     back = to_host(f.fft_inverse(y))
     assert np.array_equal(back, x)
 

@@ -197,3 +197,21 @@ def test_horner_matches_power_sum():
     coeffs = [g.randrange(p) for _ in range(20)]
     z = g.randrange(p)
     assert T.horner(coeffs, z, p) == sum(c * pow(z, i, p) for i, c in enumerate(coeffs)) % p
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 8, 9, 63, 64, 65, 200])
+def test_poly_eval_matches_horner_and_power_sum(n):
+    """Blocked evaluation (block 8 here, so the lengths cross block
+    boundaries) equals Horner and the power sum, for random coefficients on
+    the k = 8 workload prime, and for coefficients of every size class."""
+    import random
+
+    F = GFPField(**P8)
+    p = F.p
+    g = random.Random(n)
+    coeffs = [g.randrange(p) for _ in range(n)]
+    for z in (0, 1, p - 1, g.randrange(p)):
+        want = sum(c * pow(z, i, p) for i, c in enumerate(coeffs)) % p
+        assert T.poly_eval(coeffs, z, p, block=8) == want
+        assert T.poly_eval(coeffs, z, p) == want
+        assert T.horner(coeffs, z, p) == want
