@@ -54,6 +54,7 @@ extern "C" {
 #define GFP_ENOTPRIME 6    /* r^k + 1 failed the probable-prime test */
 #define GFP_ECANCELED 7    /* request loop: request cancelled at shutdown */
 #define GFP_EPENDING 8     /* request loop: result not ready yet */
+#define GFP_ENOTREADY 9    /* gfp_fft_noalloc: the size's twiddle tables are not on the device yet */
 
 /* Elementwise operations (gfp_elementwise). */
 #define GFP_OP_ADD 0       /* z = x + y */
@@ -362,6 +363,34 @@ int gfp_server_get_stats(gfp_server* s, gfp_server_stats* out);
  * admitted ones run to completion; then the threads, streams and workspace
  * are released and every ticket becomes invalid.  NULL is accepted. */
 int gfp_server_destroy(gfp_server* s);
+
+/* ---- Transforms that allocate nothing ----------------------------------------
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * gfp_fft_noalloc is gfp_fft_forward (inverse == 0) or gfp_fft_inverse
+ * (inverse != 0) with the same arguments and bit-identical results, except
+ * that the workspace is not an argument: the two work vectors come from a
+ * static device array of GFP_STATIC_SCRATCH_BYTES bytes that the library
+ * holds on every device it runs on until the process ends.  The call makes
+ * no device allocation and frees nothing.
+ *   - Size limit: 2 n k 8 <= GFP_STATIC_SCRATCH_BYTES, i.e. n <= 2^18 for
+ *     k = 8, 2^17 for k = 16, 2^16 for k = 32, 2^15 for k = 64; larger n
+ *     returns GFP_EINVAL before any work is enqueued.
+ *   - The twiddle tables of size n must already be on the current device
+ *     (built by any earlier gfp_fft_forward, gfp_fft_inverse, gfp_polymul or
+ *     gfp_tune of that size there); otherwise GFP_ENOTREADY.
+ *   - Every call on one device uses that device's single array, and the
+ *     array keeps the last call's contents (it needs no clearing: a call
+ *     reads only words it wrote first).  Calls that overlap in time on one
+ *     device -- two streams, or two host threads -- race on it and give wrong
+ *     results; run them on one stream.
+ *   - The first call on a device resolves the array's device address
+ *     (hipGetSymbolAddress; no allocation).
+ * Other errors as gfp_fft_forward. */
+#define GFP_STATIC_SCRATCH_BYTES (32ull << 20)
+int gfp_fft_noalloc(const gfp_field* f, uint64_t n, int inverse, const uint64_t* x, uint64_t ld_x, uint64_t* y,
+                    uint64_t ld_y, void* stream);
 
 /* Input validation (the library assumes canonical inputs and does not check
  * them on the hot path).  Counts the elements of the digit-major vector x

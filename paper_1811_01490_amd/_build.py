@@ -24,7 +24,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = ["gfp_shape_8_63_34.hip", "gfp_shape_8_59_16.hip", "gfp_shape_16_62_36.hip", "gfp_shape_16_58_10.hip",
            "gfp_shape_32_62_56.hip", "gfp_shape_32_56_21.hip", "gfp_shape_64_63_m40.hip",
-           "gfp_copy.hip", "gfp_bigint.hip", "gfp_dispatch.cpp", "gfp_host.cpp", "gfp_server.cpp"]
+           "gfp_copy.hip", "gfp_bigint.hip", "gfp_static.hip", "gfp_dispatch.cpp", "gfp_host.cpp", "gfp_server.cpp"]
 
 
 def _compile(src: str) -> str:

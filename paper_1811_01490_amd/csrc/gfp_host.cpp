@@ -225,7 +225,9 @@ int check_size(const gfp_field* f, uint64_t n, int* log2n, int* e) {
 // Tables are built and uploaded without the field lock held, so other
 // threads keep launching meanwhile; two threads that build the same tables
 // at once keep the first and free the second.
-int get_tables(gfp_field* f, uint64_t n, const DevTables** out) {
+// build == false: only look the tables up (GFP_ENOTREADY when they are not
+// on the device yet), never allocate.
+int get_tables(gfp_field* f, uint64_t n, const DevTables** out, bool build = true) {
   int dev = 0;
   hipError_t he = hipGetDevice(&dev);
   if (he != hipSuccess) return hip_status(he);
@@ -238,6 +240,7 @@ int get_tables(gfp_field* f, uint64_t n, const DevTables** out) {
       return GFP_OK;
     }
   }
+  if (!build) return GFP_ENOTREADY;
   const uint64_t cnt = n / (2ull * f->k);
   DevTables t;
   std::vector<uint32_t> host;
@@ -550,11 +553,11 @@ int view_layout(const VecView& X, const VecView& Y) {
 // in the first launch (X2 has X's strides, element-major)
 int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& plan, bool inverse, VecView X,
                        VecView Y, uint64_t nvec, bool canonical, uint64_t* W1, uint64_t* W2, hipStream_t st,
-                       const uint64_t* X2 = nullptr) {
+                       const uint64_t* X2 = nullptr, bool build_tables = true) {
   const uint64_t n = 1ull << log2n;
   const uint64_t k = f->k;
   const DevTables* t = nullptr;
-  int rc = get_tables(f, n, &t);
+  int rc = get_tables(f, n, &t, build_tables);
   if (rc != GFP_OK) return rc;
   if (!plan_valid(f, log2n, e, plan)) return GFP_EINVAL;
   const int lk = log2_exact(2ull * f->k);
@@ -624,8 +627,10 @@ int run_transform(gfp_field* f, int log2n, int e, bool inverse, VecView X, VecVi
                             canonical, W1, W2, st, X2);
 }
 
+// no_alloc: ws is the static scratch (gfp_fft_noalloc); the tables must
+// already exist, and nothing is allocated.
 int transform_entry(const gfp_field* cf, uint64_t n, const uint64_t* x, uint64_t ldx, uint64_t* y, uint64_t ldy,
-                    void* ws, uint64_t ws_bytes, void* stream, bool inverse) {
+                    void* ws, uint64_t ws_bytes, void* stream, bool inverse, bool no_alloc = false) {
   gfp_field* f = const_cast<gfp_field*>(cf);
   if (!f || !x || !y) return GFP_EINVAL;
   if (!f->gpu_shape) return GFP_EUNSUPPORTED;
@@ -635,20 +640,22 @@ int transform_entry(const gfp_field* cf, uint64_t n, const uint64_t* x, uint64_t
   if (ldx < n || ldy < n) return GFP_EINVAL;
   if (x == y && ldx != ldy) return GFP_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  const uint64_t need = 2ull * n * f->k * 8;
+  if (no_alloc && (!ws || ws_bytes < need)) return GFP_EINVAL;
   Scratch s;
   uint64_t* w = nullptr;
-  rc = get_workspace(ws, ws_bytes, 2ull * n * f->k * 8, st, s, &w);
+  rc = get_workspace(ws, ws_bytes, need, st, s, &w);
   if (rc != GFP_OK) return rc;
   VecView X{x, 1, ldx, 0}, Y{y, 1, ldy, 0};
   const std::vector<int> plan = plan_for(f, log2n, e, 1, GFP_LAYOUT_DIGIT_MAJOR);
   if (launch_count(f, log2n, e, plan) == 1 && x == y) {
     // one launch cannot run in place: transform into W2 (digit-major, ld n), copy back
     VecView T{w + n * f->k, 1, n, 0};
-    rc = run_transform_plan(f, log2n, e, plan, inverse, X, T, 1, true, w, w, st);
+    rc = run_transform_plan(f, log2n, e, plan, inverse, X, T, 1, true, w, w, st, nullptr, !no_alloc);
     if (rc != GFP_OK) return rc;
     return hip_status(hipMemcpy2DAsync(y, ldy * 8, T.p, n * 8, n * 8, f->k, hipMemcpyDeviceToDevice, st));
   }
-  return run_transform_plan(f, log2n, e, plan, inverse, X, Y, 1, true, w, w + n * f->k, st);
+  return run_transform_plan(f, log2n, e, plan, inverse, X, Y, 1, true, w, w + n * f->k, st, nullptr, !no_alloc);
 }
 
 // ---------------------------------------------------------------------------
@@ -818,6 +825,11 @@ namespace gfpk {
 int prepare_tables(const gfp_field* f, uint64_t n) {
   const DevTables* t = nullptr;
   return get_tables(const_cast<gfp_field*>(f), n, &t);
+}
+
+int transform_noalloc(const gfp_field* f, uint64_t n, int inverse, const uint64_t* x, uint64_t ldx, uint64_t* y,
+                      uint64_t ldy, void* scratch, uint64_t scratch_bytes, void* stream) {
+  return transform_entry(f, n, x, ldx, y, ldy, scratch, scratch_bytes, stream, inverse != 0, true);
 }
 }  // namespace gfpk
 
@@ -1434,6 +1446,7 @@ const char* gfp_strerror(int code) {
     case GFP_ENOTPRIME: return "r^k + 1 is not a probable prime";
     case GFP_ECANCELED: return "request cancelled";
     case GFP_EPENDING: return "result not ready";
+    case GFP_ENOTREADY: return "twiddle tables of this size not on the device yet";
     default: return "unknown error";
   }
 }

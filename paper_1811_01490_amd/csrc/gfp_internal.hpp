@@ -111,4 +111,11 @@ inline int tw_words(int k) { return (6 * k + 6) & ~3; }
 // n on the current device; a status code of gfp.h.
 int prepare_tables(const gfp_field* f, uint64_t n);
 
+// gfp_fft_forward / gfp_fft_inverse of size n with the two work vectors in
+// `scratch` (scratch_bytes >= 2 n k 8, else GFP_EINVAL), taking the tables
+// only if they are already on the device (else GFP_ENOTREADY): allocates
+// nothing on the device.
+int transform_noalloc(const gfp_field* f, uint64_t n, int inverse, const uint64_t* x, uint64_t ldx, uint64_t* y,
+                      uint64_t ldy, void* scratch, uint64_t scratch_bytes, void* stream);
+
 }  // namespace gfpk

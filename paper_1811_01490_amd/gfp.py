@@ -27,6 +27,8 @@ GFP_EDEVICE = 5
 GFP_ENOTPRIME = 6
 GFP_ECANCELED = 7
 GFP_EPENDING = 8
+GFP_ENOTREADY = 9
+STATIC_SCRATCH_BYTES = 32 << 20
 
 OP_ADD, OP_SUB, OP_MUL, OP_MUL_POW_R, OP_MUL_CONST, OP_MUL_SCALE, OP_MUL_NTT = range(7)
 BATCH_GRAPH = 1
@@ -90,6 +92,7 @@ SIGNATURES = {
     "gfp_fft_workspace_size": (_int, [_vp, _u64, ctypes.POINTER(_u64)]),
     "gfp_fft_forward": (_int, [_vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp]),
     "gfp_fft_inverse": (_int, [_vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp]),
+    "gfp_fft_noalloc": (_int, [_vp, _u64, _int, _vp, _u64, _vp, _u64, _vp]),
     "gfp_fft_pass": (_int, [_vp, _u64, _int, _int, _int, _vp, _u64, _vp, _u64, _vp]),
     "gfp_polymul_size": (_int, [_vp, _u64, _u64, ctypes.POINTER(_u64)]),
     "gfp_polymul_workspace_size": (_int, [_vp, _u64, _u64, ctypes.POINTER(_u64)]),
@@ -225,6 +228,18 @@ class Field:
     def fft_inverse(self, x, n=None, y=None, workspace=None, stream=None):
         n = x.shape[1] if n is None else n
         return self._transform(lib().gfp_fft_inverse, "gfp_fft_inverse", x, n, y, workspace, stream)
+
+    def fft_noalloc(self, x, n=None, y=None, inverse=False, stream=None):
+        """gfp_fft_noalloc: the transform with the library's static scratch
+        (no device allocation inside the call); y must be given by callers
+        that cannot allocate."""
+        n = x.shape[1] if n is None else n
+        px, ldx = _vec(x, self.k, n, "x")
+        if y is None:
+            y = torch.empty((self.k, n), dtype=x.dtype, device=x.device)
+        py, ldy = _vec(y, self.k, n, "y")
+        _check(lib().gfp_fft_noalloc(self._h, n, int(inverse), px, ldx, py, ldy, _stream(stream)), "gfp_fft_noalloc")
+        return y
 
     def fft_pass(self, s, x, y, n, inverse=False, in_element_major=False, out_element_major=False, stream=None,
                  code="1"):
