@@ -137,8 +137,8 @@ int gfp_fft_inverse(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t 
  * bits (0 = both digit-major).  gfp_fft_forward runs stage 0 digit-major to
  * element-major, the middle stages element-major, the last stage
  * element-major to digit-major.  With GFP_PASS_PAIR or GFP_PASS_WIDE the
- * launch runs radix-K stages s and s+1 (s + 1 < S, k = 8; for WIDE also
- * n / (K^2 Ns) >= 8), exactly as that character of a plan does.  For
+ * launch runs radix-K stages s and s+1 (s + 1 < S; PAIR: k = 8 or 16; WIDE:
+ * k = 8 and n / (K^2 Ns) >= 8), exactly as that character of a plan does.  For
  * instrumentation and custom schedules. */
 int gfp_fft_pass(const gfp_field* f, uint64_t n, int s, int inverse, int flags, const uint64_t* x, uint64_t ld_x,
                  uint64_t* y, uint64_t ld_y, void* stream);
@@ -229,14 +229,14 @@ int gfp_bigint_mul(const gfp_field* f, const uint64_t* a, uint64_t na, const uin
  *
  * A transform of size n = R K^e runs as a sequence of launches: the radix-R
  * pass alone (when R > 1), then the e radix-K passes, each launch covering
- * one radix-K pass or (k = 8) two consecutive passes fused in one launch,
+ * one radix-K pass or (k = 8, 16) two consecutive passes fused in one launch,
  * with the stride permutation between them (section 4.1, eq. sixstepfft)
  * staged through LDS so the intermediate never goes to HBM.  A plan is a
  * string with one character per launch: '1' one pass, '2' two fused passes
- * (two K^2-element blocks per workgroup; the second pass reads its twiddles
- * per element group), 'w' two fused passes over eight blocks per workgroup
- * (wavefront-uniform twiddles in both passes; needs n / (K^2 R K^s) >= 8 at
- * its first radix-K pass s).  The plan covers the radix-K passes only.
+ * (K^2-element blocks, two per workgroup for k = 8, one for k = 16; the
+ * second pass reads its twiddles per element group), 'w' (k = 8) two fused
+ * passes over eight blocks per workgroup (wavefront-uniform twiddles in both
+ * passes; needs n / (K^2 R K^s) >= 8 at its first radix-K pass s).  The plan covers the radix-K passes only.
  * Example: "1211" for e = 5.  Plans are kept per
  * (n, batch class, layout): the batch class is the number of same-size
  * transforms one launch covers (1, 2-7, 8-63, 64 and more: gfp_polymul runs

@@ -850,6 +850,75 @@ __device__ __forceinline__ L96 mul_entry(uint64_t x, const uint32_t* __restrict_
   }
 }
 
+// ------------------------------------------------------------------------
+// Per-group twiddles staged through LDS (k <= 16)
+// ------------------------------------------------------------------------
+// Where the groups of a wavefront take different twiddles (the last pass,
+// the second pass of a fused pair), the product needs the whole entry of
+// its group's twiddle in each of the group's k lanes.  Instead of every lane
+// fetching the whole entry from memory (k times the bytes through the vector
+// memory unit), lane m loads only digit m from a table of raw digits (one
+// 8k-byte segment per group), splits it into limbs, forms the suffix sum
+// sum_{t >= m} y_t by a scan across the element's lanes and writes both into
+// its group's entry of a small LDS area in the twiddle-entry layout; the
+// product then reads the entry from LDS (the group's lanes read the same
+// words).  LDS operations of one wavefront take effect in issue order, so a
+// group's own lanes see the entry right after the writes; the fences keep the
+// compiler from moving the LDS accesses of consecutive slots across each
+// other.
+
+// Value of the lane holding digit m + D of the same element, 0 past digit
+// k - 1 (a DPP row shift with zero fill; k <= 16).
+template <int KD, int D>
+__device__ __forceinline__ uint32_t dig_up(uint32_t v) {
+  static_assert(Geo<KD>::ROW, "elements inside one DPP row");
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + D * Geo<KD>::GPL, 0xF, 0xF, true);
+}
+
+// Words of the LDS staging area of one wavefront: one entry per group.
+template <int KD>
+struct StageGeo {
+  static constexpr int WORDS = TwLayout<KD>::WORDS;
+  static constexpr int PER_WAVE = Geo<KD>::G * WORDS;
+};
+
+// Once per kernel: suffix(k) = 0 in the group's entry (never written again).
+template <int KD>
+__device__ __forceinline__ void stage_init(uint32_t* __restrict__ e, int m) {
+  if (m == KD - 1) {
+    uint32_t* z = e + TwLayout<KD>::SUF + 3 * KD;
+    z[0] = 0u;
+    z[1] = 0u;
+    z[2] = 0u;
+  }
+}
+
+// Lane m holds y = digit m of its group's twiddle; writes the group's entry e.
+template <int KD>
+__device__ __forceinline__ void stage_entry(uint64_t y, uint32_t* __restrict__ e, int m) {
+  uint32_t l0, l1, l2;
+  split22(y, l0, l1, l2);
+  // inclusive suffix sum sum_{t >= m} y_t (< 2^68) by doubling steps
+  uint32_t s0 = (uint32_t)y, s1 = (uint32_t)(y >> 32), s2 = 0u;
+  static_for<ilog2(KD)>([&](auto I) {
+    constexpr int d = 1 << decltype(I)::value;
+    const uint32_t n0 = dig_up<KD, d>(s0), n1 = dig_up<KD, d>(s1), n2 = dig_up<KD, d>(s2);
+    unsigned c;
+    s0 = __builtin_addc(s0, n0, 0u, &c);
+    s1 = __builtin_addc(s1, n1, c, &c);
+    s2 = s2 + n2 + c;
+  });
+  slot_fence();
+  e[3 * m] = l0;
+  e[3 * m + 1] = l1;
+  e[3 * m + 2] = l2;
+  uint32_t* suf = e + TwLayout<KD>::SUF + 3 * m;
+  suf[0] = s0;
+  suf[1] = s1;
+  suf[2] = s2;
+  slot_fence();
+}
+
 // x * y for two data elements: every lane of the element loads all of y's
 // digits (same addresses across the element's lanes) and derives the limbs
 // and its correction sum (rot = 0: S_m = sum_{t > m} y_t).

@@ -29,7 +29,8 @@ bool shape_supported(int k, int w, int u) {
   return false;
 }
 
-bool span2_supported(int k) { return k == 8; }
+bool span2_supported(int k) { return k == 8 || k == 16; }
+bool wide_supported(int k) { return k == 8; }
 
 hipError_t launch_pass(int k, int w, int u, const PassArgs& p, hipStream_t st) {
 #define GFP_SHAPE_CASE(K, W, U, TAG) \

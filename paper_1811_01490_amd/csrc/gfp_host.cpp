@@ -39,7 +39,27 @@ struct DevTables {
   // first launch
   uint32_t* inv_s = nullptr;
   uint32_t* inv2_s = nullptr;
+  // k <= 16: fwd, inv, fwd2, inv2 again as raw digits (k u64 per entry),
+  // the form the per-group twiddle passes stage through LDS
+  uint64_t* fwd_raw = nullptr;
+  uint64_t* inv_raw = nullptr;
+  uint64_t* fwd2_raw = nullptr;
+  uint64_t* inv2_raw = nullptr;
 };
+
+void free_tables(DevTables& t) {
+  (void)hipFree(t.fwd);
+  (void)hipFree(t.inv);
+  (void)hipFree(t.fwd2);
+  (void)hipFree(t.inv2);
+  (void)hipFree(t.ninv);
+  (void)hipFree(t.inv_s);
+  (void)hipFree(t.inv2_s);
+  (void)hipFree(t.fwd_raw);
+  (void)hipFree(t.inv_raw);
+  (void)hipFree(t.fwd2_raw);
+  (void)hipFree(t.inv2_raw);
+}
 
 // Whether the inverse of size 2^log2n takes its 1/n from the scaled tables
 // (see DevTables) rather than in its first launch.
@@ -166,10 +186,12 @@ Big root_mont(const gfp_field* f, uint64_t n, bool inverse) {
 // host table of w^(sign j), j < cnt, in entry layout
 // Entries scale w^j, j < cnt (wm = w and sm = scale in Montgomery form;
 // sm == nullptr: scale 1).
+// raw != nullptr: also the raw digits, k u64 per entry.
 void build_table(const gfp_field* f, const Big& wm, uint64_t cnt, std::vector<uint32_t>& out,
-                 const Big* sm = nullptr) {
+                 const Big* sm = nullptr, std::vector<uint64_t>* raw = nullptr) {
   const int words = gfpk::tw_words((int)f->k);
   out.assign(cnt * words, 0);
+  if (raw) raw->assign(cnt * f->k, 0);
   unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   if (cnt < 4096) nth = 1;
   const uint64_t chunk = (cnt + nth - 1) / nth;
@@ -185,6 +207,7 @@ void build_table(const gfp_field* f, const Big& wm, uint64_t cnt, std::vector<ui
       for (uint64_t j = lo; j < hi; ++j) {
         to_digits(f, M.from(acc), dg.data());
         make_entry(f->k, dg.data(), &out[j * words]);
+        if (raw) std::copy(dg.begin(), dg.end(), raw->begin() + j * f->k);
         acc = M.mmul(acc, wm);
       }
     });
@@ -194,18 +217,19 @@ void build_table(const gfp_field* f, const Big& wm, uint64_t cnt, std::vector<ui
 
 int hip_status(hipError_t e) { return e == hipSuccess ? GFP_OK : (e == hipErrorOutOfMemory ? GFP_ENOMEM : GFP_EDEVICE); }
 
-int upload(const std::vector<uint32_t>& host, uint32_t** dev) {
+template <class T>
+int upload(const std::vector<T>& host, T** dev) {
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, host.size() * sizeof(uint32_t));
+  hipError_t e = hipMalloc(&p, host.size() * sizeof(T));
   if (e != hipSuccess) return hip_status(e);
   // on the per-thread stream: no implicit wait for work on other streams
-  e = hipMemcpyAsync(p, host.data(), host.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hipStreamPerThread);
+  e = hipMemcpyAsync(p, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice, hipStreamPerThread);
   if (e == hipSuccess) e = hipStreamSynchronize(hipStreamPerThread);
   if (e != hipSuccess) {
     (void)hipFree(p);
     return hip_status(e);
   }
-  *dev = (uint32_t*)p;
+  *dev = (T*)p;
   return GFP_OK;
 }
 
@@ -244,21 +268,27 @@ int get_tables(gfp_field* f, uint64_t n, const DevTables** out, bool build = tru
   const uint64_t cnt = n / (2ull * f->k);
   DevTables t;
   std::vector<uint32_t> host;
+  std::vector<uint64_t> raw;
+  std::vector<uint64_t>* rawp = f->k <= 16 ? &raw : nullptr;
   const Mont& M = *f->mont;
   const Big ninv_m = M.pow(M.to(Big(n)), gfp::sub(f->p, Big(2)));  // 1/n, Montgomery form
-  build_table(f, root_mont(f, n, false), cnt, host);
+  build_table(f, root_mont(f, n, false), cnt, host, nullptr, rawp);
   int rc = upload(host, &t.fwd);
+  if (rc == GFP_OK && rawp) rc = upload(raw, &t.fwd_raw);
   if (rc == GFP_OK) {
-    build_table(f, root_mont(f, n, true), cnt, host);
+    build_table(f, root_mont(f, n, true), cnt, host, nullptr, rawp);
     rc = upload(host, &t.inv);
+    if (rc == GFP_OK && rawp) rc = upload(raw, &t.inv_raw);
   }
   // w^K = w_{n/K} (the roots are nested): twiddles of the passes before the last
   if (rc == GFP_OK && n >= 4ull * f->k * f->k) {
-    build_table(f, root_mont(f, n / (2ull * f->k), false), cnt, host);
+    build_table(f, root_mont(f, n / (2ull * f->k), false), cnt, host, nullptr, rawp);
     rc = upload(host, &t.fwd2);
+    if (rc == GFP_OK && rawp) rc = upload(raw, &t.fwd2_raw);
     if (rc == GFP_OK) {
-      build_table(f, root_mont(f, n / (2ull * f->k), true), cnt, host);
+      build_table(f, root_mont(f, n / (2ull * f->k), true), cnt, host, nullptr, rawp);
       rc = upload(host, &t.inv2);
+      if (rc == GFP_OK && rawp) rc = upload(raw, &t.inv2_raw);
     }
   }
   if (rc == GFP_OK && scale_in_tables(f, log2_exact(n))) {
@@ -279,26 +309,12 @@ int get_tables(gfp_field* f, uint64_t n, const DevTables** out, bool build = tru
     rc = upload(host, &t.ninv);
   }
   if (rc != GFP_OK) {
-    (void)hipFree(t.fwd);
-    (void)hipFree(t.inv);
-    (void)hipFree(t.fwd2);
-    (void)hipFree(t.inv2);
-    (void)hipFree(t.ninv);
-    (void)hipFree(t.inv_s);
-    (void)hipFree(t.inv2_s);
+    free_tables(t);
     return rc;
   }
   std::lock_guard<std::mutex> g(f->mu);
   auto ins = f->tables.emplace(key, t);
-  if (!ins.second) {
-    (void)hipFree(t.fwd);
-    (void)hipFree(t.inv);
-    (void)hipFree(t.fwd2);
-    (void)hipFree(t.inv2);
-    (void)hipFree(t.ninv);
-    (void)hipFree(t.inv_s);
-    (void)hipFree(t.inv2_s);
-  }
+  if (!ins.second) free_tables(t);
   *out = &ins.first->second;
   return GFP_OK;
 }
@@ -498,6 +514,7 @@ bool plan_valid(const gfp_field* f, int log2n, int e, const std::vector<int>& pl
   for (int c : plan) {
     if (c < LC_ONE || c > LC_WIDE) return false;
     if (c != LC_ONE && !gfpk::span2_supported((int)f->k)) return false;
+    if (c == LC_WIDE && !gfpk::wide_supported((int)f->k)) return false;
     if (s + code_passes(c) > e) return false;
     if (c == LC_WIDE && log2n - 2 * lk - lr - s * lk < 3) return false;  // 8 blocks per twiddle base
     s += code_passes(c);
@@ -513,10 +530,10 @@ std::string plan_text(const std::vector<int>& plan) {
 
 // Untuned choice (k = 8), the fastest plans measured on MI355X for one
 // transform (digit-major ends) and for the two forward transforms of a
-// product (element-major); k = 16 runs one pass per launch.
+// product (element-major); other k run one pass per launch.
 std::vector<int> default_plan(const gfp_field* f, int log2n, int e, int layout) {
   std::vector<int> plan;
-  if (!gfpk::span2_supported((int)f->k)) return std::vector<int>(e, LC_ONE);
+  if (f->k != 8) return std::vector<int>(e, LC_ONE);
   static const char* dm[] = {"", "1", "2", "12", "121", "w21"};
   static const char* em[] = {"", "1", "2", "12", "22", "w12"};
   if (e <= 5) {
@@ -597,6 +614,8 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
     p.tw = p.scale ? t->ninv : (inverse ? t->inv : t->fwd);
     p.tw1 = inverse ? t->inv : t->fwd;
     p.tw2 = inverse ? t->inv2 : t->fwd2;
+    p.twr1 = inverse ? t->inv_raw : t->fwd_raw;
+    p.twr2 = inverse ? t->inv2_raw : t->fwd2_raw;
     if (scale_tab && i == 1) {  // 1/n rides on this launch's twiddle tables
       p.tw = t->inv_s;
       p.tw2 = t->inv2_s;
@@ -900,13 +919,7 @@ int gfp_field_destroy(gfp_field* f) {
   (void)hipGetDevice(&dev);
   for (auto& kv : f->tables) {
     (void)hipSetDevice(kv.first.first);
-    (void)hipFree(kv.second.fwd);
-    (void)hipFree(kv.second.inv);
-    (void)hipFree(kv.second.fwd2);
-    (void)hipFree(kv.second.inv2);
-    (void)hipFree(kv.second.ninv);
-    (void)hipFree(kv.second.inv_s);
-    (void)hipFree(kv.second.inv2_s);
+    free_tables(kv.second);
   }
   for (auto& kv : f->consts) {
     (void)hipSetDevice(kv.first);
@@ -972,6 +985,7 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   const bool wide = (flags & GFP_PASS_WIDE) != 0;
   const int span = (wide || (flags & GFP_PASS_PAIR)) ? 2 : 1;
   if (span == 2 && (radix_r || s + 1 >= total || !gfpk::span2_supported((int)f->k))) return GFP_EINVAL;
+  if (wide && !gfpk::wide_supported((int)f->k)) return GFP_EINVAL;
   if (wide && log2n - 2 * lk - lr - sk * lk < 3) return GFP_EINVAL;
   const bool in_em = (flags & GFP_PASS_IN_ELEMENT_MAJOR) != 0;
   const bool out_em = (flags & GFP_PASS_OUT_ELEMENT_MAJOR) != 0;
@@ -996,6 +1010,8 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   p.tw = p.scale ? t->ninv : (p.inverse ? t->inv : t->fwd);
   p.tw1 = p.inverse ? t->inv : t->fwd;
   p.tw2 = p.inverse ? t->inv2 : t->fwd2;
+  p.twr1 = p.inverse ? t->inv_raw : t->fwd_raw;
+  p.twr2 = p.inverse ? t->inv2_raw : t->fwd2_raw;
   if (scale_tab && s == 1) {
     p.tw = t->inv_s;
     p.tw2 = t->inv2_s;

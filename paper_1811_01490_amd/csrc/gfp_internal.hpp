@@ -40,13 +40,19 @@ struct PassArgs {
   // table of w^(K i) (w^-(K i) for the inverse), i < N/K: the twiddles of
   // every radix-K pass but the last, without a rotation
   const uint32_t* tw2 = nullptr;
+  // tw1 and tw2 as raw digits (k u64 per entry), k <= 16: the passes whose
+  // groups take different twiddles stage them through LDS from these
+  const uint64_t* twr1 = nullptr;
+  const uint64_t* twr2 = nullptr;
   // set with scale (inverse pass 0): the pass input is the pointwise product
   // in[i] in2[i] of two transforms; in2 has the strides of in and its digits
   // contiguous (sd_in 1), and the product is then multiplied by tw[0]
   const uint64_t* in2 = nullptr;
 };
-// Largest span a launch supports for k (0 if none beyond 1).
+// Whether two passes can share a launch for k (plan character '2'), and
+// the wide variant over eight blocks per workgroup (plan character 'w').
 bool span2_supported(int k);
+bool wide_supported(int k);
 
 struct EwArgs {
   int op;

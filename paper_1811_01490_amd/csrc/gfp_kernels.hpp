@@ -89,8 +89,8 @@ template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16 && !UNIF ? 2 : 8))) void k_pass(
     const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2, uint64_t se_in, uint64_t sd_in,
     uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
-    const uint32_t* __restrict__ tw2, int log2n, int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin,
-    uint64_t vout) {
+    const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1, const uint64_t* __restrict__ twr2, int log2n,
+    int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout) {
   typedef Geo<KD> Gm;
   constexpr bool LN = Gm::LEAN || !UNIF;
   constexpr int KB = Gm::KB;
@@ -160,20 +160,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16
         constexpr int t = decltype(T)::value + 1;
         v[t] = l96(x[t]);
       });
-    } else if constexpr (T2) {
+    } else if constexpr (T2 && UNIF) {
       // every exponent a t N / (K Ns) is a multiple of K: w^(a t N / (K Ns))
       // is entry (a t) N / (K^2 Ns) of the table of w^(K i), no rotation
       const int sh2 = log2n - 2 * LOGKB - log2ns;
       static_for<KB - 1>([&](auto T) {
         constexpr int t = decltype(T)::value + 1;
-        const uint32_t* e = tw2 + ((a * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS;
-        if constexpr (UNIF) {
-          v[t] = mul_entry_uniform<KD, W, U>(x[t], e, m);
-        } else {
-          v[t] = mul_entry<KD, W, U, LN>(x[t], e, m);
-        }
+        v[t] = mul_entry_uniform<KD, W, U>(x[t], tw2 + ((a * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS, m);
       });
-    } else {
+    } else if constexpr (UNIF) {
       const int shift = log2n - log2ns - LOGKB;  // table stride N / (Ns K)
       static_for<KB - 1>([&](auto T) {
         constexpr int t = decltype(T)::value + 1;
@@ -181,12 +176,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16
         const int rho = (int)(e >> log2ns);
         const uint64_t c = e & (ns - 1);
         const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
-        if constexpr (UNIF) {
-          v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
-        } else {
-          v[t] = mul_twiddle<KD, W, U, LN>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
-        }
+        v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
       });
+    } else {
+      // per-group twiddles: staged through LDS from the raw-digit tables, the
+      // next slot's digit fetched before this slot's product
+      __shared__ uint32_t stg[4 * StageGeo<KD>::PER_WAVE];
+      uint32_t* E = stg + (int)(threadIdx.x >> 6) * StageGeo<KD>::PER_WAVE + Gm::group(l) * StageGeo<KD>::WORDS;
+      stage_init<KD>(E, m);
+      if constexpr (T2) {
+        const int sh2 = log2n - 2 * LOGKB - log2ns;
+        uint64_t yn = twr2[(a << sh2) * KD + m];
+        static_for<KB - 1>([&](auto T) {
+          constexpr int t = decltype(T)::value + 1;
+          const uint64_t y = yn;
+          if constexpr (t + 1 < KB) yn = twr2[((a * (uint64_t)(t + 1)) << sh2) * KD + m];
+          stage_entry<KD>(y, E, m);
+          v[t] = mul_entry<KD, W, U, LN>(x[t], E, m);
+        });
+      } else {
+        const int shift = log2n - log2ns - LOGKB;  // table stride N / (Ns K)
+        uint64_t yn = twr1[((a & (ns - 1)) << shift) * KD + m];
+        static_for<KB - 1>([&](auto T) {
+          constexpr int t = decltype(T)::value + 1;
+          const uint64_t e = a * (uint64_t)t;
+          const int rho = (int)(e >> log2ns);
+          const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
+          const uint64_t y = yn;
+          if constexpr (t + 1 < KB) yn = twr1[(((a * (uint64_t)(t + 1)) & (ns - 1)) << shift) * KD + m];
+          stage_entry<KD>(y, E, m);
+          v[t] = mul_twiddle<KD, W, U, LN>(x[t], E, rot, l, m);
+        });
+      }
     }
   }
 
@@ -467,24 +488,29 @@ __global__ __launch_bounds__(256) void k_pass_r(const uint64_t* __restrict__ in,
 // output t2' to a + Ns t1' + K Ns t2' + K^2 Ns c -- the same element
 // operations, in the same order, as the two passes run one after the other
 // (section 4.1: the stride permutation L between the two tensor factors is
-// the LDS transpose).  Two blocks per 256-thread workgroup for k = 8.
+// the LDS transpose).  k = 8: two blocks per 256-thread workgroup; k = 16:
+// one block (1024 elements, 130 KiB of LDS) per 512-thread workgroup, so one
+// workgroup per CU.
 template <int KD>
 struct Span2Geo {
   static constexpr int KB = Geo<KD>::KB;
-  static constexpr int WPB = KB / Geo<KD>::G;  // wavefronts per block
-  static constexpr int BPW = 4 / WPB;          // blocks per 256-thread workgroup
-  static constexpr int ROW = KB * KD + 8;      // u64 words per LDS row, padded by 64 bytes
+  static constexpr int WPB = KB / Geo<KD>::G;       // wavefronts per block
+  static constexpr int BPW = WPB >= 4 ? 1 : 4 / WPB;  // blocks per workgroup
+  static constexpr int WAVES = WPB * BPW;           // wavefronts per workgroup
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int ROW = KB * KD + 8;  // u64 words per LDS row, padded by 64 bytes
 };
 
 // T2B: the second pass is not the last one and takes its twiddles from the
 // table of w^(K i); the first pass never is the last and always does.
 template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B>
-__global__ __launch_bounds__(256) void k_pass2(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
+__global__ __launch_bounds__(Span2Geo<KD>::THREADS) void k_pass2(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
                                                uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
                                                const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
-                                               const uint32_t* __restrict__ tw2, int log2n, int log2ns, uint64_t nvec,
+                                               const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1,
+                                               const uint64_t* __restrict__ twr2, int log2n, int log2ns, uint64_t nvec,
                                                uint64_t vin, uint64_t vout) {
-  static_assert(KD == 8, "the fused pass pair is built for k = 8");
+  static_assert(KD == 8 || KD == 16, "the fused pass pair is built for k = 8 and 16");
   typedef Geo<KD> Gm;
   typedef Span2Geo<KD> SG;
   constexpr int KB = Gm::KB;
@@ -561,21 +587,32 @@ __global__ __launch_bounds__(256) void k_pass2(const uint64_t* __restrict__ in, 
   const uint64_t ns1 = ns << LOGKB;
   const uint64_t a1 = a + (t1 << log2ns);
   v[0] = l96(x[0]);
+  // per-group twiddles, staged through LDS from the raw-digit tables
+  __shared__ uint32_t stg[SG::WAVES * StageGeo<KD>::PER_WAVE];
+  uint32_t* E = stg + wv * StageGeo<KD>::PER_WAVE + g * StageGeo<KD>::WORDS;
+  stage_init<KD>(E, m);
   if constexpr (T2B) {
     const int sh2 = log2n - 2 * LOGKB - log2ns1;
+    uint64_t yn = twr2[(a1 << sh2) * KD + m];
     static_for<KB - 1>([&](auto T) {
       constexpr int t = decltype(T)::value + 1;
-      v[t] = mul_entry<KD, W, U>(x[t], tw2 + ((a1 * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS, m);
+      const uint64_t y = yn;
+      if constexpr (t + 1 < KB) yn = twr2[((a1 * (uint64_t)(t + 1)) << sh2) * KD + m];
+      stage_entry<KD>(y, E, m);
+      v[t] = mul_entry<KD, W, U>(x[t], E, m);
     });
   } else {
     const int shift1 = log2n - log2ns1 - LOGKB;
+    uint64_t yn = twr1[((a1 & (ns1 - 1)) << shift1) * KD + m];
     static_for<KB - 1>([&](auto T) {
       constexpr int t = decltype(T)::value + 1;
       const uint64_t e = a1 * (uint64_t)t;
       const int rho = (int)(e >> log2ns1);
-      const uint64_t cc = e & (ns1 - 1);
       const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
-      v[t] = mul_twiddle<KD, W, U>(x[t], tw1 + (cc << shift1) * TwLayout<KD>::WORDS, rot, l, m);
+      const uint64_t y = yn;
+      if constexpr (t + 1 < KB) yn = twr1[(((a1 * (uint64_t)(t + 1)) & (ns1 - 1)) << shift1) * KD + m];
+      stage_entry<KD>(y, E, m);
+      v[t] = mul_twiddle<KD, W, U>(x[t], E, rot, l, m);
     });
   }
   dft_base<KD, INV>(v, m);
@@ -772,7 +809,7 @@ inline unsigned blocks_for(uint64_t groups, int G) {
 
 template <int KD, int W, int U>
 hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
-  if constexpr (KD != 8) {
+  if constexpr (KD != 8 && KD != 16) {
     return hipErrorInvalidValue;
   } else {
     constexpr int LOGKB = ilog2(2 * KD);
@@ -780,6 +817,9 @@ hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
     // the second pass takes the w^(K i) table unless it is the last pass
     const bool t2b = !p.last && p.log2n - 2 * LOGKB - (p.log2ns + LOGKB) >= 0;
     if (p.wide) {
+      if constexpr (KD != 8) {
+        return hipErrorInvalidValue;
+      } else {
       // 8 blocks per workgroup: both halves with uniform twiddles
       if (p.log2n - 2 * LOGKB - p.log2ns < 3) return hipErrorInvalidValue;
       const uint64_t wgs = p.nvec << (p.log2n - 2 * LOGKB - 3);
@@ -803,13 +843,16 @@ hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
 #undef GFP_LAUNCH2U_T
 #undef GFP_LAUNCH2U
       return hipGetLastError();
+      }
     }
     const uint64_t blocks = (p.nvec << (p.log2n - 2 * LOGKB));
     const unsigned nb = (unsigned)((blocks + Span2Geo<KD>::BPW - 1) / Span2Geo<KD>::BPW);
     if (nb == 0) return hipSuccess;
 #define GFP_LAUNCH2(INV, MODE, LAST, T2B)                                                                         \
-  hipLaunchKernelGGL((k_pass2<KD, W, U, INV, MODE, LAST, T2B>), dim3(nb), dim3(256), 0, st, p.in, p.in2, p.se_in,   \
-                     p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.log2n, p.log2ns, p.nvec, p.vin, p.vout)
+  hipLaunchKernelGGL((k_pass2<KD, W, U, INV, MODE, LAST, T2B>), dim3(nb), dim3(Span2Geo<KD>::THREADS), 0, st, p.in, \
+                     p.in2, p.se_in,                                                                                  \
+                     p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.twr1, p.twr2, p.log2n, p.log2ns, p.nvec, \
+                     p.vin, p.vout)
 #define GFP_LAUNCH2_T(INV, MODE)                   \
   if (p.last) GFP_LAUNCH2(INV, MODE, true, false); \
   else if (t2b) GFP_LAUNCH2(INV, MODE, false, true); \
@@ -940,8 +983,8 @@ hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
   if (nb == 0) return hipSuccess;
 #define GFP_LAUNCH(INV, MODE, LAST, UNIF, T2)                                                                       \
   hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST, UNIF, T2>), dim3(nb), dim3(256), 0, st, p.in, p.in2, p.se_in,   \
-                     p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.log2n, p.log2ns, p.ngroups, p.nvec, p.vin,      \
-                     p.vout)
+                     p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.twr1, p.twr2, p.log2n, p.log2ns, p.ngroups,     \
+                     p.nvec, p.vin, p.vout)
   // uniform twiddles when every base a has at least one wavefront of groups;
   // the w^(K i) table for every pass but the last
   const int lk = ilog2(2 * KD);
