@@ -173,8 +173,11 @@ def test_plan_strings():
         f.set_plan(2 ** 20, "111w")  # the last pair has one block per twiddle base
     g = gfp.Field(**P16)
     assert g.plan(2 ** 20) == "1111"
+    g.set_plan(32768, "21")  # fused pairs exist for k = 16 ...
+    assert g.plan(32768) == "21"
     with pytest.raises(gfp.GFPError):
-        g.set_plan(32768, "21")
+        g.set_plan(2 ** 20, "w11")  # ... the wide pair does not
+    g.set_plan(32768, None)
 
 
 def test_k32_field_host():
