@@ -5,11 +5,13 @@
 
 reads the CSV files rocprofv3 writes with ``--output-format csv``
 (``*_kernel_stats.csv`` from ``--kernel-trace --stats``, and
-``*_counter_collection.csv`` from ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``)
-and writes ``profiles/<label>.txt`` (durations and bytes per kernel) and,
-when counters are given, updates ``profiles/pmc_traffic.json`` (bytes per
-launch per kernel, keyed like bench.py's roofline kernel, with the hash of
-the kernel sources they were taken on).
+``*_counter_collection.csv`` from ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``,
+and from ``--pmc SQ_...`` runs given with ``--sq``) and writes
+``profiles/<label>.txt`` (durations, bytes and instruction counts per
+kernel) and, when counters are given, updates ``profiles/pmc_traffic.json``
+(bytes per launch per kernel, keyed like bench.py's roofline kernel) and
+``profiles/pmc_counters.json`` (instructions per wavefront, VALU busy), per
+workload label, with the hash of the kernel sources they were taken on.
 
 Counter scaling: FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is
 scaled by the ratio known bytes / counter value of the calibration copy
@@ -74,10 +76,18 @@ def _one(dirname: str, pattern: str) -> str:
     return files[0]
 
 
+def ours(name: str) -> bool:
+    """Kernels of this library and the calibration copy (not torch's own
+    kernels, such as the fill that initialises the calibration buffer)."""
+    return "at::native" not in name
+
+
 def read_stats(trace_dir: str):
     rows = list(csv.DictReader(open(_one(trace_dir, "*kernel_stats.csv"))))
     out = []
     for r in rows:
+        if not ours(r["Name"]):
+            continue
         out.append(dict(kernel=kernel_key(r["Name"]), calls=int(r["Calls"]), avg_us=float(r["AverageNs"]) / 1e3,
                         min_us=float(r["MinNs"]) / 1e3, max_us=float(r["MaxNs"]) / 1e3, pct=float(r["Percentage"])))
     return out
@@ -89,10 +99,61 @@ def read_counter(pmc_dir: str):
     scale = CALIB_BYTES / (float(calib["Counter_Value"]) * 1024) if calib else 1.0
     per = {}
     for r in rows:
-        if "copyBuffer" in r["Kernel_Name"]:
+        if "copyBuffer" in r["Kernel_Name"] or not ours(r["Kernel_Name"]):
             continue
         per.setdefault(kernel_key(r["Kernel_Name"]), []).append(float(r["Counter_Value"]) * 1024 * scale)
     return scale, {k: sum(v) / len(v) for k, v in per.items()}, rows[0]["Counter_Name"] if rows else "?"
+
+
+def read_sq(dirs):
+    """Mean value per dispatch of every counter in the counter_collection CSVs
+    under the given directories, per kernel: {kernel: {counter: value}}."""
+    per = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if "copyBuffer" in r["Kernel_Name"] or not ours(r["Kernel_Name"]):
+                    continue
+                per.setdefault(kernel_key(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+                    float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in per.items()}
+
+
+SIMDS = 256 * 4  # MI355X: 256 CUs of 4 SIMDs
+CLOCK_HZ = 2.4e9  # peak engine clock
+VALU_CYCLES = 4  # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
+
+
+def sq_table(sq, stats):
+    """Instruction mix and VALU issue share per kernel: VALU busy = VALU
+    instructions x 4 cycles / (1024 SIMDs x 2.4 GHz x mean duration)."""
+    dur = {s["kernel"]: s["avg_us"] for s in stats}
+    lines = ["", "## Instruction counters per dispatch (rocprofv3 --pmc SQ_*)", "",
+             "VALU busy = SQ_INSTS_VALU x %d cycles / (%d SIMDs x %.1f GHz x mean duration from the trace above)."
+             % (VALU_CYCLES, SIMDS, CLOCK_HZ / 1e9), "",
+             "| kernel | waves | VALU / wave | of which 64-bit | SALU / wave | LDS / wave | VMEM rd / wave | "
+             "LDS bank conflicts / wave | VALU busy |", "|---|---|---|---|---|---|---|---|---|"]
+    out = {}
+    for k in sorted(sq):
+        c = sq[k]
+        w = c.get("SQ_WAVES", 0.0)
+        if not w:
+            continue
+        valu = c.get("SQ_INSTS_VALU", 0.0)
+        busy = valu * VALU_CYCLES / (SIMDS * CLOCK_HZ * dur[k] * 1e-6) if k in dur and dur[k] else None
+        row = {"waves": round(w), "valu_per_wave": round(valu / w, 1),
+               "valu64_per_wave": round(c.get("SQ_INSTS_VALU_INT64", 0.0) / w, 1),
+               "salu_per_wave": round(c.get("SQ_INSTS_SALU", 0.0) / w, 1),
+               "lds_per_wave": round(c.get("SQ_INSTS_LDS", 0.0) / w, 1),
+               "vmem_rd_per_wave": round(c.get("SQ_INSTS_VMEM_RD", 0.0) / w, 1),
+               "lds_bank_conflicts_per_wave": round(c.get("SQ_LDS_BANK_CONFLICT", 0.0) / w, 1),
+               "valu_busy": round(busy, 3) if busy is not None else None}
+        out[k] = row
+        lines.append("| %s | %d | %.0f | %.0f | %.0f | %.0f | %.0f | %.0f | %s |" % (
+            k, row["waves"], row["valu_per_wave"], row["valu64_per_wave"], row["salu_per_wave"],
+            row["lds_per_wave"], row["vmem_rd_per_wave"], row["lds_bank_conflicts_per_wave"],
+            "%.2f" % busy if busy is not None else "-"))
+    return lines, out
 
 
 def main():
@@ -100,6 +161,7 @@ def main():
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch")
     ap.add_argument("--write")
+    ap.add_argument("--sq", nargs="*", default=[], help="directories of --pmc SQ_* runs")
     ap.add_argument("--label", required=True)
     ap.add_argument("--command", required=True, help="the rocprofv3 command lines that produced the data")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
@@ -129,10 +191,17 @@ def main():
         jpath = os.path.join(args.out, "pmc_traffic.json")
         d = json.load(open(jpath)) if os.path.exists(jpath) else {}
         if d.get("source_hash") != source_hash():
-            d = {"source_hash": source_hash(), "kernels": {}}
-        d["kernels"].update(traffic)
-        d["fetch_scale"] = round(fs, 6)
-        d["write_scale"] = round(ws, 6)
+            d = {"source_hash": source_hash(), "workloads": {}}
+        d["workloads"][args.label] = {"kernels": traffic, "fetch_scale": round(fs, 6), "write_scale": round(ws, 6)}
+        json.dump(d, open(jpath, "w"), indent=1, sort_keys=True)
+    if args.sq:
+        sq_lines, sq_rows = sq_table(read_sq(args.sq), stats)
+        lines += sq_lines
+        jpath = os.path.join(args.out, "pmc_counters.json")
+        d = json.load(open(jpath)) if os.path.exists(jpath) else {}
+        if d.get("source_hash") != source_hash():
+            d = {"source_hash": source_hash(), "workloads": {}}
+        d["workloads"][args.label] = {"kernels": sq_rows}
         json.dump(d, open(jpath, "w"), indent=1, sort_keys=True)
     with open(os.path.join(args.out, args.label + ".txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
