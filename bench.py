@@ -37,6 +37,7 @@ R16 = 2 ** 62 + 2 ** 36  # the k = 16 prime of the served workload
 LOG2N = 20
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit integer lane-ops per second (Tops/s)
 HBM_PEAK_GBS = 8000.0
+PROFILE_LABEL = "fft_forward_k8_n1048576"  # the profiles/ summary of this workload
 
 
 def pass_counts(N: int, K: int, s: int, k: int):
@@ -75,7 +76,7 @@ def traffic_from_profiles(kernel_key: str):
         return None
     if d.get("source_hash") != source_hash():
         return None
-    ent = d.get("kernels", {}).get(kernel_key)
+    ent = d.get("workloads", {}).get(PROFILE_LABEL, {}).get("kernels", {}).get(kernel_key)
     return ent.get("bytes_per_launch") if ent else None
 
 
@@ -246,8 +247,10 @@ def served_leg(torch, dev, n_req: int, loads, workspace_gib: int, slots: int, ex
     one stream).  Each stream is served twice: by the request loop (continuous
     batching over `slots` streams) and by a one-request-per-launch FIFO loop
     (one slot, batches of one), reporting p50/p99 latency (done - scheduled
-    arrival) and throughput.  Every served result is compared with the plain
-    run's result of the same request through a 64-bit digest."""
+    arrival) and throughput.  The request loop runs with its batches replayed
+    as hipGraphs (the default) and, for comparison, launched eagerly.  Every
+    served result is compared with the plain run's result of the same request
+    through a 64-bit digest."""
     import numpy as np
 
     import gfp_inputs as gi
@@ -341,6 +344,8 @@ def served_leg(torch, dev, n_req: int, loads, workspace_gib: int, slots: int, ex
             "batches": st["batches"],
             "max_batch_size": st["max_batch_size"],
             "overlapped_batches": st["overlapped_batches"],
+            "graph_launches": st["graph_launches"],
+            "graph_captures": st["graph_captures"],
             "identical_to_alone": same,
         }
 
@@ -350,12 +355,19 @@ def served_leg(torch, dev, n_req: int, loads, workspace_gib: int, slots: int, ex
         with Server(workspace_bytes=workspace_gib << 30, slots=slots, max_batch=256, max_pending=n_req,
                     express_log2n=express_log2n) as srv:
             cb = serve(srv, lam, j)
-        print("served: load %.2f continuous batching p99 %.3f ms" % (load, cb["p99_ms"]), file=sys.stderr, flush=True)
-        with Server(workspace_bytes=2 << 30, slots=1, max_batch=1, max_pending=n_req) as srv:
+        print("served: load %.2f continuous batching, graphs p99 %.3f ms" % (load, cb["p99_ms"]), file=sys.stderr,
+              flush=True)
+        with Server(workspace_bytes=workspace_gib << 30, slots=slots, max_batch=256, max_pending=n_req,
+                    express_log2n=express_log2n, graphs=False) as srv:
+            cbe = serve(srv, lam, j)
+        print("served: load %.2f continuous batching, eager p99 %.3f ms" % (load, cbe["p99_ms"]), file=sys.stderr,
+              flush=True)
+        with Server(workspace_bytes=2 << 30, slots=1, max_batch=1, max_pending=n_req, graphs=False) as srv:
             fifo = serve(srv, lam, j)
         print("served: load %.2f plain FIFO p99 %.3f ms" % (load, fifo["p99_ms"]), file=sys.stderr, flush=True)
         runs[str(load)] = {"arrival_rate_per_s": round(lam, 1), "continuous_batching": cb,
-                           "plain_fifo": fifo, "p99_speedup": round(fifo["p99_ms"] / cb["p99_ms"], 3)}
+                           "continuous_batching_eager": cbe, "plain_fifo": fifo,
+                           "p99_speedup": round(fifo["p99_ms"] / cb["p99_ms"], 3)}
     for f in fields.values():
         f.close()
     return {

@@ -35,6 +35,12 @@
  * asynchronous device work surface as GFP_EDEVICE from a later call on the
  * stream or from the caller's own synchronisation.  Inputs are assumed
  * canonical; non-canonical digits give unspecified (but memory-safe) results.
+ * Validation: when the environment variable GFP_VALIDATE is set (to anything
+ * but "0") at gfp_field_create, the transform, product and elementwise calls
+ * on that field first count non-canonical input elements on the device (as
+ * gfp_check_canonical does, synchronising the stream) and return GFP_EINVAL
+ * if there are any.  gfp_fft_noalloc, gfp_fft_pass, the integer products and
+ * the request loop do not validate.
  */
 #ifndef GFP_H
 #define GFP_H
@@ -72,7 +78,8 @@ typedef struct gfp_field gfp_field;
  * r = 2^w + 2^u with (k, w, u) in {(8, 63, 34), (8, 59, 16), (16, 62, 36),
  * (16, 58, 10), (32, 62, 56), (32, 56, 21)} and for r = 2^63 - 2^40 with
  * k = 64 (Table 1 and Table testprimes).  p is checked
- * with a Miller-Rabin probable-prime test (12 fixed bases).
+ * with the Baillie-PSW probable-prime test (a strong test to base 2 and a
+ * strong Lucas test with Selfridge's parameters).
  * Returns GFP_EINVAL (out == NULL, bad k/r), GFP_EUNSUPPORTED (shape not
  * compiled in), GFP_ENOTPRIME.  On success *out owns the field; release it
  * with gfp_field_destroy. */
@@ -118,6 +125,7 @@ int gfp_fft_inverse(const gfp_field* f, uint64_t n, const uint64_t* x, uint64_t 
 #define GFP_PASS_OUT_ELEMENT_MAJOR 2
 #define GFP_PASS_PAIR 4 /* passes s and s+1 in one launch, as plan character '2' */
 #define GFP_PASS_WIDE 8 /* passes s and s+1 in one launch, as plan character 'w' */
+#define GFP_PASS_NTT 16 /* k >= 32: twiddles multiplied by the FFT-based product, as plan character 'n' */
 
 /* One pass (stage s) of the transform schedule used by gfp_fft_forward /
  * gfp_fft_inverse, n = R K^e.  The stages are s = 0..S-1 with S = e + 1 when
@@ -236,7 +244,12 @@ int gfp_bigint_mul(const gfp_field* f, const uint64_t* a, uint64_t na, const uin
  * (K^2-element blocks, two per workgroup for k = 8, one for k = 16; the
  * second pass reads its twiddles per element group), 'w' (k = 8) two fused
  * passes over eight blocks per workgroup (wavefront-uniform twiddles in both
- * passes; needs n / (K^2 R K^s) >= 8 at its first radix-K pass s).  The plan covers the radix-K passes only.
+ * passes; needs n / (K^2 R K^s) >= 8 at its first radix-K pass s), and for
+ * k = 32, 64 'n': one pass whose twiddle products use the FFT-based
+ * multiplication of section 3.3 (negacyclic transforms of the digits modulo
+ * three word primes and the CRT) with the twiddles' transforms tabulated
+ * (built on the first such transform of a size on a device), instead of the
+ * schoolbook column product; the results are identical.  The plan covers the radix-K passes only.
  * Example: "1211" for e = 5.  Plans are kept per
  * (n, batch class, layout): the batch class is the number of same-size
  * transforms one launch covers (1, 2-7, 8-63, 64 and more: gfp_polymul runs
@@ -278,7 +291,8 @@ int gfp_tune(gfp_field* f, uint64_t n, uint64_t nvec, int layout, void* stream, 
  * each class is done as soon as its own work is.  Requests that arrive while
  * slots are busy wait until a slot frees, and batches of different slots run
  * concurrently on the device.  An express slot (express_log2n) serves only
- * small requests, taken from anywhere in the queue in arrival order.  Each result is bit-identical to gfp_polymul of
+ * small requests, taken from anywhere in the queue in arrival order.  Batches run as replayed hipGraphs (see
+ * gfp_server_config.flags).  Each result is bit-identical to gfp_polymul of
  * the same request alone: the arithmetic is exact and does not depend on the
  * batch.  All calls are thread-safe, except that gfp_server_destroy must not
  * overlap any other call on the same server.  Timestamps are CLOCK_MONOTONIC
@@ -294,7 +308,20 @@ typedef struct gfp_server_config {
   int32_t device;           /* HIP device ordinal, -1 = the current device */
   uint32_t express_log2n;   /* 0, or: the last slot only takes requests of transform size <= 2^express_log2n
                                (needs slots >= 2) */
+  uint32_t flags;           /* GFP_SERVER_* bits */
 } gfp_server_config;
+
+/* gfp_server_config.flags.  By default each slot runs a chunk of C requests
+ * of one (field, transform size) class as a hipGraph: the chunk's launch
+ * sequence (as in gfp_polymul_batched) is captured per (field, size, C) and
+ * slot, the second time that shape occurs (the first time it runs eagerly),
+ * with the copy descriptors read from a small device table of the slot, and
+ * replayed for every later chunk of that shape after the new descriptors are
+ * copied into the table.  C is rounded up to a power of two where the
+ * chunk's work is small (C n <= 2^17 elements; the extra entries copy
+ * nothing).  With GFP_SERVER_EAGER the launches are enqueued one by one
+ * instead. */
+#define GFP_SERVER_EAGER 1
 
 typedef struct gfp_request {
   const gfp_field* field; /* must outlive the request */
@@ -325,12 +352,17 @@ typedef struct gfp_server_stats {
   uint64_t max_batch_workspace;            /* largest workspace a batch needed, bytes */
   uint64_t overlapped_batches;             /* batches launched while another slot's batch was in flight */
   uint64_t slot_bytes;                     /* workspace per slot */
+  uint64_t graph_launches;                 /* chunks run by replaying a captured graph */
+  uint64_t graph_captures;                 /* chunk graphs captured (a shape's second occurrence) */
 } gfp_server_stats;
 
-/* Start a server on cfg->device: allocates the workspace (cfg->workspace_bytes)
- * and creates the slot streams and threads.  Errors: GFP_EINVAL (NULL
- * argument, slots > 64, workspace_bytes / slots under 256 bytes,
- * express_log2n > 40 or with fewer than 2 slots), GFP_ENOMEM, GFP_EDEVICE. */
+/* Start a server on cfg->device: allocates the workspace (cfg->workspace_bytes),
+ * a copy-descriptor table per slot (96 max_batch bytes, rounded up to 256)
+ * and pinned host staging for the descriptors (192 max_batch bytes per
+ * slot), and creates the slot streams and threads.  Errors: GFP_EINVAL
+ * (NULL argument, slots > 64, max_batch > 65535, workspace_bytes / slots
+ * under 256 bytes, express_log2n > 40 or with fewer than 2 slots, unknown
+ * flags), GFP_ENOMEM, GFP_EDEVICE. */
 int gfp_server_create(const gfp_server_config* cfg, gfp_server** out);
 
 /* Queue one request; returns at once with a ticket (1, 2, ...), except that

@@ -223,4 +223,118 @@ struct Mont {
   }
 };
 
+// ---- Baillie-PSW probable-prime test ----------------------------------------
+// A strong probable-prime test to base 2 followed by a strong Lucas test with
+// Selfridge's parameters (D the first of 5, -7, 9, -11, ... with Jacobi
+// symbol (D/n) = -1, P = 1, Q = (1 - D) / 4).  No composite is known to pass
+// both.
+
+// Jacobi symbol (D / n) for odd n > 0 and D = +-a, a odd and small.
+inline int jacobi_small(bool negative, uint64_t a, const Big& n) {
+  int t = 1;
+  const uint64_t n4 = n.limb(0) & 3;
+  if (negative && n4 == 3) t = -t;      // (-1 / n) = (-1)^((n - 1) / 2)
+  if ((a & 3) == 3 && n4 == 3) t = -t;  // reciprocity: (a / n) = +-(n / a)
+  uint64_t x;
+  (void)divmod_small(n, a, &x);
+  uint64_t y = a;
+  while (x != 0) {  // (x / y), y odd
+    while ((x & 1) == 0) {
+      x >>= 1;
+      const uint64_t y8 = y & 7;
+      if (y8 == 3 || y8 == 5) t = -t;  // (2 / y)
+    }
+    std::swap(x, y);
+    if ((x & 3) == 3 && (y & 3) == 3) t = -t;
+    x %= y;
+  }
+  return y == 1 ? t : 0;
+}
+
+// floor(sqrt(a)) by Newton's iteration.
+inline Big isqrt(const Big& a) {
+  if (a.is_zero()) return a;
+  Big x = shl(Big(1), (a.bits() + 1) / 2 + 1);
+  for (;;) {
+    Big y = shr(add(x, divq(a, x)), 1);
+    if (cmp(y, x) >= 0) return x;
+    x = y;
+  }
+}
+
+inline bool strong_probable_prime_base2(const Big& n, const Mont& M) {
+  const Big nm1 = sub(n, Big(1));
+  const unsigned s = ctz(nm1);
+  const Big minus_one = M.to(nm1);
+  Big x = M.pow(M.to(Big(2)), shr(nm1, s));
+  if (cmp(x, M.one) == 0 || cmp(x, minus_one) == 0) return true;
+  for (unsigned i = 1; i < s; ++i) {
+    x = M.mmul(x, x);
+    if (cmp(x, minus_one) == 0) return true;
+  }
+  return false;
+}
+
+inline bool strong_lucas_probable_prime(const Big& n, const Mont& M) {
+  // Selfridge: D = 5, -7, 9, -11, ...
+  uint64_t a = 5;
+  bool neg = false;
+  for (;; a += 2, neg = !neg) {
+    const int j = jacobi_small(neg, a, n);
+    if (j == -1) break;
+    if (j == 0 && cmp(n, Big(a)) != 0) return false;  // a shares a factor with n
+    if (a == 61) {  // no D so far: rule out a perfect square, which has none
+      const Big r = isqrt(n);
+      if (cmp(mul(r, r), n) == 0) return false;
+    }
+  }
+  auto neg_mod = [&](const Big& v) { return v.is_zero() ? v : sub(n, v); };
+  auto addm = [&](const Big& x, const Big& y) {
+    Big z = add(x, y);
+    return cmp(z, n) >= 0 ? sub(z, n) : z;
+  };
+  auto subm = [&](const Big& x, const Big& y) { return cmp(x, y) >= 0 ? sub(x, y) : sub(add(x, n), y); };
+  auto half = [&](const Big& x) { return (x.limb(0) & 1) ? shr(add(x, n), 1) : shr(x, 1); };
+  // Montgomery forms (halving commutes with the factor R)
+  const Big Dm = neg ? neg_mod(M.to(Big(a))) : M.to(Big(a));
+  // Q = (1 - D) / 4: D = a gives -(a - 1) / 4, D = -a gives (a + 1) / 4
+  const Big Qm = neg ? M.to(Big((a + 1) / 4)) : neg_mod(M.to(Big((a - 1) / 4)));
+  const Big np1 = add(n, Big(1));
+  const unsigned s = ctz(np1);
+  const Big d = shr(np1, s);
+  // U_1 = 1, V_1 = P = 1, Q^1; then the bits of d below the top one
+  Big U = M.one, V = M.one, Qk = Qm;
+  for (unsigned i = d.bits() - 1; i-- > 0;) {
+    U = M.mmul(U, V);                               // U_2k = U_k V_k
+    V = subm(M.mmul(V, V), addm(Qk, Qk));           // V_2k = V_k^2 - 2 Q^k
+    Qk = M.mmul(Qk, Qk);
+    if (d.bit(i)) {
+      const Big U1 = half(addm(U, V));              // U_2k+1 = (P U + V) / 2
+      const Big V1 = half(addm(M.mmul(Dm, U), V));  // V_2k+1 = (D U + P V) / 2
+      U = U1;
+      V = V1;
+      Qk = M.mmul(Qk, Qm);
+    }
+  }
+  if (U.is_zero() || V.is_zero()) return true;
+  for (unsigned r = 1; r < s; ++r) {
+    V = subm(M.mmul(V, V), addm(Qk, Qk));  // V_(d 2^r)
+    if (V.is_zero()) return true;
+    Qk = M.mmul(Qk, Qk);
+  }
+  return false;
+}
+
+// Baillie-PSW for odd n > 3.
+inline bool bpsw(const Big& n) {
+  static const uint64_t small[] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47};
+  for (uint64_t q : small) {
+    uint64_t rem;
+    (void)divmod_small(n, q, &rem);
+    if (rem == 0) return cmp(n, Big(q)) == 0;
+  }
+  const Mont M(n);
+  return strong_probable_prime_base2(n, M) && strong_lucas_probable_prime(n, M);
+}
+
 }  // namespace gfp

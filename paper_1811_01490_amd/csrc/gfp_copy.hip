@@ -34,6 +34,34 @@ __global__ __launch_bounds__(256) void k_unpad(const CopyBatch desc, const uint6
   cd.dst[(uint64_t)d * cd.ld + i] = work[(uint64_t)v * n * k + i * k + d];
 }
 
+// The same two copies with the descriptors read from device memory (entry
+// base + blockIdx.y), so that a captured launch sequence can be replayed for
+// new requests by rewriting the descriptor table; unpad covers all n
+// elements of each vector (entries past a descriptor's len write nothing).
+__global__ __launch_bounds__(256) void k_pad_dev(const CopyDesc* __restrict__ desc, uint64_t* __restrict__ work,
+                                                 uint64_t n, uint32_t k, uint32_t log2k) {
+  const uint32_t v = blockIdx.y;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * k) return;
+  const uint64_t i = t >> log2k;
+  const uint32_t d = (uint32_t)(t & (k - 1));
+  const CopyDesc cd = desc[v];
+  work[(uint64_t)v * n * k + t] = (i < cd.len) ? cd.src[(uint64_t)d * cd.ld + i] : 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_unpad_dev(const CopyDesc* __restrict__ desc,
+                                                   const uint64_t* __restrict__ work, uint64_t n, uint32_t k,
+                                                   uint32_t log2n) {
+  const uint32_t v = blockIdx.y;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * k) return;
+  const uint32_t d = (uint32_t)(t >> log2n);
+  const uint64_t i = t & (n - 1);
+  const CopyDesc cd = desc[v];
+  if (i >= cd.len) return;
+  cd.dst[(uint64_t)d * cd.ld + i] = work[(uint64_t)v * n * k + i * k + d];
+}
+
 // Elements of a digit-major vector that are not canonical (section 2: every
 // digit below r, or p - 1 written as (0, ..., 0, r)), counted into *bad
 // (vector atomics).  One thread per element.
@@ -85,6 +113,28 @@ hipError_t launch_unpad(int k, const CopyDesc* d, uint32_t nvec, const uint64_t*
   const uint64_t tot = maxlen * (uint64_t)k;
   dim3 grid((unsigned)((tot + 255) / 256), nvec);
   hipLaunchKernelGGL(k_unpad, grid, dim3(256), 0, st, b, work, n, maxlen, (uint32_t)k);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_dev(int k, const CopyDesc* dev_desc, uint32_t nvec, uint64_t* work, uint64_t n,
+                          hipStream_t st) {
+  if (nvec == 0) return hipSuccess;
+  if (nvec > 65535) return hipErrorInvalidValue;
+  uint32_t lk = 0;
+  while ((1u << lk) < (uint32_t)k) ++lk;
+  dim3 grid((unsigned)((n * (uint64_t)k + 255) / 256), nvec);
+  hipLaunchKernelGGL(k_pad_dev, grid, dim3(256), 0, st, dev_desc, work, n, (uint32_t)k, lk);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpad_dev(int k, const CopyDesc* dev_desc, uint32_t nvec, const uint64_t* work, uint64_t n,
+                            hipStream_t st) {
+  if (nvec == 0) return hipSuccess;
+  if (nvec > 65535 || (n & (n - 1))) return hipErrorInvalidValue;
+  uint32_t ln = 0;
+  while ((1ull << ln) < n) ++ln;
+  dim3 grid((unsigned)((n * (uint64_t)k + 255) / 256), nvec);
+  hipLaunchKernelGGL(k_unpad_dev, grid, dim3(256), 0, st, dev_desc, work, n, (uint32_t)k, ln);
   return hipGetLastError();
 }
 

@@ -1022,42 +1022,47 @@ __device__ __forceinline__ uint64_t lane_xchg(uint64_t v, int src) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <int KD, int W, int U>
-__device__ __forceinline__ L96 mul_ntt(uint64_t x, uint64_t y, const uint64_t* __restrict__ tb, int l, int m) {
+// Forward length-k DFT across the element's lanes modulo q (decimation in
+// frequency, natural order in, bit-reversed out): lane m holds v_m < q.
+// Halves k/2, ..., 1: the upper lane of a pair takes (a - b) w^(j k / (2h)),
+// the lower a + b.
+template <int KD>
+__device__ __forceinline__ uint64_t ntt_fwd_lanes(uint64_t v, const uint64_t* __restrict__ b, uint64_t q, uint64_t qn,
+                                                  int l, int m) {
   constexpr int LK = ilog2(KD);
-  uint64_t u[3];
-  static_for<3>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    const uint64_t q = tb[i], qn = tb[3 + i];
-    const uint64_t* b = tb + NTT_HEAD + 3 * KD * i;
-    // A x, A y (x, y < 2^64 and theta^m < q: the products stay below q 2^64)
-    uint64_t xv = mont_mul(x, b[m], q, qn);
-    uint64_t yv = mont_mul(y, b[m], q, qn);
-    // forward DFTs: half sizes k/2, ..., 1; the upper lane of a pair takes
-    // (a - b) w^(j k / (2h)), the lower a + b
-    static_for<LK>([&](auto S) {
-      constexpr int h = KD >> (decltype(S)::value + 1);
-      const int src = Geo<KD>::lane_of(l, m ^ h);
-      const bool up = (m & h) != 0;
-      const uint64_t w = b[2 * KD + (m & (h - 1)) * (KD / (2 * h))];
-      const uint64_t px = lane_xchg<KD>(xv, src), py = lane_xchg<KD>(yv, src);
-      xv = up ? mont_mul(sub_q(px, xv, q), w, q, qn) : add_q(xv, px, q);
-      yv = up ? mont_mul(sub_q(py, yv, q), w, q, qn) : add_q(yv, py, q);
-    });
-    uint64_t uv = mont_mul(xv, yv, q, qn);  // carries a factor 2^-64
-    // inverse DFT: half sizes 1, ..., k/2; the upper lane first takes b w^-j
-    static_for<LK>([&](auto S) {
-      constexpr int h = 1 << decltype(S)::value;
-      const int src = Geo<KD>::lane_of(l, m ^ h);
-      const bool up = (m & h) != 0;
-      const uint64_t w = b[2 * KD + KD / 2 + (m & (h - 1)) * (KD / (2 * h))];
-      const uint64_t bw = up ? mont_mul(uv, w, q, qn) : uv;
-      const uint64_t pu = lane_xchg<KD>(bw, src);
-      uv = up ? sub_q(pu, bw, q) : add_q(bw, pu, q);
-    });
-    // theta^-m / k, and the 2^64 of the pointwise product
-    u[i] = mont_mul(uv, b[KD + m], q, qn);
+  static_for<LK>([&](auto S) {
+    constexpr int h = KD >> (decltype(S)::value + 1);
+    const int src = Geo<KD>::lane_of(l, m ^ h);
+    const bool up = (m & h) != 0;
+    const uint64_t w = b[2 * KD + (m & (h - 1)) * (KD / (2 * h))];
+    const uint64_t pv = lane_xchg<KD>(v, src);
+    v = up ? mont_mul(sub_q(pv, v, q), w, q, qn) : add_q(v, pv, q);
   });
+  return v;
+}
+
+// The inverse (decimation in time, bit-reversed in, natural out, without
+// the factor 1/k): halves 1, ..., k/2; the upper lane first takes b w^-j.
+template <int KD>
+__device__ __forceinline__ uint64_t ntt_inv_lanes(uint64_t v, const uint64_t* __restrict__ b, uint64_t q, uint64_t qn,
+                                                  int l, int m) {
+  constexpr int LK = ilog2(KD);
+  static_for<LK>([&](auto S) {
+    constexpr int h = 1 << decltype(S)::value;
+    const int src = Geo<KD>::lane_of(l, m ^ h);
+    const bool up = (m & h) != 0;
+    const uint64_t w = b[2 * KD + KD / 2 + (m & (h - 1)) * (KD / (2 * h))];
+    const uint64_t bw = up ? mont_mul(v, w, q, qn) : v;
+    const uint64_t pv = lane_xchg<KD>(bw, src);
+    v = up ? sub_q(pv, bw, q) : add_q(bw, pv, q);
+  });
+  return v;
+}
+
+// Column u_m from its three residues (Garner's CRT into (-Q/2, Q/2]), then
+// the schoolbook product's fold into the lazy digit T_m + Q_{m-1}.
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 ntt_crt_tail(const uint64_t (&u)[3], const uint64_t* __restrict__ tb, int m) {
   // CRT (Garner): u = v1 + q1 v2 + q1 q2 v3, then into (-Q/2, Q/2]
   const uint64_t q1 = tb[0], q2 = tb[1], q3 = tb[2];
   const uint64_t v1 = u[0];
@@ -1084,6 +1089,55 @@ __device__ __forceinline__ L96 mul_ntt(uint64_t x, uint64_t y, const uint64_t* _
   }
   return column_tail<KD, W, U>((uint32_t)c0, (uint32_t)(c0 >> 32), (uint32_t)c1, (uint32_t)(c1 >> 32),
                                (uint32_t)c2, m);
+}
+
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_ntt(uint64_t x, uint64_t y, const uint64_t* __restrict__ tb, int l, int m) {
+  uint64_t u[3];
+  static_for<3>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const uint64_t q = tb[i], qn = tb[3 + i];
+    const uint64_t* b = tb + NTT_HEAD + 3 * KD * i;
+    // A x, A y (x, y < 2^64 and theta^m < q: the products stay below q 2^64)
+    const uint64_t xv = ntt_fwd_lanes<KD>(mont_mul(x, b[m], q, qn), b, q, qn, l, m);
+    const uint64_t yv = ntt_fwd_lanes<KD>(mont_mul(y, b[m], q, qn), b, q, qn, l, m);
+    const uint64_t uv = ntt_inv_lanes<KD>(mont_mul(xv, yv, q, qn), b, q, qn, l, m);  // carries 2^-64
+    // theta^-m / k, and the 2^64 of the pointwise product
+    u[i] = mont_mul(uv, b[KD + m], q, qn);
+  });
+  return ntt_crt_tail<KD, W, U>(u, tb, m);
+}
+
+// The FFT-based product as a twiddle multiplier: x r^rot times a constant y
+// whose three transforms are tabulated (spec[i k + m]: lane m's value of the
+// forward transform of A y modulo prime i, as ntt_fwd_lanes leaves it), so
+// only x is transformed.  xs: the lane's digit of x r^rot before its sign
+// (digit (m - rot) mod k of x), neg: that digit enters negated (r^k = -1).
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_ntt_spec(uint64_t xs, bool neg, const uint64_t* __restrict__ spec,
+                                            const uint64_t* __restrict__ tb, int l, int m) {
+  uint64_t u[3];
+  static_for<3>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const uint64_t q = tb[i], qn = tb[3 + i];
+    const uint64_t* b = tb + NTT_HEAD + 3 * KD * i;
+    uint64_t xv = mont_mul(xs, b[m], q, qn);
+    if (neg) xv = xv ? q - xv : 0ull;
+    xv = ntt_fwd_lanes<KD>(xv, b, q, qn, l, m);
+    const uint64_t uv = ntt_inv_lanes<KD>(mont_mul(xv, spec[i * KD + m], q, qn), b, q, qn, l, m);
+    u[i] = mont_mul(uv, b[KD + m], q, qn);
+  });
+  return ntt_crt_tail<KD, W, U>(u, tb, m);
+}
+
+// x w r^rot with w's transforms tabulated (spec) and x's digits in place:
+// lane m fetches digit (m - rot) mod k of x from the lane holding it.
+template <int KD, int W, int U>
+__device__ __forceinline__ L96 mul_twiddle_ntt(uint64_t x, const uint64_t* __restrict__ spec,
+                                               const uint64_t* __restrict__ tb, int rot, int l, int m) {
+  const RotLane<KD> rl = rot_lane<KD>(rot, m);
+  const uint64_t xs = lane_xchg<KD>(x, Geo<KD>::lane_of(l, rl.src));
+  return mul_ntt_spec<KD, W, U>(xs, rl.flip, spec, tb, l, m);
 }
 
 // ------------------------------------------------------------------------

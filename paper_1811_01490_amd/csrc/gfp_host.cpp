@@ -2,6 +2,7 @@
 // twiddle tables, pass scheduling and the C ABI declared in include/gfp.h.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -45,6 +46,15 @@ struct DevTables {
   uint64_t* inv_raw = nullptr;
   uint64_t* fwd2_raw = nullptr;
   uint64_t* inv2_raw = nullptr;
+  // k >= 32, built on the first transform that selects the FFT-based twiddle
+  // product: the transforms of every entry of fwd, inv, fwd2, inv2, inv_s,
+  // inv2_s (3k u64 per entry; see ntt_spectrum)
+  uint64_t* fwd_spec = nullptr;
+  uint64_t* inv_spec = nullptr;
+  uint64_t* fwd2_spec = nullptr;
+  uint64_t* inv2_spec = nullptr;
+  uint64_t* inv_s_spec = nullptr;
+  uint64_t* inv2_s_spec = nullptr;
 };
 
 void free_tables(DevTables& t) {
@@ -59,6 +69,12 @@ void free_tables(DevTables& t) {
   (void)hipFree(t.inv_raw);
   (void)hipFree(t.fwd2_raw);
   (void)hipFree(t.inv2_raw);
+  (void)hipFree(t.fwd_spec);
+  (void)hipFree(t.inv_spec);
+  (void)hipFree(t.fwd2_spec);
+  (void)hipFree(t.inv2_spec);
+  (void)hipFree(t.inv_s_spec);
+  (void)hipFree(t.inv2_s_spec);
 }
 
 // Whether the inverse of size 2^log2n takes its 1/n from the scaled tables
@@ -77,6 +93,7 @@ struct gfp_field {
   uint64_t r = 0;
   int w = -1, u = 0;  // r = 2^w + 2^u (or 2^w - 2^-u for u < 0); w = -1: neither form
   bool gpu_shape = false;
+  bool validate = false;  // GFP_VALIDATE set at create: check inputs are canonical
   Big p, pm1;
   std::unique_ptr<Mont> mont;
   uint32_t log2max = 0;
@@ -112,25 +129,6 @@ bool scale_in_tables(const gfp_field* f, int log2n) {
   return f->k >= 32 && log2n > log2_exact(2ull * f->k);
 }
 
-// Miller-Rabin to a fixed base set (host-side sanity check of p).
-bool probable_prime(const Big& n, const Mont& M) {
-  Big nm1 = gfp::sub(n, Big(1));
-  unsigned s = gfp::ctz(nm1);
-  Big d = gfp::shr(nm1, s);
-  Big minus_one = M.to(nm1);
-  static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
-  for (uint64_t b : bases) {
-    Big x = M.pow(M.to(Big(b)), d);
-    if (gfp::cmp(x, M.one) == 0 || gfp::cmp(x, minus_one) == 0) continue;
-    bool ok = false;
-    for (unsigned i = 1; i < s; ++i) {
-      x = M.mmul(x, x);
-      if (gfp::cmp(x, minus_one) == 0) { ok = true; break; }
-    }
-    if (!ok) return false;
-  }
-  return true;
-}
 
 // canonical radix-r digits of v (0 <= v < p)
 void to_digits(const gfp_field* f, const Big& v, uint64_t* out) {
@@ -373,11 +371,48 @@ bool prime64(uint64_t n) {  // deterministic Miller-Rabin for n < 2^64
   }
   return true;
 }
-std::vector<uint64_t> ntt_constants(uint32_t k) {
-  uint64_t q[3];
+// The three word primes of the FFT-based product (the largest q < 2^62 with
+// q = 1 mod 128) and, for each, the primitive 2k-th root theta from its
+// smallest quadratic non-residue.
+void ntt_primes(uint32_t k, uint64_t q[3], uint64_t th[3]) {
   int found = 0;
   for (uint64_t c = (1ull << 62) - 127; found < 3; c -= 128)  // c = 1 (mod 128)
     if (prime64(c)) q[found++] = c;
+  for (int i = 0; i < 3; ++i) {
+    uint64_t g = 2;
+    while (powm(g, (q[i] - 1) / 2, q[i]) != q[i] - 1) ++g;
+    th[i] = powm(g, (q[i] - 1) / (2 * k), q[i]);
+  }
+}
+
+// The transforms of a twiddle y as the FFT-based twiddle product reads them:
+// for each prime, v_m = y_m theta^m mod q, then the device's forward
+// transform (decimation in frequency over the lanes: for halves k/2, ..., 1,
+// the pair (m, m + h) becomes (a + b, (a - b) w^(j k / (2h))), j = m mod h,
+// w = theta^2); out[i k + m] = lane m's value.
+void ntt_spectrum(uint32_t k, const uint64_t q[3], const uint64_t th[3], const uint64_t* y, uint64_t* out) {
+  std::vector<uint64_t> v(k), wp(k / 2);
+  for (int i = 0; i < 3; ++i) {
+    const uint64_t qq = q[i], w = mulm(th[i], th[i], qq);
+    uint64_t t = 1;
+    for (uint32_t m = 0; m < k; ++m, t = mulm(t, th[i], qq)) v[m] = mulm(y[m] % qq, t, qq);
+    wp[0] = 1;
+    for (uint32_t j = 1; j < k / 2; ++j) wp[j] = mulm(wp[j - 1], w, qq);
+    for (uint32_t h = k / 2; h >= 1; h /= 2) {
+      for (uint32_t m = 0; m < k; ++m) {
+        if (m & h) continue;
+        const uint64_t a = v[m], b = v[m | h];
+        v[m] = a + b >= qq ? a + b - qq : a + b;
+        v[m | h] = mulm(a >= b ? a - b : a + qq - b, wp[(m & (h - 1)) * (k / (2 * h))], qq);
+      }
+    }
+    std::copy(v.begin(), v.end(), out + (size_t)i * k);
+  }
+}
+
+std::vector<uint64_t> ntt_constants(uint32_t k) {
+  uint64_t q[3], thq[3];
+  ntt_primes(k, q, thq);
   std::vector<uint64_t> t(20 + 9 * k, 0);
   auto mont = [](uint64_t a, uint64_t qq) { return (uint64_t)(((u128h)(a % qq) << 64) % qq); };
   for (int i = 0; i < 3; ++i) {
@@ -386,9 +421,7 @@ std::vector<uint64_t> ntt_constants(uint32_t k) {
     for (int it = 0; it < 7; ++it) inv *= 2 - qq * inv;
     t[i] = qq;
     t[3 + i] = 0 - inv;
-    uint64_t g = 2;
-    while (powm(g, (qq - 1) / 2, qq) != qq - 1) ++g;
-    const uint64_t th = powm(g, (qq - 1) / (2 * k), qq), thi = powm(th, qq - 2, qq);
+    const uint64_t th = thq[i], thi = powm(th, qq - 2, qq);
     const uint64_t om = mulm(th, th, qq), omi = mulm(thi, thi, qq);
     const uint64_t kinv = powm(k, qq - 2, qq);
     const uint64_t r128 = mulm(mont(1, qq), mont(1, qq), qq);  // 2^128 mod q
@@ -453,6 +486,97 @@ int get_ntt(gfp_field* f, const uint64_t** out) {
   return GFP_OK;
 }
 
+// Transforms of the entries w^j (scaled by sm), j < cnt, for the FFT-based
+// twiddle product (3k u64 per entry).
+void build_spec_table(const gfp_field* f, const Big& wm, uint64_t cnt, std::vector<uint64_t>& out,
+                      const Big* sm = nullptr) {
+  const uint32_t k = f->k;
+  uint64_t q[3], th[3];
+  ntt_primes(k, q, th);
+  out.assign(cnt * 3 * k, 0);
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (cnt < 1024) nth = 1;
+  const uint64_t chunk = (cnt + nth - 1) / nth;
+  std::vector<std::thread> ths;
+  for (unsigned t = 0; t < nth; ++t) {
+    const uint64_t lo = t * chunk, hi = std::min(cnt, lo + chunk);
+    if (lo >= hi) break;
+    ths.emplace_back([&, lo, hi]() {
+      const Mont& M = *f->mont;
+      Big acc = M.pow(wm, Big(lo));
+      if (sm) acc = M.mmul(acc, *sm);
+      std::vector<uint64_t> dg(k);
+      for (uint64_t j = lo; j < hi; ++j) {
+        to_digits(f, M.from(acc), dg.data());
+        ntt_spectrum(k, q, th, dg.data(), &out[j * 3 * k]);
+        acc = M.mmul(acc, wm);
+      }
+    });
+  }
+  for (auto& x : ths) x.join();
+}
+
+// The tables of get_tables plus, for the FFT-based twiddle product (k >= 32),
+// their transforms (built and uploaded on the first call for n on the
+// device, without the field lock held).
+int get_spec_tables(gfp_field* f, uint64_t n, const DevTables** out) {
+  if (f->k < 32) return GFP_EUNSUPPORTED;
+  int rc = get_tables(f, n, out);
+  if (rc != GFP_OK) return rc;
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return hip_status(he);
+  {
+    std::lock_guard<std::mutex> g(f->mu);
+    if ((*out)->fwd_spec) return GFP_OK;
+  }
+  const uint64_t cnt = n / (2ull * f->k);
+  const Mont& M = *f->mont;
+  const Big ninv_m = M.pow(M.to(Big(n)), gfp::sub(f->p, Big(2)));
+  DevTables sp;
+  std::vector<uint64_t> host;
+  build_spec_table(f, root_mont(f, n, false), cnt, host);
+  rc = upload(host, &sp.fwd_spec);
+  if (rc == GFP_OK) {
+    build_spec_table(f, root_mont(f, n, true), cnt, host);
+    rc = upload(host, &sp.inv_spec);
+  }
+  if (rc == GFP_OK && n >= 4ull * f->k * f->k) {
+    build_spec_table(f, root_mont(f, n / (2ull * f->k), false), cnt, host);
+    rc = upload(host, &sp.fwd2_spec);
+    if (rc == GFP_OK) {
+      build_spec_table(f, root_mont(f, n / (2ull * f->k), true), cnt, host);
+      rc = upload(host, &sp.inv2_spec);
+    }
+  }
+  if (rc == GFP_OK && scale_in_tables(f, log2_exact(n))) {
+    build_spec_table(f, root_mont(f, n, true), cnt, host, &ninv_m);
+    rc = upload(host, &sp.inv_s_spec);
+    if (rc == GFP_OK && n >= 4ull * f->k * f->k) {
+      build_spec_table(f, root_mont(f, n / (2ull * f->k), true), cnt, host, &ninv_m);
+      rc = upload(host, &sp.inv2_s_spec);
+    }
+  }
+  if (rc != GFP_OK) {
+    free_tables(sp);
+    return rc;
+  }
+  std::lock_guard<std::mutex> g(f->mu);
+  DevTables& t = f->tables[std::make_pair(dev, n)];
+  if (t.fwd_spec) {  // another thread built them meanwhile
+    free_tables(sp);
+  } else {
+    t.fwd_spec = sp.fwd_spec;
+    t.inv_spec = sp.inv_spec;
+    t.fwd2_spec = sp.fwd2_spec;
+    t.inv2_spec = sp.inv2_spec;
+    t.inv_s_spec = sp.inv_s_spec;
+    t.inv2_s_spec = sp.inv2_s_spec;
+  }
+  *out = &t;
+  return GFP_OK;
+}
+
 // Stream-ordered scratch when the caller passes no workspace.
 struct Scratch {
   void* p = nullptr;
@@ -479,6 +603,16 @@ int get_workspace(void* ws, uint64_t ws_bytes, uint64_t need, hipStream_t st, Sc
   return GFP_OK;
 }
 
+// GFP_VALIDATE: GFP_EINVAL when any of the n elements of the digit-major
+// vector x is not canonical (synchronises the stream).
+int validate_input(const gfp_field* f, const uint64_t* x, uint64_t ld, uint64_t n, hipStream_t st) {
+  if (!f->validate || n == 0) return GFP_OK;
+  uint64_t bad = 0;
+  const int rc = gfp_check_canonical(f, x, ld, n, st, &bad);
+  if (rc != GFP_OK) return rc;
+  return bad ? GFP_EINVAL : GFP_OK;
+}
+
 // Vector view for the pass scheduler: digit d of element i of vector v at
 // base[v * vs + i * se + d * sd].
 struct VecView {
@@ -501,10 +635,14 @@ int batch_class(uint64_t nvec) { return nvec <= 1 ? 0 : nvec < 8 ? 1 : nvec < 64
 
 // Launch codes: 1 = one pass, 2 = two passes fused (two blocks per
 // workgroup), 3 = two passes fused, eight blocks per workgroup ("wide").
-enum { LC_ONE = 1, LC_PAIR = 2, LC_WIDE = 3 };
-int code_passes(int c) { return c == LC_ONE ? 1 : 2; }
-char code_char(int c) { return c == LC_WIDE ? 'w' : (char)('0' + c); }
-int char_code(char c) { return c == '1' ? LC_ONE : c == '2' ? LC_PAIR : c == 'w' ? LC_WIDE : 0; }
+// 4 = one pass whose twiddles are multiplied with the FFT-based product of
+// section 3.3 (k >= 32).
+enum { LC_ONE = 1, LC_PAIR = 2, LC_WIDE = 3, LC_NTT = 4 };
+int code_passes(int c) { return (c == LC_ONE || c == LC_NTT) ? 1 : 2; }
+char code_char(int c) { return c == LC_WIDE ? 'w' : c == LC_NTT ? 'n' : (char)('0' + c); }
+int char_code(char c) {
+  return c == '1' ? LC_ONE : c == '2' ? LC_PAIR : c == 'w' ? LC_WIDE : c == 'n' ? LC_NTT : 0;
+}
 
 // The plan covers the e radix-K passes (after the radix-R pass, if any).
 bool plan_valid(const gfp_field* f, int log2n, int e, const std::vector<int>& plan) {
@@ -512,8 +650,9 @@ bool plan_valid(const gfp_field* f, int log2n, int e, const std::vector<int>& pl
   const int lr = log2n - e * lk;
   int s = 0;
   for (int c : plan) {
-    if (c < LC_ONE || c > LC_WIDE) return false;
-    if (c != LC_ONE && !gfpk::span2_supported((int)f->k)) return false;
+    if (c < LC_ONE || c > LC_NTT) return false;
+    if (c == LC_NTT && f->k < 32) return false;
+    if ((c == LC_PAIR || c == LC_WIDE) && !gfpk::span2_supported((int)f->k)) return false;
     if (c == LC_WIDE && !gfpk::wide_supported((int)f->k)) return false;
     if (s + code_passes(c) > e) return false;
     if (c == LC_WIDE && log2n - 2 * lk - lr - s * lk < 3) return false;  // 8 blocks per twiddle base
@@ -577,6 +716,21 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
   int rc = get_tables(f, n, &t, build_tables);
   if (rc != GFP_OK) return rc;
   if (!plan_valid(f, log2n, e, plan)) return GFP_EINVAL;
+  const uint64_t* ntt = nullptr;
+  if (std::find(plan.begin(), plan.end(), (int)LC_NTT) != plan.end()) {
+    if (build_tables) {
+      rc = get_spec_tables(f, n, &t);
+      if (rc == GFP_OK) rc = get_ntt(f, &ntt);
+      if (rc != GFP_OK) return rc;
+    } else {  // look up only: the transforms and constants must exist already
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess) return GFP_EDEVICE;
+      std::lock_guard<std::mutex> g(f->mu);
+      auto it = f->consts.find(dev);
+      if (!t->fwd_spec || it == f->consts.end() || !it->second.ntt) return GFP_ENOTREADY;
+      ntt = it->second.ntt;
+    }
+  }
   const int lk = log2_exact(2ull * f->k);
   const int lr = log2n - e * lk;  // radix-R pass first when lr > 0
   // launch codes in order: 0 = the radix-R pass
@@ -620,6 +774,12 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
       p.tw = t->inv_s;
       p.tw2 = t->inv2_s;
     }
+    if (codes[i] == LC_NTT) {
+      p.ntt_mul = true;
+      p.ntt = ntt;
+      p.spec1 = (scale_tab && i == 1) ? t->inv_s_spec : (inverse ? t->inv_spec : t->fwd_spec);
+      p.spec2 = (scale_tab && i == 1) ? t->inv2_s_spec : (inverse ? t->inv2_spec : t->fwd2_spec);
+    }
     p.last = (i == nl - 1) && canonical;
     p.nvec = nvec;
     p.vin = src.vs;
@@ -661,6 +821,10 @@ int transform_entry(const gfp_field* cf, uint64_t n, const uint64_t* x, uint64_t
   hipStream_t st = (hipStream_t)stream;
   const uint64_t need = 2ull * n * f->k * 8;
   if (no_alloc && (!ws || ws_bytes < need)) return GFP_EINVAL;
+  if (!no_alloc) {
+    rc = validate_input(f, x, ldx, n, st);
+    if (rc != GFP_OK) return rc;
+  }
   Scratch s;
   uint64_t* w = nullptr;
   rc = get_workspace(ws, ws_bytes, need, st, s, &w);
@@ -720,20 +884,34 @@ int copy_out(gfp_field* f, const std::vector<gfpk::CopyDesc>& d, const uint64_t*
 // 2^18 elements on, slower below, where that launch is latency bound).
 constexpr uint64_t kFuseProductElems = 1ull << 18;
 
-int polymul_chunk(gfp_field* f, int log2n, int e, const PolyReq* r, uint64_t C, uint64_t* ws, hipStream_t st) {
+// dev_desc != nullptr: r is unused and the copies read their descriptors
+// from device memory instead (dev_desc[0, 2C): the operands a then b,
+// dev_desc[2C, 3C): the products), so the launches do not depend on the
+// requests and a captured sequence serves any chunk of C requests.
+int polymul_chunk(gfp_field* f, int log2n, int e, const PolyReq* r, uint64_t C, uint64_t* ws, hipStream_t st,
+                  const gfpk::CopyDesc* dev_desc = nullptr) {
   const uint64_t n = 1ull << log2n, k = f->k;
   const uint64_t vw = n * k;  // words per vector
   uint64_t* A = ws;
   uint64_t* F = A + 2 * C * vw;
   uint64_t* W1 = F + 2 * C * vw;
   uint64_t* W2 = W1 + 2 * C * vw;
-  std::vector<gfpk::CopyDesc> din(2 * C), dout(C);
-  for (uint64_t i = 0; i < C; ++i) {
-    din[i] = gfpk::CopyDesc{r[i].a, nullptr, r[i].la, r[i].lda};
-    din[C + i] = gfpk::CopyDesc{r[i].b, nullptr, r[i].lb, r[i].ldb};
-    dout[i] = gfpk::CopyDesc{nullptr, r[i].c, r[i].la + r[i].lb - 1, r[i].ldc};
+  std::vector<gfpk::CopyDesc> din, dout;
+  if (!dev_desc) {
+    din.resize(2 * C);
+    dout.resize(C);
+    for (uint64_t i = 0; i < C; ++i) {
+      din[i] = gfpk::CopyDesc{r[i].a, nullptr, r[i].la, r[i].lda};
+      din[C + i] = gfpk::CopyDesc{r[i].b, nullptr, r[i].lb, r[i].ldb};
+      dout[i] = gfpk::CopyDesc{nullptr, r[i].c, r[i].la + r[i].lb - 1, r[i].ldc};
+    }
   }
-  int rc = copy_in(f, din, A, n, st);
+  auto copy_out_any = [&](const uint64_t* src) -> int {
+    if (dev_desc) return hip_status(gfpk::launch_unpad_dev((int)k, dev_desc + 2 * C, (uint32_t)C, src, n, st));
+    return copy_out(f, dout, src, n, st);
+  };
+  int rc = dev_desc ? hip_status(gfpk::launch_pad_dev((int)k, dev_desc, (uint32_t)(2 * C), A, n, st))
+                    : copy_in(f, din, A, n, st);
   // forward transforms of all 2C operands in one launch per pass; the last
   // pass leaves congruent (not canonical) digits for the pointwise product
   const VecView em{A, k, 1, vw}, fm{F, k, 1, vw};
@@ -744,7 +922,7 @@ int polymul_chunk(gfp_field* f, int log2n, int e, const PolyReq* r, uint64_t C, 
     // launch, into A (free once the forward transforms are done)
     rc = run_transform(f, log2n, e, true, fm, em, C, true, W1, W2, st, F + C * vw);
     if (rc != GFP_OK) return rc;
-    return copy_out(f, dout, A, n, st);
+    return copy_out_any(A);
   }
   // small chunks: the first inverse launch has too few groups to hide the
   // extra loads, so the product is a launch of its own (memory bound)
@@ -766,7 +944,7 @@ int polymul_chunk(gfp_field* f, int log2n, int e, const PolyReq* r, uint64_t C, 
   if (he != hipSuccess) return hip_status(he);
   rc = run_transform(f, log2n, e, true, em, fm, C, true, W1, W2, st);
   if (rc != GFP_OK) return rc;
-  return copy_out(f, dout, F, n, st);
+  return copy_out_any(F);
 }
 
 int check_req(const gfp_field* f, const PolyReq& q) {
@@ -850,6 +1028,33 @@ int transform_noalloc(const gfp_field* f, uint64_t n, int inverse, const uint64_
                       uint64_t ldy, void* scratch, uint64_t scratch_bytes, void* stream) {
   return transform_entry(f, n, x, ldx, y, ldy, scratch, scratch_bytes, stream, inverse != 0, true);
 }
+
+uint64_t polymul_chunk_bytes(const gfp_field* f, uint64_t n, uint64_t C) { return chunk_words(n, f->k, C) * 8; }
+
+int capture_polymul_chunk(const gfp_field* cf, uint64_t n, uint64_t C, uint64_t* ws, const CopyDesc* dev_desc,
+                          hipStream_t st, hipGraphExec_t* out) {
+  gfp_field* f = const_cast<gfp_field*>(cf);
+  if (!f || !ws || !dev_desc || !out || C == 0 || !st) return GFP_EINVAL;
+  if (!f->gpu_shape) return GFP_EUNSUPPORTED;
+  int log2n, e;
+  int rc = check_size(f, n, &log2n, &e);
+  if (rc != GFP_OK) return rc;
+  const DevTables* t = nullptr;
+  rc = get_tables(f, n, &t);  // outside the capture: building them synchronises
+  if (rc != GFP_OK) return rc;
+  hipError_t he = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (he != hipSuccess) return hip_status(he);
+  rc = polymul_chunk(f, log2n, e, nullptr, C, ws, st, dev_desc);
+  hipGraph_t g = nullptr;
+  he = hipStreamEndCapture(st, &g);
+  if (rc != GFP_OK || he != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc != GFP_OK ? rc : hip_status(he);
+  }
+  he = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return hip_status(he);
+}
 }  // namespace gfpk
 
 extern "C" {
@@ -862,6 +1067,8 @@ int gfp_field_create(uint32_t k, uint64_t r, gfp_field** out) {
   if (!f) return GFP_ENOMEM;
   f->k = k;
   f->r = r;
+  const char* v = getenv("GFP_VALIDATE");
+  f->validate = v && *v && strcmp(v, "0") != 0;
   // r = 2^w + 2^u (u > 0), or r = 2^w - 2^-u (u < 0) ?
   if (__builtin_popcountll(r) == 2) {
     f->u = __builtin_ctzll(r);
@@ -880,7 +1087,7 @@ int gfp_field_create(uint32_t k, uint64_t r, gfp_field** out) {
   f->pm1 = rk;
   f->p = gfp::add(rk, Big(1));
   f->mont.reset(new Mont(f->p));
-  if (!probable_prime(f->p, *f->mont)) {
+  if (!gfp::bpsw(f->p)) {
     delete f;
     return GFP_ENOTPRIME;
   }
@@ -979,21 +1186,27 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   const int lk = log2_exact(2ull * f->k);
   const int lr = log2n - e * lk;
   const int total = e + (lr > 0 ? 1 : 0);  // passes: the radix-R one first, if any
-  if (s < 0 || s >= total || (flags & ~15)) return GFP_EINVAL;
+  if (s < 0 || s >= total || (flags & ~31)) return GFP_EINVAL;
   const bool radix_r = lr > 0 && s == 0;
   const int sk = s - (lr > 0 ? 1 : 0);  // index among the radix-K passes
   const bool wide = (flags & GFP_PASS_WIDE) != 0;
   const int span = (wide || (flags & GFP_PASS_PAIR)) ? 2 : 1;
   if (span == 2 && (radix_r || s + 1 >= total || !gfpk::span2_supported((int)f->k))) return GFP_EINVAL;
   if (wide && !gfpk::wide_supported((int)f->k)) return GFP_EINVAL;
+  const bool nttm = (flags & GFP_PASS_NTT) != 0;
+  if (nttm && (f->k < 32 || span != 1 || radix_r)) return GFP_EINVAL;
   if (wide && log2n - 2 * lk - lr - sk * lk < 3) return GFP_EINVAL;
   const bool in_em = (flags & GFP_PASS_IN_ELEMENT_MAJOR) != 0;
   const bool out_em = (flags & GFP_PASS_OUT_ELEMENT_MAJOR) != 0;
   if ((!in_em && ld_x < n) || (!out_em && ld_y < n)) return GFP_EINVAL;
   const DevTables* t = nullptr;
-  rc = get_tables(f, n, &t);
+  rc = nttm ? get_spec_tables(f, n, &t) : get_tables(f, n, &t);
   if (rc != GFP_OK) return rc;
   gfpk::PassArgs p;
+  if (nttm) {
+    rc = get_ntt(f, &p.ntt);
+    if (rc != GFP_OK) return rc;
+  }
   p.in = x;
   p.se_in = in_em ? f->k : 1;
   p.sd_in = in_em ? 1 : ld_x;
@@ -1015,6 +1228,11 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   if (scale_tab && s == 1) {
     p.tw = t->inv_s;
     p.tw2 = t->inv2_s;
+  }
+  if (nttm) {
+    p.ntt_mul = true;
+    p.spec1 = (scale_tab && s == 1) ? t->inv_s_spec : (p.inverse ? t->inv_spec : t->fwd_spec);
+    p.spec2 = (scale_tab && s == 1) ? t->inv2_s_spec : (p.inverse ? t->inv2_spec : t->fwd2_spec);
   }
   p.span = span;
   p.wide = wide;
@@ -1060,6 +1278,9 @@ int gfp_polymul(const gfp_field* cf, const uint64_t* a, uint64_t la, uint64_t ld
   int log2n, e;
   check_size(f, N, &log2n, &e);
   hipStream_t st = (hipStream_t)stream;
+  rc = validate_input(f, a, ld_a, la, st);
+  if (rc == GFP_OK) rc = validate_input(f, b, ld_b, lb, st);
+  if (rc != GFP_OK) return rc;
   Scratch s;
   uint64_t* w = nullptr;
   rc = get_workspace(workspace, ws_bytes, chunk_words(N, f->k, 1) * 8, st, s, &w);
@@ -1188,6 +1409,11 @@ int gfp_polymul_batched(const gfp_field* cf, uint32_t n, const gfp_polymul_desc*
   hipStream_t st = (hipStream_t)stream;
   const bool graph = (flags & GFP_BATCH_GRAPH) != 0;
   if (graph && (!st || !workspace)) return GFP_EINVAL;
+  for (uint32_t i = 0; f->validate && i < n; ++i) {
+    rc = validate_input(f, d[i].a, d[i].ld_a, d[i].la, st);
+    if (rc == GFP_OK) rc = validate_input(f, d[i].b, d[i].ld_b, d[i].lb, st);
+    if (rc != GFP_OK) return rc;
+  }
   // twiddle tables are uploaded synchronously: do it before any capture
   for (const auto& g : plan.groups) {
     const DevTables* t;
@@ -1267,6 +1493,9 @@ int gfp_elementwise(const gfp_field* cf, int op, const uint64_t* x, uint64_t ld_
   if (ld_x < n || ld_z < n || (needs_y && ld_y < n)) return GFP_EINVAL;
   if (n == 0) return GFP_OK;
   hipStream_t st = (hipStream_t)stream;
+  int rc = validate_input(f, x, ld_x, n, st);
+  if (rc == GFP_OK && needs_y) rc = validate_input(f, y, ld_y, n, st);
+  if (rc != GFP_OK) return rc;
   const uint32_t* cst = nullptr;
   Scratch cs;
   if (needs_c) {
@@ -1387,7 +1616,7 @@ int gfp_tune(gfp_field* f, uint64_t n, uint64_t nvec, int layout, void* stream, 
       if (plan_valid(f, log2n, e, cur)) cands.push_back(cur);
       return;
     }
-    for (int c = LC_ONE; c <= LC_WIDE; ++c) {
+    for (int c = LC_ONE; c <= LC_NTT; ++c) {
       if (s + code_passes(c) > e) continue;
       cur.push_back(c);
       gen(s + code_passes(c));

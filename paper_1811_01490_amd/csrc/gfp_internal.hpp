@@ -44,6 +44,13 @@ struct PassArgs {
   // groups take different twiddles stage them through LDS from these
   const uint64_t* twr1 = nullptr;
   const uint64_t* twr2 = nullptr;
+  // k >= 32, MODE_PLAIN passes: multiply the twiddles with the FFT-based
+  // product (section 3.3) using their tabulated transforms (spec1 for the
+  // table of tw, spec2 for tw2; 3k u64 per entry) and the constants ntt
+  bool ntt_mul = false;
+  const uint64_t* spec1 = nullptr;
+  const uint64_t* spec2 = nullptr;
+  const uint64_t* ntt = nullptr;
   // set with scale (inverse pass 0): the pass input is the pointwise product
   // in[i] in2[i] of two transforms; in2 has the strides of in and its digits
   // contiguous (sd_in 1), and the product is then multiplied by tw[0]
@@ -81,6 +88,12 @@ constexpr uint32_t kCopyBatch = 48;
 hipError_t launch_pad(int k, const CopyDesc* host_d, uint32_t nvec, uint64_t* work, uint64_t n, hipStream_t st);
 hipError_t launch_unpad(int k, const CopyDesc* host_d, uint32_t nvec, const uint64_t* work, uint64_t n,
                         uint64_t maxlen, hipStream_t st);
+// The same with the descriptors in device memory (dev_desc[0, nvec)); unpad
+// needs n a power of two.
+hipError_t launch_pad_dev(int k, const CopyDesc* dev_desc, uint32_t nvec, uint64_t* work, uint64_t n,
+                          hipStream_t st);
+hipError_t launch_unpad_dev(int k, const CopyDesc* dev_desc, uint32_t nvec, const uint64_t* work, uint64_t n,
+                            hipStream_t st);
 
 // integer products (gfp_bigint.hip)
 hipError_t launch_bigint_split(const uint64_t* a, uint64_t na, uint64_t* A, uint64_t la, int k, int b, int ua,
@@ -123,5 +136,17 @@ int prepare_tables(const gfp_field* f, uint64_t n);
 // nothing on the device.
 int transform_noalloc(const gfp_field* f, uint64_t n, int inverse, const uint64_t* x, uint64_t ldx, uint64_t* y,
                       uint64_t ldy, void* scratch, uint64_t scratch_bytes, void* stream);
+
+// Products of C requests of transform size n as a graph for the request
+// loop: the launch sequence of one chunk of gfp_polymul_batched (pad, forward
+// transforms, pointwise product, inverse transform, unpad) on workspace ws
+// (polymul_chunk_bytes(f, n, C) bytes), captured on stream st with the copy
+// descriptors read from dev_desc (3C entries: operands a, operands b,
+// products; an entry with len 0 copies nothing), so that replaying it after
+// rewriting dev_desc computes any C requests of that size.  The size's
+// twiddle tables are built before the capture if needed.
+uint64_t polymul_chunk_bytes(const gfp_field* f, uint64_t n, uint64_t C);
+int capture_polymul_chunk(const gfp_field* f, uint64_t n, uint64_t C, uint64_t* ws, const CopyDesc* dev_desc,
+                          hipStream_t st, hipGraphExec_t* out);
 
 }  // namespace gfpk

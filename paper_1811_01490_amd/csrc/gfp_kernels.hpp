@@ -239,12 +239,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16
 // output u2 by r^(t1 u2) and stores it, semi-normalised, to LDS.  Round B:
 // for u2 = w and w + 4, DFT_8 over t1 and output u = u2 + 8 u1 goes to
 // (j - a) K + a + u Ns.
-template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2>
+// NTTM: the pass twiddles are multiplied with the FFT-based product of
+// section 3.3 (mul_twiddle_ntt), their transforms read from spec (the table
+// of w^j) and spec2 (of w^(K i)), instead of the schoolbook column product.
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2, bool NTTM>
 __global__ __launch_bounds__(256) void k_pass_k32(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
                                                   uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out,
                                                   uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
-                                                  const uint32_t* __restrict__ tw2, int log2n, int log2ns,
-                                                  uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout) {
+                                                  const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ spec,
+                                                  const uint64_t* __restrict__ spec2, const uint64_t* __restrict__ ntb,
+                                                  int log2n, int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin,
+                                                  uint64_t vout) {
   static_assert(KD == 32, "the split base case is built for k = 32");
   typedef Geo<KD> Gm;
   constexpr int KB = Gm::KB;
@@ -284,7 +289,11 @@ __global__ __launch_bounds__(256) void k_pass_k32(const uint64_t* __restrict__ i
       } else if constexpr (T2) {
         // w^(a t N / (K Ns)) = entry (a t) N / (K^2 Ns) of the w^(K i) table
         const int sh2 = log2n - 2 * LOGKB - log2ns;
-        v[t2] = (log2ns == 0) ? l96(x) : mul_entry<KD, W, U>(x, tw2 + ((a * t) << sh2) * TwLayout<KD>::WORDS, m);
+        if constexpr (NTTM) {
+          v[t2] = (log2ns == 0) ? l96(x) : mul_twiddle_ntt<KD, W, U>(x, spec2 + ((a * t) << sh2) * (3 * KD), ntb, 0, l, m);
+        } else {
+          v[t2] = (log2ns == 0) ? l96(x) : mul_entry<KD, W, U>(x, tw2 + ((a * t) << sh2) * TwLayout<KD>::WORDS, m);
+        }
       } else {
         if (log2ns == 0) {
           v[t2] = l96(x);
@@ -294,7 +303,11 @@ __global__ __launch_bounds__(256) void k_pass_k32(const uint64_t* __restrict__ i
           const int rho = (int)(at >> log2ns);
           const uint64_t c = at & (ns - 1);
           const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
-          v[t2] = mul_twiddle<KD, W, U>(x, tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
+          if constexpr (NTTM) {
+            v[t2] = mul_twiddle_ntt<KD, W, U>(x, spec + (c << shift) * (3 * KD), ntb, rot, l, m);
+          } else {
+            v[t2] = mul_twiddle<KD, W, U>(x, tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
+          }
         }
       }
     });
@@ -343,12 +356,14 @@ __global__ __launch_bounds__(256) void k_pass_k32(const uint64_t* __restrict__ i
 // multiplies output u2 by r^(t1 u2) and stores it to LDS (64 KiB).  Round B:
 // for u2 = w and w + 4, DFT_16 over t1 (root r^8); output u2 + 8 u1 goes to
 // (j - a) K + a + u Ns.
-template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2>
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2, bool NTTM>
 __global__ __launch_bounds__(256) void k_pass_k64(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
                                                   uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out,
                                                   uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
-                                                  const uint32_t* __restrict__ tw2, int log2n, int log2ns,
-                                                  uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout) {
+                                                  const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ spec,
+                                                  const uint64_t* __restrict__ spec2, const uint64_t* __restrict__ ntb,
+                                                  int log2n, int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin,
+                                                  uint64_t vout) {
   static_assert(KD == 64, "the split base case is built for k = 64");
   typedef Geo<KD> Gm;
   constexpr int KB = Gm::KB;
@@ -383,7 +398,11 @@ __global__ __launch_bounds__(256) void k_pass_k64(const uint64_t* __restrict__ i
         v[t2] = first_slot<KD, W, U, MODE>(x, in2 + e * se_in, tw, l, m);
       } else if constexpr (T2) {
         const int sh2 = log2n - 2 * LOGKB - log2ns;
-        v[t2] = (log2ns == 0) ? l96(x) : mul_entry<KD, W, U>(x, tw2 + ((a * t) << sh2) * TwLayout<KD>::WORDS, m);
+        if constexpr (NTTM) {
+          v[t2] = (log2ns == 0) ? l96(x) : mul_twiddle_ntt<KD, W, U>(x, spec2 + ((a * t) << sh2) * (3 * KD), ntb, 0, l, m);
+        } else {
+          v[t2] = (log2ns == 0) ? l96(x) : mul_entry<KD, W, U>(x, tw2 + ((a * t) << sh2) * TwLayout<KD>::WORDS, m);
+        }
       } else {
         if (log2ns == 0) {
           v[t2] = l96(x);
@@ -393,7 +412,11 @@ __global__ __launch_bounds__(256) void k_pass_k64(const uint64_t* __restrict__ i
           const int rho = (int)(at >> log2ns);
           const uint64_t c = at & (ns - 1);
           const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
-          v[t2] = mul_twiddle<KD, W, U>(x, tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
+          if constexpr (NTTM) {
+            v[t2] = mul_twiddle_ntt<KD, W, U>(x, spec + (c << shift) * (3 * KD), ntb, rot, l, m);
+          } else {
+            v[t2] = mul_twiddle<KD, W, U>(x, tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
+          }
         }
       }
     });
@@ -914,23 +937,34 @@ hipError_t launch_pass_k32_t(const PassArgs& p, hipStream_t st) {
   const uint64_t groups = p.ngroups * p.nvec;
   const unsigned nb = (unsigned)((groups + 1) / 2);  // two groups per workgroup
   if (nb == 0) return hipSuccess;
-#define GFP_LAUNCH32(INV, MODE, LAST, T2)                                                                         \
-  hipLaunchKernelGGL((k_pass_k32<KD, W, U, INV, MODE, LAST, T2>), dim3(nb), dim3(256), 0, st, p.in, p.in2, p.se_in, \
-                     p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.log2n, p.log2ns, p.ngroups, p.nvec, p.vin,  \
-                     p.vout)
+#define GFP_LAUNCH32(INV, MODE, LAST, T2, NTTM)                                                                    \
+  hipLaunchKernelGGL((k_pass_k32<KD, W, U, INV, MODE, LAST, T2, NTTM>), dim3(nb), dim3(256), 0, st, p.in, p.in2,     \
+                     p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.spec1, p.spec2, p.ntt, p.log2n,      \
+                     p.log2ns, p.ngroups, p.nvec, p.vin, p.vout)
   const bool t2 = !p.last && p.log2n - 2 * lk - p.log2ns >= 0;
-#define GFP_LAUNCH32_T(INV, MODE)                  \
-  if (p.last) GFP_LAUNCH32(INV, MODE, true, false); \
-  else if (t2) GFP_LAUNCH32(INV, MODE, false, true); \
-  else GFP_LAUNCH32(INV, MODE, false, false);
+  // the scaled first launch of an inverse (a constant factor, MODE_SCALE or
+  // MODE_PRODUCT) keeps the schoolbook product; plain passes need the tables
+  if (p.ntt_mul && !p.in2 && !p.scale && (!p.spec1 || !p.ntt || (t2 && !p.spec2))) return hipErrorInvalidValue;
+#define GFP_LAUNCH32_T(INV, MODE, NTTM)                  \
+  if (p.last) GFP_LAUNCH32(INV, MODE, true, false, NTTM); \
+  else if (t2) GFP_LAUNCH32(INV, MODE, false, true, NTTM); \
+  else GFP_LAUNCH32(INV, MODE, false, false, NTTM);
   if (p.in2) {
-    GFP_LAUNCH32_T(true, MODE_PRODUCT)
+    GFP_LAUNCH32_T(true, MODE_PRODUCT, false)
   } else if (p.scale) {
-    GFP_LAUNCH32_T(true, MODE_SCALE)
+    GFP_LAUNCH32_T(true, MODE_SCALE, false)
   } else if (p.inverse) {
-    GFP_LAUNCH32_T(true, MODE_PLAIN)
+    if (p.ntt_mul) {
+      GFP_LAUNCH32_T(true, MODE_PLAIN, true)
+    } else {
+      GFP_LAUNCH32_T(true, MODE_PLAIN, false)
+    }
   } else {
-    GFP_LAUNCH32_T(false, MODE_PLAIN)
+    if (p.ntt_mul) {
+      GFP_LAUNCH32_T(false, MODE_PLAIN, true)
+    } else {
+      GFP_LAUNCH32_T(false, MODE_PLAIN, false)
+    }
   }
 #undef GFP_LAUNCH32_T
 #undef GFP_LAUNCH32
@@ -944,23 +978,34 @@ hipError_t launch_pass_k64_t(const PassArgs& p, hipStream_t st) {
   const uint64_t nb = p.ngroups * p.nvec;  // one group per workgroup
   if (nb == 0) return hipSuccess;
   if (nb > 0xFFFFFFFFull) return hipErrorInvalidValue;
-#define GFP_LAUNCH64(INV, MODE, LAST, T2)                                                                          \
-  hipLaunchKernelGGL((k_pass_k64<KD, W, U, INV, MODE, LAST, T2>), dim3((unsigned)nb), dim3(256), 0, st, p.in, p.in2, \
-                     p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.log2n, p.log2ns, p.ngroups, p.nvec, \
-                     p.vin, p.vout)
+#define GFP_LAUNCH64(INV, MODE, LAST, T2, NTTM)                                                                     \
+  hipLaunchKernelGGL((k_pass_k64<KD, W, U, INV, MODE, LAST, T2, NTTM>), dim3((unsigned)nb), dim3(256), 0, st, p.in,    \
+                     p.in2, p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.spec1, p.spec2, p.ntt, p.log2n, \
+                     p.log2ns, p.ngroups, p.nvec, p.vin, p.vout)
   const bool t2 = !p.last && p.log2n - 2 * lk - p.log2ns >= 0;
-#define GFP_LAUNCH64_T(INV, MODE)                  \
-  if (p.last) GFP_LAUNCH64(INV, MODE, true, false); \
-  else if (t2) GFP_LAUNCH64(INV, MODE, false, true); \
-  else GFP_LAUNCH64(INV, MODE, false, false);
+  // the scaled first launch of an inverse (a constant factor, MODE_SCALE or
+  // MODE_PRODUCT) keeps the schoolbook product; plain passes need the tables
+  if (p.ntt_mul && !p.in2 && !p.scale && (!p.spec1 || !p.ntt || (t2 && !p.spec2))) return hipErrorInvalidValue;
+#define GFP_LAUNCH64_T(INV, MODE, NTTM)                  \
+  if (p.last) GFP_LAUNCH64(INV, MODE, true, false, NTTM); \
+  else if (t2) GFP_LAUNCH64(INV, MODE, false, true, NTTM); \
+  else GFP_LAUNCH64(INV, MODE, false, false, NTTM);
   if (p.in2) {
-    GFP_LAUNCH64_T(true, MODE_PRODUCT)
+    GFP_LAUNCH64_T(true, MODE_PRODUCT, false)
   } else if (p.scale) {
-    GFP_LAUNCH64_T(true, MODE_SCALE)
+    GFP_LAUNCH64_T(true, MODE_SCALE, false)
   } else if (p.inverse) {
-    GFP_LAUNCH64_T(true, MODE_PLAIN)
+    if (p.ntt_mul) {
+      GFP_LAUNCH64_T(true, MODE_PLAIN, true)
+    } else {
+      GFP_LAUNCH64_T(true, MODE_PLAIN, false)
+    }
   } else {
-    GFP_LAUNCH64_T(false, MODE_PLAIN)
+    if (p.ntt_mul) {
+      GFP_LAUNCH64_T(false, MODE_PLAIN, true)
+    } else {
+      GFP_LAUNCH64_T(false, MODE_PLAIN, false)
+    }
   }
 #undef GFP_LAUNCH64_T
 #undef GFP_LAUNCH64

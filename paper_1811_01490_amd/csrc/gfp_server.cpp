@@ -14,6 +14,14 @@
 // slot configured, the last worker only takes requests of small transform
 // size (the earliest ones waiting, wherever they are in the queue), so those
 // never queue behind large ones.
+//
+// Graphs: a chunk of C requests of one class is one launch sequence that
+// depends on the requests only through the pad / unpad copy descriptors.
+// Each slot keeps a descriptor table in device memory, and per
+// (field, size, C) the sequence captured once with its copies reading that
+// table; a chunk then costs one host-to-device copy of 3C descriptors (from
+// pinned staging, a distinct region per chunk of the batch, since the copies
+// run later on the stream) and one graph launch.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <time.h>
@@ -24,7 +32,9 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -51,10 +61,19 @@ struct Request {
 struct Slot {
   hipStream_t stream = nullptr;
   std::vector<hipEvent_t> events;  // one per class of a batch, created on demand
-  uint64_t* ws = nullptr;
+  uint64_t* ws = nullptr;          // chunk workspace (after the descriptor table)
+  gfpk::CopyDesc* table = nullptr;  // device descriptor table, 3 max_batch entries
+  gfpk::CopyDesc* stage = nullptr;  // pinned host staging, 6 max_batch entries
+  std::map<std::tuple<const gfp_field*, uint64_t, uint64_t>, hipGraphExec_t> graphs;  // (field, n, C)
+  std::set<std::tuple<const gfp_field*, uint64_t, uint64_t>> seen;                    // chunk shapes met so far
+  uint64_t captures = 0, graph_launches = 0;
   bool express = false;  // takes only requests with n <= express_n
   std::thread thread;
 };
+
+// Captured chunk graphs kept per slot; beyond this the slot drops them all
+// (between batches, when its stream is idle) and captures again.
+constexpr size_t kMaxSlotGraphs = 256;
 
 // Requests of one (field, transform size) class within a batch.
 struct Class {
@@ -71,6 +90,7 @@ struct gfp_server {
   uint64_t slot_bytes = 0;
   uint64_t express_n = 0;  // 0: no express slot
   void* ws_base = nullptr;
+  void* table_base = nullptr;  // the slots' descriptor tables
   std::vector<Slot> slots;
 
   std::mutex mu;
@@ -116,6 +136,62 @@ void finish(gfp_server* s, const std::vector<uint64_t>& tickets, int status, uin
   s->st.completed += tickets.size();
 }
 
+// One class of a batch through the slot's chunk graphs: chunks of at most
+// cap requests (the rule of gfp_polymul_batched).  Where a chunk's work is
+// small (C n <= kPadElems), C is rounded up to a power of two (at most
+// max_batch, within the slot's workspace) so that few distinct graphs serve
+// all batch sizes; larger chunks keep their exact C, since padding them
+// would cost real work.  A (field, size, C) is captured the second time it
+// occurs; the first time its chunk runs eagerly, so that shapes seen once
+// cost no capture.
+constexpr uint64_t kPadElems = 1ull << 17;
+
+int run_class_graphed(gfp_server* s, Slot& sl, const Class& c, size_t& staged) {
+  const uint64_t per = gfpk::polymul_chunk_bytes(c.field, c.n, 1);
+  const uint64_t cnt = c.descs.size();
+  const uint64_t cap = std::min<uint64_t>(cnt, gfpk::chunk_cap(per));
+  for (uint64_t i = 0; i < cnt; i += cap) {
+    const uint64_t C = std::min<uint64_t>(cap, cnt - i);
+    uint64_t Cb = 1;
+    while (Cb < C) Cb <<= 1;
+    if (Cb * c.n > kPadElems || Cb > s->cfg.max_batch || gfpk::polymul_chunk_bytes(c.field, c.n, Cb) > s->slot_bytes)
+      Cb = C;
+    const auto key = std::make_tuple(c.field, c.n, Cb);
+    auto it = sl.graphs.find(key);
+    if (it == sl.graphs.end() && sl.seen.insert(key).second) {
+      // first occurrence: eager launches, no capture
+      const int rc = gfp_polymul_batched(c.field, (uint32_t)C, c.descs.data() + i, sl.ws, s->slot_bytes, 0, sl.stream);
+      if (rc != GFP_OK) return rc;
+      continue;
+    }
+    if (staged + 3 * Cb > 6ull * s->cfg.max_batch) return GFP_EINVAL;  // cannot happen: Cb <= 2C
+    gfpk::CopyDesc* h = sl.stage + staged;
+    for (uint64_t j = 0; j < Cb; ++j) {
+      if (j < C) {
+        const gfp_polymul_desc& d = c.descs[i + j];
+        h[j] = gfpk::CopyDesc{d.a, nullptr, d.la, d.ld_a};
+        h[Cb + j] = gfpk::CopyDesc{d.b, nullptr, d.lb, d.ld_b};
+        h[2 * Cb + j] = gfpk::CopyDesc{nullptr, d.c, d.la + d.lb - 1, d.ld_c};
+      } else {  // padding entries: zero operands, nothing written back
+        h[j] = h[Cb + j] = h[2 * Cb + j] = gfpk::CopyDesc{nullptr, nullptr, 0, 0};
+      }
+    }
+    staged += 3 * Cb;
+    if (it == sl.graphs.end()) {
+      hipGraphExec_t ex = nullptr;
+      int rc = gfpk::capture_polymul_chunk(c.field, c.n, Cb, sl.ws, sl.table, sl.stream, &ex);
+      if (rc != GFP_OK) return rc;
+      it = sl.graphs.emplace(key, ex).first;
+      ++sl.captures;
+    }
+    ++sl.graph_launches;
+    if (hipMemcpyAsync(sl.table, h, 3 * Cb * sizeof(gfpk::CopyDesc), hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+      return GFP_EDEVICE;
+    if (hipGraphLaunch(it->second, sl.stream) != hipSuccess) return GFP_EDEVICE;
+  }
+  return GFP_OK;
+}
+
 // Enqueue the batch's classes on the slot's stream (smallest transform size
 // first), each followed by an event, then wait for the events in order and
 // mark each class done when its event completes.  Enqueueing runs without
@@ -128,10 +204,20 @@ void run_batch(gfp_server* s, Slot& sl, std::vector<Class>& classes, const std::
   for (void* ev : ready) {
     if (hipStreamWaitEvent(sl.stream, (hipEvent_t)ev, 0) != hipSuccess) err = GFP_EDEVICE;
   }
+  if (sl.graphs.size() > kMaxSlotGraphs) {
+    // the stream is idle between batches, so no graph is still running
+    for (auto& g : sl.graphs) (void)hipGraphExecDestroy(g.second);
+    sl.graphs.clear();
+    sl.seen.clear();
+  }
+  const bool graphs = !(s->cfg.flags & GFP_SERVER_EAGER);
+  size_t staged = 0;  // host staging entries used by this batch
   for (size_t i = 0; i < classes.size(); ++i) {
     if (err == GFP_OK) {
       Class& c = classes[i];
-      err = gfp_polymul_batched(c.field, (uint32_t)c.descs.size(), c.descs.data(), sl.ws, s->slot_bytes, 0, sl.stream);
+      err = graphs ? run_class_graphed(s, sl, c, staged)
+                   : gfp_polymul_batched(c.field, (uint32_t)c.descs.size(), c.descs.data(), sl.ws, s->slot_bytes, 0,
+                                         sl.stream);
     }
     rc[i] = err;
     while (sl.events.size() <= i) {
@@ -235,10 +321,13 @@ void worker(gfp_server* s, size_t idx) {
     if (!s->queue.empty()) s->cv_work.notify_all();  // let other free slots take the rest
     lk.unlock();
 
+    const uint64_t cap0 = sl.captures, gl0 = sl.graph_launches;
     run_batch(s, sl, classes, ready);
 
     lk.lock();
     --s->in_flight;
+    s->st.graph_captures += sl.captures - cap0;
+    s->st.graph_launches += sl.graph_launches - gl0;
   }
 }
 
@@ -250,10 +339,13 @@ bool valid_request(const gfp_request* q) {
 
 void release(gfp_server* s) {
   for (auto& sl : s->slots) {
+    for (auto& g : sl.graphs) (void)hipGraphExecDestroy(g.second);
     for (hipEvent_t e : sl.events) (void)hipEventDestroy(e);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.stage) (void)hipHostFree(sl.stage);
   }
   if (s->ws_base) (void)hipFree(s->ws_base);
+  if (s->table_base) (void)hipFree(s->table_base);
   delete s;
 }
 
@@ -270,8 +362,11 @@ int gfp_server_create(const gfp_server_config* cfg, gfp_server** out) {
   if (c.max_batch == 0) c.max_batch = 256;
   if (c.max_pending == 0) c.max_pending = 65536;
   if (c.slots > 64 || c.express_log2n > 40 || (c.express_log2n && c.slots < 2)) return GFP_EINVAL;
-  // slot shares are multiples of 256 bytes
+  if (c.max_batch > 65535 || (c.flags & ~(uint32_t)GFP_SERVER_EAGER)) return GFP_EINVAL;
+  // slot shares are multiples of 256 bytes; the descriptor tables are
+  // allocated beside the workspace
   const uint64_t slot_bytes = (c.workspace_bytes / c.slots) & ~255ull;
+  const uint64_t table_bytes = (3ull * c.max_batch * sizeof(gfpk::CopyDesc) + 255) & ~255ull;
   if (slot_bytes == 0) return GFP_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return GFP_EDEVICE;
@@ -291,12 +386,23 @@ int gfp_server_create(const gfp_server_config* cfg, gfp_server** out) {
     s->ws_base = nullptr;
     rc = GFP_ENOMEM;
   }
+  if (rc == GFP_OK && hipMalloc(&s->table_base, table_bytes * c.slots) != hipSuccess) {
+    s->table_base = nullptr;
+    rc = GFP_ENOMEM;
+  }
   s->express_n = c.express_log2n ? (1ull << c.express_log2n) : 0;
   s->slots.resize(c.slots);
   for (uint32_t i = 0; rc == GFP_OK && i < c.slots; ++i) {
     Slot& sl = s->slots[i];
+    sl.table = (gfpk::CopyDesc*)((char*)s->table_base + i * table_bytes);
     sl.ws = (uint64_t*)((char*)s->ws_base + i * slot_bytes);
     sl.express = c.express_log2n && i + 1 == c.slots;
+    if (hipHostMalloc((void**)&sl.stage, 6ull * c.max_batch * sizeof(gfpk::CopyDesc), hipHostMallocDefault) !=
+        hipSuccess) {
+      sl.stage = nullptr;
+      rc = GFP_ENOMEM;
+      break;
+    }
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
       sl.stream = nullptr;
       rc = GFP_EDEVICE;

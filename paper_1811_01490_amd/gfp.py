@@ -32,6 +32,7 @@ STATIC_SCRATCH_BYTES = 32 << 20
 
 OP_ADD, OP_SUB, OP_MUL, OP_MUL_POW_R, OP_MUL_CONST, OP_MUL_SCALE, OP_MUL_NTT = range(7)
 BATCH_GRAPH = 1
+SERVER_EAGER = 1
 LAYOUT_DIGIT_MAJOR, LAYOUT_ELEMENT_MAJOR = 0, 1
 
 
@@ -45,7 +46,7 @@ class ServerConfig(ctypes.Structure):
     """gfp_server_config"""
     _fields_ = [("workspace_bytes", ctypes.c_uint64), ("slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
                 ("max_pending", ctypes.c_uint32), ("max_wait_us", ctypes.c_uint32), ("device", ctypes.c_int32),
-                ("express_log2n", ctypes.c_uint32)]
+                ("express_log2n", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class Request(ctypes.Structure):
@@ -70,7 +71,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("max_batch_size", ctypes.c_uint64),
                 ("max_batch_workspace", ctypes.c_uint64), ("overlapped_batches", ctypes.c_uint64),
-                ("slot_bytes", ctypes.c_uint64)]
+                ("slot_bytes", ctypes.c_uint64), ("graph_launches", ctypes.c_uint64),
+                ("graph_captures", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -254,7 +256,7 @@ class Field:
             return _vec(t, self.k, n, name)
         px, ldx = ptr(x, in_element_major, "x")
         py, ldy = ptr(y, out_element_major, "y")
-        flags = (1 if in_element_major else 0) | (2 if out_element_major else 0) | {"1": 0, "2": 4, "w": 8}[code]
+        flags = (1 if in_element_major else 0) | (2 if out_element_major else 0) | {"1": 0, "2": 4, "w": 8, "n": 16}[code]
         _check(lib().gfp_fft_pass(self._h, n, s, int(inverse), flags, px, ldx, py, ldy, _stream(stream)),
                "gfp_fft_pass")
         return y
@@ -368,8 +370,9 @@ class Server:
     stream; otherwise they must be ready when submit is called."""
 
     def __init__(self, workspace_bytes: int, slots: int = 2, max_batch: int = 256, max_pending: int = 65536,
-                 max_wait_us: int = 0, device: int = -1, express_log2n: int = 0):
-        cfg = ServerConfig(workspace_bytes, slots, max_batch, max_pending, max_wait_us, device, express_log2n)
+                 max_wait_us: int = 0, device: int = -1, express_log2n: int = 0, graphs: bool = True):
+        cfg = ServerConfig(workspace_bytes, slots, max_batch, max_pending, max_wait_us, device, express_log2n,
+                           0 if graphs else SERVER_EAGER)
         h = _vp()
         _check(lib().gfp_server_create(ctypes.byref(cfg), ctypes.byref(h)), "gfp_server_create")
         self._h = h

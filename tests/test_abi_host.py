@@ -104,6 +104,10 @@ def test_server_argument_errors():
     assert L.gfp_server_create(ctypes.byref(tiny), ctypes.byref(h)) == gfp.GFP_EINVAL
     many = gfp.ServerConfig(1 << 30, 65, 16, 64, 0, -1, 0)
     assert L.gfp_server_create(ctypes.byref(many), ctypes.byref(h)) == gfp.GFP_EINVAL
+    flags = gfp.ServerConfig(1 << 30, 2, 16, 64, 0, -1, 0, 6)  # unknown flag bits
+    assert L.gfp_server_create(ctypes.byref(flags), ctypes.byref(h)) == gfp.GFP_EINVAL
+    big = gfp.ServerConfig(1 << 30, 2, 70000, 64, 0, -1, 0)
+    assert L.gfp_server_create(ctypes.byref(big), ctypes.byref(h)) == gfp.GFP_EINVAL
     t = ctypes.c_uint64()
     r = gfp.Result()
     assert L.gfp_server_submit(None, None, ctypes.byref(t)) == gfp.GFP_EINVAL

@@ -179,4 +179,4 @@ def test_tuner_picks_a_valid_plan(torch_mod):
     plan16, _ = Field(**P16).tune(32768, nvec=2, layout=1)
     assert plan16 in compositions(3, 15, 0, 5)  # fused pairs, no wide pair for k = 16
     plan32, _ = Field(k=32, r=2 ** 62 + 2 ** 56).tune(2 ** 18)
-    assert plan32 == "111"  # one pass per launch for k = 32
+    assert len(plan32) == 3 and set(plan32) <= {"1", "n"}  # one pass per launch for k = 32, either multiplier

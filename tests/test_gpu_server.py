@@ -295,3 +295,39 @@ def test_mixed_batch_completes_small_class_first(torch_mod, fields, sleep_cycles
     assert rs["t_done_ns"] <= rl["t_done_ns"]
     _check_alone(f, large[2], large[3], cl)
     _check_alone(f, small[2], small[3], cs)
+
+
+def test_graph_replay_matches_eager_and_alone(torch_mod, fields):
+    """Batches run as replayed chunk graphs (the default) give the same
+    products as eagerly launched batches and as each product alone, also when
+    a graph captured for one chunk is replayed for later chunks of the same
+    (field, size, count) with other operands, and when the count is rounded
+    up to a power of two (padding entries copy nothing)."""
+    import torch
+
+    from paper_1811_01490_amd import Server, to_host
+
+    g = gi.rng(SEED, 9)
+    rounds = []
+    for rnd in range(3):
+        reqs = []
+        for i in range(3 + rnd * 2):  # 3, 5, 7 requests: counts rounded up to 4 and 8
+            params = P8 if i % 2 == 0 else P16
+            la, lb = int(g.integers(100, 2000)), int(g.integers(100, 2000))
+            a, b, da, db = _operands(params, la, lb, 300 + 20 * rnd + i)
+            reqs.append((params, da, db, _out(torch, params["k"], la + lb - 1), _out(torch, params["k"], la + lb - 1)))
+        rounds.append(reqs)
+    torch.cuda.synchronize()
+    with Server(workspace_bytes=1 << 30, slots=1, max_batch=64, max_wait_us=20000) as gsrv, \
+            Server(workspace_bytes=1 << 30, slots=1, max_batch=64, max_wait_us=20000, graphs=False) as esrv:
+        for reqs in rounds + rounds:  # every round twice: the second time replays its graphs
+            tg = [gsrv.submit(fields[p["k"]], da, db, cg) for p, da, db, cg, ce in reqs]
+            te = [esrv.submit(fields[p["k"]], da, db, ce) for p, da, db, cg, ce in reqs]
+            assert all(r["status"] == 0 for r in [gsrv.wait(t) for t in tg] + [esrv.wait(t) for t in te])
+            for p, da, db, cg, ce in reqs:
+                got = to_host(cg)
+                assert np.array_equal(got, to_host(ce))
+                assert np.array_equal(got, _check_alone(fields[p["k"]], da, db, cg))
+                cg.fill_(-1)
+                ce.fill_(-1)
+            torch.cuda.synchronize()
