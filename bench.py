@@ -466,6 +466,50 @@ def element_leg(torch, dev, n: int, reps: int):
             "paper_units": "as printed in the paper's Table multiplication (10^-6 s scale, serial CPU)", "rows": rows}
 
 
+def twiddle_multiplier_leg(torch, dev, reps: int = 10):
+    """The two twiddle multipliers inside the transforms of the k = 32 and
+    k = 64 primes of Table 1: every plan of one pass per launch, each pass
+    with the schoolbook column product ('1') or the FFT-based product of
+    section 3.3 ('n', twiddle transforms tabulated); forward transforms at
+    N = 2^20 (k = 64) and 2^18 (k = 32), outputs compared with the
+    schoolbook plan."""
+    import gfp_inputs as gi
+    from paper_1811_01490_amd import Field, to_device
+
+    rows = []
+    for k, r, label, n in ((64, 2 ** 63 - 2 ** 40, "2^63-2^40", 1 << 20), (32, 2 ** 62 + 2 ** 56, "2^62+2^56", 1 << 18)):
+        f = Field(k, r)
+        lk = (2 * k).bit_length() - 1
+        e = (n.bit_length() - 1) // lk
+        x = to_device(gi.uniform_digits(k, r, n, gi.BASE_SEED + 8, 0), dev)
+        y = torch.empty_like(x)
+        ws = torch.empty(f.fft_workspace_size(n) // 8, dtype=torch.int64, device=dev)
+        plans = [""]
+        for _ in range(e):
+            plans = [p + c for p in plans for c in "1n"]
+        ref = None
+        for plan in plans:
+            f.set_plan(n, plan)
+            f.fft_forward(x, y=y, workspace=ws)  # builds the twiddle transforms on the first 'n' plan
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                f.fft_forward(x, y=y, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            same = True
+            if ref is None:
+                ref = y.clone()
+            else:
+                same = bool(torch.equal(y, ref))
+            rows.append({"k": k, "r": label, "N": n, "plan": plan, "forward_us": round(e0.elapsed_time(e1) / reps * 1e3, 1),
+                         "identical_to_schoolbook": same})
+        f.close()
+    return {"workload": "forward transforms, uniform random coefficients (seed 1811014908), plans '1' (schoolbook "
+                        "twiddle product) and 'n' (FFT-based twiddle product) per pass", "rows": rows}
+
+
 # The paper's FFT timings (Table fftoverprimefield, FFT-based column, serial
 # CPU, machine unstated, units inferred as ms) for its test primes (Table
 # testprimes).
@@ -688,6 +732,7 @@ def main():
         out["paper_context"] = paper_context_leg(torch, dev)
     if not args.no_element:
         out["element_products"] = element_leg(torch, dev, 1 << args.element_log2, 20)
+        out["twiddle_multipliers"] = twiddle_multiplier_leg(torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_reps)
     print(json.dumps(out), flush=True)

@@ -116,6 +116,15 @@ struct gfp_field {
   // pass, 2: fused pair, 3: wide fused pair), set by gfp_plan_set /
   // gfp_tune; keys without an entry use default_plan
   std::map<std::tuple<int, int, int>, std::vector<int>> plans;
+  // side streams (default priority) for the size classes of a batched
+  // product, per device, with their join events and the fork event
+  struct Side {
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
+  };
+  std::mutex side_mu;
+  std::map<int, Side> side;
 };
 
 namespace {
@@ -127,6 +136,15 @@ int log2_exact(uint64_t n) {
 
 bool scale_in_tables(const gfp_field* f, int log2n) {
   return f->k >= 32 && log2n > log2_exact(2ull * f->k);
+}
+
+// Per-group twiddles go through LDS from the raw-digit tables for transforms
+// of at least 2^18 elements per vector times vectors (measured on MI355X: the
+// k = 8 last pass at 2^20 67.5 -> 56.4 us), and are read whole by each lane
+// from the limb tables below that, where the staging's longer chain per slot
+// costs more than it saves (k = 16 at 2^15: 72.7 against 68.4 us).
+bool staged_twiddles(const gfp_field* f, int log2n, uint64_t nvec) {
+  return f->k <= 16 && (nvec << log2n) >= (1ull << 18);
 }
 
 
@@ -770,6 +788,7 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
     p.tw2 = inverse ? t->inv2 : t->fwd2;
     p.twr1 = inverse ? t->inv_raw : t->fwd_raw;
     p.twr2 = inverse ? t->inv2_raw : t->fwd2_raw;
+    p.staged = staged_twiddles(f, log2n, nvec);
     if (scale_tab && i == 1) {  // 1/n rides on this launch's twiddle tables
       p.tw = t->inv_s;
       p.tw2 = t->inv2_s;
@@ -962,10 +981,11 @@ struct BatchPlan {
   struct Group {
     int log2n, e;
     std::vector<PolyReq> reqs;
-    uint64_t cap;  // requests per chunk
+    uint64_t cap;         // requests per chunk
+    uint64_t ws_off = 0;  // its workspace region (words), used chunk after chunk
   };
   std::vector<Group> groups;  // ascending size
-  uint64_t ws_words = 0;
+  uint64_t ws_words = 0;      // the regions of all groups, which run concurrently
 };
 
 int plan_batch(gfp_field* f, uint32_t n, const gfp_polymul_desc* d, BatchPlan& plan) {
@@ -994,20 +1014,69 @@ int plan_batch(gfp_field* f, uint32_t n, const gfp_polymul_desc* d, BatchPlan& p
   for (auto& g : plan.groups) {
     const uint64_t per = chunk_words(1ull << g.log2n, f->k, 1) * 8;
     g.cap = std::min<uint64_t>(g.reqs.size(), gfpk::chunk_cap(per));
-    plan.ws_words = std::max(plan.ws_words, chunk_words(1ull << g.log2n, f->k, g.cap));
+    g.ws_off = plan.ws_words;
+    plan.ws_words += chunk_words(1ull << g.log2n, f->k, g.cap);
   }
   return GFP_OK;
 }
 
-int enqueue_batch(gfp_field* f, const BatchPlan& plan, uint64_t* ws, hipStream_t st) {
-  for (const auto& g : plan.groups) {
-    for (size_t i = 0; i < g.reqs.size(); i += g.cap) {
-      const uint64_t C = std::min<uint64_t>(g.cap, g.reqs.size() - i);
-      int rc = polymul_chunk(f, g.log2n, g.e, g.reqs.data() + i, C, ws, st);
-      if (rc != GFP_OK) return rc;
-    }
+int enqueue_group(gfp_field* f, const BatchPlan::Group& g, uint64_t* ws, hipStream_t st) {
+  for (size_t i = 0; i < g.reqs.size(); i += g.cap) {
+    const uint64_t C = std::min<uint64_t>(g.cap, g.reqs.size() - i);
+    int rc = polymul_chunk(f, g.log2n, g.e, g.reqs.data() + i, C, ws + g.ws_off, st);
+    if (rc != GFP_OK) return rc;
   }
   return GFP_OK;
+}
+
+// The size classes of a batch are independent: each runs on a side stream of
+// its own, forked from `st` by an event and joined back into it, so that the
+// small classes' launches overlap the large ones' instead of waiting behind
+// them (under stream capture the forks become parallel graph branches).
+int enqueue_batch(gfp_field* f, const BatchPlan& plan, uint64_t* ws, hipStream_t st) {
+  if (plan.groups.size() == 1) return enqueue_group(f, plan.groups[0], ws, st);
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return hip_status(he);
+  std::lock_guard<std::mutex> lk(f->side_mu);  // the side streams and events serve one enqueue at a time
+  gfp_field::Side& sd = f->side[dev];
+  while (sd.streams.size() < plan.groups.size()) {
+    hipStream_t s2 = nullptr;
+    hipEvent_t e2 = nullptr;
+    he = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&e2, hipEventDisableTiming);
+    if (he != hipSuccess) {
+      if (s2) (void)hipStreamDestroy(s2);
+      return hip_status(he);
+    }
+    sd.streams.push_back(s2);
+    sd.joins.push_back(e2);
+  }
+  if (!sd.fork) {
+    he = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming);
+    if (he != hipSuccess) return hip_status(he);
+  }
+  he = hipEventRecord(sd.fork, st);
+  if (he != hipSuccess) return hip_status(he);
+  int rc = GFP_OK;
+  size_t forked = 0;
+  for (size_t j = 0; j < plan.groups.size(); ++j) {
+    he = hipStreamWaitEvent(sd.streams[j], sd.fork, 0);
+    if (he != hipSuccess) {
+      rc = hip_status(he);
+      break;
+    }
+    ++forked;
+    rc = enqueue_group(f, plan.groups[j], ws, sd.streams[j]);
+    if (rc != GFP_OK) break;
+  }
+  // join every forked stream back, also after an error (a capture must end joined)
+  for (size_t j = 0; j < forked; ++j) {
+    he = hipEventRecord(sd.joins[j], sd.streams[j]);
+    if (he == hipSuccess) he = hipStreamWaitEvent(st, sd.joins[j], 0);
+    if (he != hipSuccess && rc == GFP_OK) rc = hip_status(he);
+  }
+  return rc;
 }
 
 uint64_t hash_bytes(uint64_t h, const void* p, size_t n) {
@@ -1134,7 +1203,13 @@ int gfp_field_destroy(gfp_field* f) {
     (void)hipFree(kv.second.ntt);
   }
   for (auto& kv : f->graphs) (void)hipGraphExecDestroy(kv.second.exec);
-  if (!f->tables.empty() || !f->consts.empty()) (void)hipSetDevice(dev);
+  for (auto& kv : f->side) {
+    (void)hipSetDevice(kv.first);
+    for (hipStream_t s2 : kv.second.streams) (void)hipStreamDestroy(s2);
+    for (hipEvent_t e2 : kv.second.joins) (void)hipEventDestroy(e2);
+    if (kv.second.fork) (void)hipEventDestroy(kv.second.fork);
+  }
+  if (!f->tables.empty() || !f->consts.empty() || !f->side.empty()) (void)hipSetDevice(dev);
   delete f;
   return GFP_OK;
 }
@@ -1225,6 +1300,7 @@ int gfp_fft_pass(const gfp_field* cf, uint64_t n, int s, int inverse, int flags,
   p.tw2 = p.inverse ? t->inv2 : t->fwd2;
   p.twr1 = p.inverse ? t->inv_raw : t->fwd_raw;
   p.twr2 = p.inverse ? t->inv2_raw : t->fwd2_raw;
+  p.staged = staged_twiddles(f, log2n, 1);
   if (scale_tab && s == 1) {
     p.tw = t->inv_s;
     p.tw2 = t->inv2_s;

@@ -44,6 +44,9 @@ struct PassArgs {
   // groups take different twiddles stage them through LDS from these
   const uint64_t* twr1 = nullptr;
   const uint64_t* twr2 = nullptr;
+  // per-group twiddles through the raw-digit tables and LDS (large
+  // transforms) rather than whole limb-table entries read by every lane
+  bool staged = false;
   // k >= 32, MODE_PLAIN passes: multiply the twiddles with the FFT-based
   // product (section 3.3) using their tabulated transforms (spec1 for the
   // table of tw, spec2 for tw2; 3k u64 per entry) and the constants ntt

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16
     const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2, uint64_t se_in, uint64_t sd_in,
     uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
     const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1, const uint64_t* __restrict__ twr2, int log2n,
-    int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout) {
+    int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout, int staged) {
   typedef Geo<KD> Gm;
   constexpr bool LN = Gm::LEAN || !UNIF;
   constexpr int KB = Gm::KB;
@@ -178,6 +178,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16
         const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
         v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
       });
+    } else if (!staged) {
+      // per-group twiddles, each lane reading the whole entry from the limb
+      // tables (small transforms: shorter latency per slot than staging)
+      if constexpr (T2) {
+        const int sh2 = log2n - 2 * LOGKB - log2ns;
+        static_for<KB - 1>([&](auto T) {
+          constexpr int t = decltype(T)::value + 1;
+          v[t] = mul_entry<KD, W, U, LN>(x[t], tw2 + ((a * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS, m);
+        });
+      } else {
+        const int shift = log2n - log2ns - LOGKB;
+        static_for<KB - 1>([&](auto T) {
+          constexpr int t = decltype(T)::value + 1;
+          const uint64_t e = a * (uint64_t)t;
+          const int rho = (int)(e >> log2ns);
+          const uint64_t c = e & (ns - 1);
+          const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
+          v[t] = mul_twiddle<KD, W, U, LN>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
+        });
+      }
     } else {
       // per-group twiddles: staged through LDS from the raw-digit tables, the
       // next slot's digit fetched before this slot's product
@@ -532,7 +552,7 @@ __global__ __launch_bounds__(Span2Geo<KD>::THREADS) void k_pass2(const uint64_t*
                                                const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
                                                const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1,
                                                const uint64_t* __restrict__ twr2, int log2n, int log2ns, uint64_t nvec,
-                                               uint64_t vin, uint64_t vout) {
+                                               uint64_t vin, uint64_t vout, int staged) {
   static_assert(KD == 8 || KD == 16, "the fused pass pair is built for k = 8 and 16");
   typedef Geo<KD> Gm;
   typedef Span2Geo<KD> SG;
@@ -610,11 +630,30 @@ __global__ __launch_bounds__(Span2Geo<KD>::THREADS) void k_pass2(const uint64_t*
   const uint64_t ns1 = ns << LOGKB;
   const uint64_t a1 = a + (t1 << log2ns);
   v[0] = l96(x[0]);
-  // per-group twiddles, staged through LDS from the raw-digit tables
+  // per-group twiddles, staged through LDS from the raw-digit tables (or, for
+  // small transforms, read whole by each lane from the limb tables)
   __shared__ uint32_t stg[SG::WAVES * StageGeo<KD>::PER_WAVE];
   uint32_t* E = stg + wv * StageGeo<KD>::PER_WAVE + g * StageGeo<KD>::WORDS;
-  stage_init<KD>(E, m);
-  if constexpr (T2B) {
+  if (!staged) {
+    if constexpr (T2B) {
+      const int sh2 = log2n - 2 * LOGKB - log2ns1;
+      static_for<KB - 1>([&](auto T) {
+        constexpr int t = decltype(T)::value + 1;
+        v[t] = mul_entry<KD, W, U>(x[t], tw2 + ((a1 * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS, m);
+      });
+    } else {
+      const int shift1 = log2n - log2ns1 - LOGKB;
+      static_for<KB - 1>([&](auto T) {
+        constexpr int t = decltype(T)::value + 1;
+        const uint64_t e = a1 * (uint64_t)t;
+        const int rho = (int)(e >> log2ns1);
+        const uint64_t cc = e & (ns1 - 1);
+        const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
+        v[t] = mul_twiddle<KD, W, U>(x[t], tw1 + (cc << shift1) * TwLayout<KD>::WORDS, rot, l, m);
+      });
+    }
+  } else if constexpr (T2B) {
+    stage_init<KD>(E, m);
     const int sh2 = log2n - 2 * LOGKB - log2ns1;
     uint64_t yn = twr2[(a1 << sh2) * KD + m];
     static_for<KB - 1>([&](auto T) {
@@ -625,6 +664,7 @@ __global__ __launch_bounds__(Span2Geo<KD>::THREADS) void k_pass2(const uint64_t*
       v[t] = mul_entry<KD, W, U>(x[t], E, m);
     });
   } else {
+    stage_init<KD>(E, m);
     const int shift1 = log2n - log2ns1 - LOGKB;
     uint64_t yn = twr1[((a1 & (ns1 - 1)) << shift1) * KD + m];
     static_for<KB - 1>([&](auto T) {
@@ -875,7 +915,7 @@ hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
   hipLaunchKernelGGL((k_pass2<KD, W, U, INV, MODE, LAST, T2B>), dim3(nb), dim3(Span2Geo<KD>::THREADS), 0, st, p.in, \
                      p.in2, p.se_in,                                                                                  \
                      p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.twr1, p.twr2, p.log2n, p.log2ns, p.nvec, \
-                     p.vin, p.vout)
+                     p.vin, p.vout, (int)p.staged)
 #define GFP_LAUNCH2_T(INV, MODE)                   \
   if (p.last) GFP_LAUNCH2(INV, MODE, true, false); \
   else if (t2b) GFP_LAUNCH2(INV, MODE, false, true); \
@@ -1029,7 +1069,7 @@ hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
 #define GFP_LAUNCH(INV, MODE, LAST, UNIF, T2)                                                                       \
   hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST, UNIF, T2>), dim3(nb), dim3(256), 0, st, p.in, p.in2, p.se_in,   \
                      p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.twr1, p.twr2, p.log2n, p.log2ns, p.ngroups,     \
-                     p.nvec, p.vin, p.vout)
+                     p.nvec, p.vin, p.vout, (int)p.staged)
   // uniform twiddles when every base a has at least one wavefront of groups;
   // the w^(K i) table for every pass but the last
   const int lk = ilog2(2 * KD);
