@@ -166,8 +166,9 @@ def batched_leg(torch, f, dev, reps: int):
     uniform coefficients.  The stage grouping of every (size, batch class)
     either path uses is autotuned first (gfp_tune).  Times 256 separate
     gfp_polymul calls against one gfp_polymul_batched call replayed from its
-    hipGraph, on one stream, and checks that both give the same 256
-    products."""
+    hipGraph and against the persistent batched launch (one cooperative
+    launch over a device work list), on one stream, and checks that all give
+    the same 256 products."""
     import numpy as np
 
     import gfp_inputs as gi
@@ -207,6 +208,12 @@ def batched_leg(torch, f, dev, reps: int):
     def batched():
         f.polymul_batched(descs, workspace=wsb, graph=True, stream=stream)
 
+    c_pers = [torch.empty_like(c) for c in c_plain]
+    descs_p = f.batch_descs([(a, b, c) for (a, b), c in zip(reqs, c_pers)])
+
+    def persistent():
+        f.polymul_batched(descs_p, workspace=wsb, persistent=True, stream=stream)
+
     def timed(fn):
         torch.cuda.synchronize()
         fn()
@@ -221,7 +228,9 @@ def batched_leg(torch, f, dev, reps: int):
 
     t_plain = timed(plain)
     t_batch = timed(batched)
+    t_pers = timed(persistent)
     same = all(torch.equal(x, y) for x, y in zip(c_plain, c_batch))
+    same_p = all(torch.equal(x, y) for x, y in zip(c_plain, c_pers))
     coefs = sum(a.shape[1] + b.shape[1] - 1 for a, b in reqs)
     hist = {str(n): sizes.count(n) for n in sorted(set(sizes))}
     return {
@@ -235,6 +244,8 @@ def batched_leg(torch, f, dev, reps: int):
         "batched_coeffs_per_s": round(coefs / (t_batch * 1e-3), 1),
         "plain_coeffs_per_s": round(coefs / (t_plain * 1e-3), 1),
         "identical_outputs": bool(same),
+        "persistent_ms": round(t_pers, 3),
+        "persistent_identical_outputs": bool(same_p),
         "tuned_plans": tuned,
     }
 

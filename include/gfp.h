@@ -178,7 +178,8 @@ typedef struct gfp_polymul_desc {
 } gfp_polymul_desc;
 
 /* gfp_polymul_batched flags */
-#define GFP_BATCH_GRAPH 1 /* capture the launches into a hipGraph, cache it per argument list, replay it */
+#define GFP_BATCH_GRAPH 1      /* capture the launches into a hipGraph, cache it per argument list, replay it */
+#define GFP_BATCH_PERSISTENT 2 /* k <= 16: the whole batch as one cooperative launch over a device work list */
 
 /* Workspace bytes gfp_polymul_batched needs for this request list. */
 int gfp_polymul_batched_workspace_size(const gfp_field* f, uint32_t n, const gfp_polymul_desc* d, uint64_t* bytes);
@@ -194,7 +195,14 @@ int gfp_polymul_batched_workspace_size(const gfp_field* f, uint32_t n, const gfp
  * on the first call with this exact argument list (descriptors, workspace,
  * stream) and plans, and replayed on later calls; stream must not be NULL.
  * A field keeps at most 64 such graphs; capturing another evicts the oldest
- * after synchronising the stream it was last launched on.  Results
+ * after synchronising the stream it was last launched on.
+ * flags & GFP_BATCH_PERSISTENT (k = 8 and 16 only, else GFP_EUNSUPPORTED;
+ * not with GFP_BATCH_GRAPH): one cooperative launch walks a work list of
+ * (launch, tile) items, grouped in levels separated by grid-wide barriers:
+ * pad, each pass of the forward transforms, the pointwise product, each
+ * pass of the inverse, unpad; the size classes share every level.  The list
+ * is written into the workspace tail by a stream-ordered copy before the
+ * launch, so one launch serves any number of size classes.  Results
  * do not depend on the batch composition (bit-identical to gfp_polymul).
  * Errors: GFP_EINVAL (bad descriptor, n == 0, NULL stream with
  * GFP_BATCH_GRAPH, workspace too small), GFP_EUNSUPPORTED, GFP_EDEVICE. */

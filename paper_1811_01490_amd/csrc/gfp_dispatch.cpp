@@ -15,9 +15,12 @@ namespace gfpk {
   X(32, 56, 21, 32_56_21)     \
   X(64, 63, -40, 64_63_m40)
 
-#define GFP_DECLARE(K, W, U, TAG)                                   \
-  hipError_t launch_pass_##TAG(const PassArgs& p, hipStream_t st); \
-  hipError_t launch_elementwise_##TAG(const EwArgs& a, hipStream_t st);
+#define GFP_DECLARE(K, W, U, TAG)                                                                             \
+  hipError_t launch_pass_##TAG(const PassArgs& p, hipStream_t st);                                           \
+  hipError_t launch_elementwise_##TAG(const EwArgs& a, hipStream_t st);                                      \
+  hipError_t launch_persistent_##TAG(const PLevel* levels, uint32_t nlevels, const PRec* recs, uint32_t* sync, \
+                                     uint32_t grid, hipStream_t st);                                           \
+  int persistent_capacity_##TAG(int* grid);
 GFP_FOR_EACH_SHAPE(GFP_DECLARE)
 #undef GFP_DECLARE
 
@@ -46,6 +49,24 @@ hipError_t launch_elementwise(int k, int w, int u, const EwArgs& a, hipStream_t 
   GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
 #undef GFP_SHAPE_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_persistent(int k, int w, int u, const PLevel* levels, uint32_t nlevels, const PRec* recs,
+                             uint32_t* sync, uint32_t grid, hipStream_t st) {
+#define GFP_SHAPE_CASE(K, W, U, TAG) \
+  if (k == K && w == W && u == U) return launch_persistent_##TAG(levels, nlevels, recs, sync, grid, st);
+  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
+#undef GFP_SHAPE_CASE
+  return hipErrorInvalidValue;
+}
+
+int persistent_capacity(int k, int w, int u, int* grid) {
+#define GFP_SHAPE_CASE(K, W, U, TAG) \
+  if (k == K && w == W && u == U) return persistent_capacity_##TAG(grid);
+  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
+#undef GFP_SHAPE_CASE
+  *grid = 0;
+  return 0;
 }
 
 }  // namespace gfpk

@@ -723,6 +723,10 @@ int view_layout(const VecView& X, const VecView& Y) {
   return (X.se == 1 || Y.se == 1) ? GFP_LAYOUT_DIGIT_MAJOR : GFP_LAYOUT_ELEMENT_MAJOR;
 }
 
+// While set (on this thread), run_transform_plan appends the pass arguments
+// here instead of launching (the persistent batch turns them into records).
+thread_local std::vector<gfpk::PassArgs>* t_record = nullptr;
+
 // X2 (inverse only): the transform input is the pointwise product X X2, formed
 // in the first launch (X2 has X's strides, element-major)
 int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& plan, bool inverse, VecView X,
@@ -812,8 +816,12 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
       p.wide = codes[i] == LC_WIDE;
       s += p.span;
     }
-    hipError_t he = gfpk::launch_pass((int)f->k, f->w, f->u, p, st);
-    if (he != hipSuccess) return hip_status(he);
+    if (t_record) {
+      t_record->push_back(p);
+    } else {
+      hipError_t he = gfpk::launch_pass((int)f->k, f->w, f->u, p, st);
+      if (he != hipSuccess) return hip_status(he);
+    }
     src = dst;
   }
   return GFP_OK;
@@ -985,8 +993,19 @@ struct BatchPlan {
     uint64_t ws_off = 0;  // its workspace region (words), used chunk after chunk
   };
   std::vector<Group> groups;  // ascending size
-  uint64_t ws_words = 0;      // the regions of all groups, which run concurrently
+  uint64_t ws_words = 0;      // the regions of all groups, which run concurrently, and the tail
+  // Tail of the workspace (words from tail_off): the work list of the
+  // persistent launch (levels, records, copy descriptors, barrier counters).
+  uint64_t tail_off = 0, nlevels = 0, nrecs = 0, ndesc = 0;
 };
+
+// Launches of one chunk in the persistent work list: pad, the forward
+// passes, the pointwise product, the inverse passes, unpad.
+uint64_t persist_levels_per_chunk(const gfp_field* f, int log2n, int e) {
+  const int nl = e + (log2n != e * log2_exact(2ull * f->k) ? 1 : 0);
+  return 2ull * nl + 3;
+}
+uint64_t align_words(uint64_t bytes) { return ((bytes + 255) & ~255ull) / 8; }
 
 int plan_batch(gfp_field* f, uint32_t n, const gfp_polymul_desc* d, BatchPlan& plan) {
   if (!f || !d || n == 0) return GFP_EINVAL;
@@ -1016,7 +1035,15 @@ int plan_batch(gfp_field* f, uint32_t n, const gfp_polymul_desc* d, BatchPlan& p
     g.cap = std::min<uint64_t>(g.reqs.size(), gfpk::chunk_cap(per));
     g.ws_off = plan.ws_words;
     plan.ws_words += chunk_words(1ull << g.log2n, f->k, g.cap);
+    const uint64_t chunks = (g.reqs.size() + g.cap - 1) / g.cap;
+    const uint64_t lv = chunks * persist_levels_per_chunk(f, g.log2n, g.e);
+    plan.nlevels = std::max(plan.nlevels, lv);
+    plan.nrecs += lv;
   }
+  plan.ndesc = 3ull * n;
+  plan.tail_off = plan.ws_words;
+  plan.ws_words += align_words(plan.nlevels * sizeof(gfpk::PLevel)) + align_words(plan.nrecs * sizeof(gfpk::PRec)) +
+                   align_words(plan.ndesc * sizeof(gfpk::CopyDesc)) + align_words(gfpk::kPersistSyncBytes);
   return GFP_OK;
 }
 
@@ -1077,6 +1104,172 @@ int enqueue_batch(gfp_field* f, const BatchPlan& plan, uint64_t* ws, hipStream_t
     if (he != hipSuccess && rc == GFP_OK) rc = hip_status(he);
   }
   return rc;
+}
+
+// A record of the persistent work list for one pass launch.
+int pass_record(const gfp_field* f, const gfpk::PassArgs& p, gfpk::PRec* r) {
+  uint32_t kind = 0;
+  uint64_t tiles = 0;
+  if (!gfpk::persist_pass_kind((int)f->k, p, &kind, &tiles)) return GFP_EUNSUPPORTED;
+  *r = gfpk::PRec{};
+  r->kind = kind;
+  r->log2n = p.log2n;
+  r->log2ns = p.log2ns;
+  r->lr = p.radix_log2;
+  r->staged = p.staged ? 1 : 0;
+  r->tiles = tiles;
+  r->in = p.in;
+  r->in2 = p.in2;
+  r->se_in = p.se_in;
+  r->sd_in = p.sd_in;
+  r->out = p.out;
+  r->se_out = p.se_out;
+  r->sd_out = p.sd_out;
+  r->tw = p.tw;
+  r->tw2 = p.tw2;
+  r->twr1 = p.twr1;
+  r->twr2 = p.twr2;
+  r->ngroups = p.ngroups;
+  r->nvec = p.nvec;
+  r->vin = p.vin;
+  r->vout = p.vout;
+  return GFP_OK;
+}
+
+// The records of one chunk of C products of size 2^log2n (the launches of
+// polymul_chunk with one pass per launch and the pointwise product as a
+// launch of its own), one per level, appended to seq.  dev_desc: its 3C copy
+// descriptors in device memory (operands a, operands b, products).
+int persist_chunk(gfp_field* f, int log2n, int e, uint64_t C, uint64_t* ws, const gfpk::CopyDesc* dev_desc,
+                  std::vector<gfpk::PRec>& seq) {
+  const uint64_t n = 1ull << log2n, k = f->k;
+  const uint64_t vw = n * k;
+  uint64_t* A = ws;
+  uint64_t* F = A + 2 * C * vw;
+  uint64_t* W1 = F + 2 * C * vw;
+  uint64_t* W2 = W1 + 2 * C * vw;
+  const uint64_t copy_tiles = (vw + 255) / 256;  // 256 words per tile
+  const uint64_t ew_tiles = (C * n + 4 * (64 / k) - 1) / (4 * (64 / k));
+  gfpk::PRec r{};
+  r.kind = gfpk::PK_PAD;
+  r.in = dev_desc;
+  r.out = A;
+  r.ngroups = n;
+  r.nvec = 2 * C;
+  r.tiles = 2 * C * copy_tiles;
+  seq.push_back(r);
+  const std::vector<int> ones(e, LC_ONE);
+  const VecView em{A, k, 1, vw}, fm{F, k, 1, vw};
+  std::vector<gfpk::PassArgs> fwd, inv;
+  t_record = &fwd;
+  int rc = run_transform_plan(f, log2n, e, ones, false, em, fm, 2 * C, false, W1, W2, nullptr);
+  if (rc == GFP_OK) {
+    t_record = &inv;
+    rc = run_transform_plan(f, log2n, e, ones, true, em, fm, C, true, W1, W2, nullptr);
+  }
+  t_record = nullptr;
+  if (rc != GFP_OK) return rc;
+  for (const auto& p : fwd) {
+    rc = pass_record(f, p, &r);
+    if (rc != GFP_OK) return rc;
+    seq.push_back(r);
+  }
+  r = gfpk::PRec{};
+  r.kind = gfpk::PK_MUL;
+  r.in = F;
+  r.in2 = F + C * vw;
+  r.out = A;
+  r.nvec = C * n;  // elements, C vectors back to back
+  r.tiles = ew_tiles;
+  seq.push_back(r);
+  for (const auto& p : inv) {
+    rc = pass_record(f, p, &r);
+    if (rc != GFP_OK) return rc;
+    seq.push_back(r);
+  }
+  r = gfpk::PRec{};
+  r.kind = gfpk::PK_UNPAD;
+  r.in = dev_desc + 2 * C;
+  r.in2 = F;
+  r.ngroups = n;
+  r.nvec = C;
+  r.tiles = C * copy_tiles;
+  seq.push_back(r);
+  return GFP_OK;
+}
+
+// The whole batch as one cooperative launch over a work list (k <= 16): the
+// chunks of each size class run level after level, the classes side by side
+// (level j of every class in one grid-wide step).  The list and the zeroed
+// barrier counters are copied into the workspace tail ahead of the launch,
+// in stream order.
+int enqueue_batch_persistent(gfp_field* f, const BatchPlan& plan, uint64_t* ws, hipStream_t st) {
+  if (f->k > 16) return GFP_EUNSUPPORTED;
+  int cap = 0;
+  if (gfpk::persistent_capacity((int)f->k, f->w, f->u, &cap) != 0) return GFP_EDEVICE;
+  if (cap <= 0) return GFP_EUNSUPPORTED;
+  char* tail = reinterpret_cast<char*>(ws + plan.tail_off);
+  const uint64_t lev_bytes = align_words(plan.nlevels * sizeof(gfpk::PLevel)) * 8;
+  const uint64_t rec_bytes = align_words(plan.nrecs * sizeof(gfpk::PRec)) * 8;
+  const uint64_t desc_bytes = align_words(plan.ndesc * sizeof(gfpk::CopyDesc)) * 8;
+  const gfpk::CopyDesc* ddesc = reinterpret_cast<const gfpk::CopyDesc*>(tail + lev_bytes + rec_bytes);
+  std::vector<gfpk::CopyDesc> descs;
+  descs.reserve(plan.ndesc);
+  std::vector<std::vector<gfpk::PRec>> levels(plan.nlevels);
+  for (const auto& g : plan.groups) {
+    uint64_t lvl = 0;
+    for (size_t i = 0; i < g.reqs.size(); i += g.cap) {
+      const uint64_t C = std::min<uint64_t>(g.cap, g.reqs.size() - i);
+      const size_t d0 = descs.size();
+      for (uint64_t j = 0; j < C; ++j) {
+        const PolyReq& q = g.reqs[i + j];
+        descs.push_back(gfpk::CopyDesc{q.a, nullptr, q.la, q.lda});
+      }
+      for (uint64_t j = 0; j < C; ++j) {
+        const PolyReq& q = g.reqs[i + j];
+        descs.push_back(gfpk::CopyDesc{q.b, nullptr, q.lb, q.ldb});
+      }
+      for (uint64_t j = 0; j < C; ++j) {
+        const PolyReq& q = g.reqs[i + j];
+        descs.push_back(gfpk::CopyDesc{nullptr, q.c, q.la + q.lb - 1, q.ldc});
+      }
+      std::vector<gfpk::PRec> seq;
+      int rc = persist_chunk(f, g.log2n, g.e, C, ws + g.ws_off, ddesc + d0, seq);
+      if (rc != GFP_OK) return rc;
+      for (const auto& r : seq) {
+        if (lvl >= levels.size()) return GFP_EINVAL;  // cannot happen: plan_batch counted them
+        levels[lvl++].push_back(r);
+      }
+    }
+  }
+  std::vector<gfpk::PLevel> lv;
+  std::vector<gfpk::PRec> recs;
+  uint64_t most = 0;
+  for (auto& L : levels) {
+    if (L.empty()) continue;
+    gfpk::PLevel pl{(uint32_t)recs.size(), (uint32_t)L.size(), 0};
+    for (auto& r : L) {
+      r.tile0 = pl.tiles;
+      pl.tiles += r.tiles;
+      recs.push_back(r);
+    }
+    most = std::max(most, pl.tiles);
+    lv.push_back(pl);
+  }
+  if (lv.size() > plan.nlevels || recs.size() > plan.nrecs || descs.size() > plan.ndesc) return GFP_EINVAL;
+  // the barrier counters (zeros) travel with the list
+  std::vector<char> host(lev_bytes + rec_bytes + desc_bytes + gfpk::kPersistSyncBytes, 0);
+  memcpy(host.data(), lv.data(), lv.size() * sizeof(gfpk::PLevel));
+  memcpy(host.data() + lev_bytes, recs.data(), recs.size() * sizeof(gfpk::PRec));
+  memcpy(host.data() + lev_bytes + rec_bytes, descs.data(), descs.size() * sizeof(gfpk::CopyDesc));
+  // a copy from pageable memory returns once the source has been read
+  hipError_t he = hipMemcpyAsync(tail, host.data(), host.size(), hipMemcpyHostToDevice, st);
+  if (he != hipSuccess) return hip_status(he);
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)cap, most);
+  return hip_status(gfpk::launch_persistent(
+      (int)f->k, f->w, f->u, reinterpret_cast<const gfpk::PLevel*>(tail), (uint32_t)lv.size(),
+      reinterpret_cast<const gfpk::PRec*>(tail + lev_bytes),
+      reinterpret_cast<uint32_t*>(tail + lev_bytes + rec_bytes + desc_bytes), grid, st));
 }
 
 uint64_t hash_bytes(uint64_t h, const void* p, size_t n) {
@@ -1478,7 +1671,9 @@ int gfp_polymul_batched_workspace_size(const gfp_field* cf, uint32_t n, const gf
 int gfp_polymul_batched(const gfp_field* cf, uint32_t n, const gfp_polymul_desc* d, void* workspace, uint64_t ws_bytes,
                         int flags, void* stream) {
   gfp_field* f = const_cast<gfp_field*>(cf);
-  if (flags & ~GFP_BATCH_GRAPH) return GFP_EINVAL;
+  if (flags & ~(GFP_BATCH_GRAPH | GFP_BATCH_PERSISTENT)) return GFP_EINVAL;
+  if ((flags & GFP_BATCH_GRAPH) && (flags & GFP_BATCH_PERSISTENT)) return GFP_EINVAL;
+  if ((flags & GFP_BATCH_PERSISTENT) && f && f->k > 16) return GFP_EUNSUPPORTED;
   BatchPlan plan;
   int rc = plan_batch(f, n, d, plan);
   if (rc != GFP_OK) return rc;
@@ -1500,6 +1695,7 @@ int gfp_polymul_batched(const gfp_field* cf, uint32_t n, const gfp_polymul_desc*
   uint64_t* w = nullptr;
   rc = get_workspace(workspace, ws_bytes, plan.ws_words * 8, st, s, &w);
   if (rc != GFP_OK) return rc;
+  if (flags & GFP_BATCH_PERSISTENT) return enqueue_batch_persistent(f, plan, w, st);
   if (!graph) return enqueue_batch(f, plan, w, st);
 
   uint64_t key = 1469598103934665603ull;

@@ -117,6 +117,93 @@ bool shape_supported(int k, int w, int u);
 hipError_t launch_pass(int k, int w, int u, const PassArgs& p, hipStream_t st);
 hipError_t launch_elementwise(int k, int w, int u, const EwArgs& a, hipStream_t st);
 
+// ---- one persistent launch for a batch of products ---------------------------
+// A batched product as one cooperative launch (k = 8 and 16): the launches
+// the per-class path would make (pad, the single-pass transforms, the
+// pointwise product, unpad) become records of a device work list grouped in
+// levels; every workgroup walks the tiles (virtual blocks) of a level, then
+// the grid synchronises before the next level.  Kinds of records:
+enum PersistKind : uint32_t {
+  PK_PAD = 0,          // copy-in: desc table `in` (CopyDesc), n = ngroups, nvec vectors into `out`
+  PK_UNPAD = 1,        // copy-out: desc table `in`, n = ngroups, nvec vectors from `in2`
+  PK_MUL = 2,          // elementwise product out = in * in2 over nvec elements (element-major)
+  PK_PASS_FIRST = 3,   // k_pass <fwd, plain, not last, per group, w^j table> (first or last forward pass)
+  PK_PASS_MID = 4,     // k_pass <fwd, plain, not last, uniform, w^(K i) table>
+  PK_PASS_IMID = 5,    // k_pass <inv, plain, not last, uniform, w^(K i) table>
+  PK_PASS_ILAST = 6,   // k_pass <inv, plain, last (canonical), per group>
+  PK_PASS_ISCALE = 7,  // k_pass <inv, scale, not last>
+  PK_PASS_ISCALE_LAST = 8,  // k_pass <inv, scale, last>
+  PK_PASS_R_F = 9,     // k_pass_r <fwd, plain, radix 2^lr>
+  PK_PASS_R_I = 10,    // k_pass_r <inv, scale, radix 2^lr>
+};
+
+struct PRec {
+  uint32_t kind;
+  int32_t log2n, log2ns, lr;
+  int32_t staged, pad0;
+  uint64_t tile0;  // first tile of the record in its level
+  uint64_t tiles;  // virtual blocks of the record
+  const void* in;
+  const uint64_t* in2;
+  uint64_t se_in, sd_in;
+  uint64_t* out;
+  uint64_t se_out, sd_out;
+  const uint32_t* tw;
+  const uint32_t* tw2;
+  const uint64_t* twr1;
+  const uint64_t* twr2;
+  uint64_t ngroups, nvec, vin, vout;
+};
+
+struct PLevel {
+  uint32_t rec0, nrec;  // records [rec0, rec0 + nrec)
+  uint64_t tiles;       // total tiles of the level
+};
+
+// Kind and tile count of a pass launch (the variant launch_pass_t would
+// pick) for k <= 16 single passes; false if the persistent launch does not
+// carry it (fused pairs, k >= 32, the fused pointwise product).
+inline bool persist_pass_kind(int k, const PassArgs& p, uint32_t* kind, uint64_t* tiles) {
+  if (k > 16 || p.span != 1 || p.in2 || p.ntt_mul) return false;
+  const int lk = k == 8 ? 4 : 5;
+  const int lg = k == 8 ? 3 : 2;  // log2 of the element groups per wavefront
+  const uint64_t groups_per_block = 4ull << lg;
+  if (p.radix_log2 != 0) {
+    if (p.last) return false;
+    *kind = p.inverse ? PK_PASS_R_I : PK_PASS_R_F;
+    if (p.inverse != p.scale) return false;  // the inverse's radix-R pass carries 1/n
+    *tiles = ((p.nvec << (p.log2n - p.radix_log2)) + groups_per_block - 1) / groups_per_block;
+    return true;
+  }
+  const bool unif = p.log2ns > 0 && (p.log2n - lk - p.log2ns) >= lg;
+  const bool t2 = !p.last && p.log2n - 2 * lk - p.log2ns >= 0;
+  if (p.scale) {
+    *kind = p.last ? PK_PASS_ISCALE_LAST : PK_PASS_ISCALE;
+  } else if (!p.inverse) {
+    if (p.last) return false;  // forward transforms of a product stay non-canonical
+    // not uniform: the first pass (Ns = 1, no twiddles, whichever table) or
+    // the final one (per-group twiddles of the w^j table)
+    if (unif && t2) *kind = PK_PASS_MID;
+    else if (!unif && (p.log2ns == 0 || !t2)) *kind = PK_PASS_FIRST;
+    else return false;
+  } else {
+    if (p.last) *kind = PK_PASS_ILAST;
+    else if (unif && t2) *kind = PK_PASS_IMID;
+    else return false;
+  }
+  *tiles = (p.ngroups * p.nvec + groups_per_block - 1) / groups_per_block;
+  return true;
+}
+
+// Cooperative launch of the work list (levels, recs: device memory) for the
+// radix shape (k, w, u); grid: workgroups (all resident at once); sync:
+// kPersistSyncBytes of zeros (device memory) for the level barriers.
+constexpr uint64_t kPersistSyncBytes = 64 * 128;
+hipError_t launch_persistent(int k, int w, int u, const PLevel* levels, uint32_t nlevels, const PRec* recs,
+                             uint32_t* sync, uint32_t grid, hipStream_t st);
+// Workgroups of that kernel that fit on the device at once (0 if the shape has none).
+int persistent_capacity(int k, int w, int u, int* grid);
+
 // Batched products run each transform size in chunks of requests whose
 // workspace fits kChunkBytes (at least one request per chunk); the request
 // loop sizes its batches with the same rule.

@@ -29,11 +29,19 @@ namespace gfpk {
 // its neighbour the other half) and costs 1-3% otherwise (measured), so it is
 // used only then.  A pure permutation of the work; identity when G is not a multiple
 // of 8.
-__device__ __forceinline__ uint64_t xcd_block(bool on) {
-  const uint64_t b = blockIdx.x, g = gridDim.x;
+// A kernel body runs on a virtual block: a launch's blockIdx.x of gridDim.x,
+// or one tile of a persistent launch (k_batch_persistent).
+struct VB {
+  uint64_t idx, cnt;
+};
+__device__ __forceinline__ VB launch_vb() { return VB{blockIdx.x, gridDim.x}; }
+
+__device__ __forceinline__ uint64_t xcd_block(bool on, VB vb) {
+  const uint64_t b = vb.idx, g = vb.cnt;
   if (!on || (g & 7)) return b;
   return (b & 7) * (g >> 3) + (b >> 3);
 }
+__device__ __forceinline__ uint64_t xcd_block(bool on) { return xcd_block(on, launch_vb()); }
 
 // ---------------------------------------------------------------------------
 // one radix-K Stockham pass
@@ -86,11 +94,12 @@ __device__ __forceinline__ L96 first_slot(uint64_t x, const uint64_t* __restrict
 // wavefronts per SIMD expected, so the scheduler keeps their instruction-level
 // parallelism (with fewer registers it aims at 3 and runs slower).
 template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T2>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16 && !UNIF ? 2 : 8))) void k_pass(
+__device__ __forceinline__ void pass_body(
     const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2, uint64_t se_in, uint64_t sd_in,
     uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
     const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1, const uint64_t* __restrict__ twr2, int log2n,
-    int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout, int staged) {
+    int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout, int staged, VB vb,
+    uint32_t* __restrict__ stg) {
   typedef Geo<KD> Gm;
   constexpr bool LN = Gm::LEAN || !UNIF;
   constexpr int KB = Gm::KB;
@@ -99,7 +108,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16
   const int m = Gm::digit(l);
   // A launch covers nvec transforms of the same size: vector v reads
   // in + v vin and writes out + v vout.
-  const uint64_t wave = xcd_block(se_in == 1 || se_out == 1) * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const uint64_t wave = xcd_block(se_in == 1 || se_out == 1, vb) * (blockDim.x / 64) + (threadIdx.x >> 6);
   const uint64_t nk = ngroups;  // N / K
   const int log2nk = log2n - LOGKB;
   const uint64_t ns = 1ull << log2ns;
@@ -201,7 +210,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16
     } else {
       // per-group twiddles: staged through LDS from the raw-digit tables, the
       // next slot's digit fetched before this slot's product
-      __shared__ uint32_t stg[4 * StageGeo<KD>::PER_WAVE];
       uint32_t* E = stg + (int)(threadIdx.x >> 6) * StageGeo<KD>::PER_WAVE + Gm::group(l) * StageGeo<KD>::WORDS;
       stage_init<KD>(E, m);
       if constexpr (T2) {
@@ -244,6 +252,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16
     }
     if (active) out[(uint64_t)m * sd_out + (obase + (uint64_t)t * ns) * se_out] = d;
   });
+}
+
+// stg: 4 wavefronts' LDS staging areas (StageGeo<KD>::PER_WAVE words each).
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T2>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16 && !UNIF ? 2 : 8))) void k_pass(
+    const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2, uint64_t se_in, uint64_t sd_in,
+    uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
+    const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1, const uint64_t* __restrict__ twr2, int log2n,
+    int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout, int staged) {
+  __shared__ uint32_t stg[4 * StageGeo<KD>::PER_WAVE];
+  pass_body<KD, W, U, INV, MODE, LAST, UNIF, T2>(in, in2, se_in, sd_in, out, se_out, sd_out, tw, tw2, twr1, twr2, log2n,
+                                                 log2ns, ngroups, nvec, vin, vout, staged, launch_vb(), stg);
 }
 
 // ---------------------------------------------------------------------------
@@ -483,15 +503,15 @@ __global__ __launch_bounds__(256) void k_pass_k64(const uint64_t* __restrict__ i
 // factorisation N = N1 N2 with the base case at powers of r).  MODE_SCALE
 // multiplies every element by the 1/N entry first (inverse transform).
 template <int KD, int W, int U, bool INV, int MODE, int LR>
-__global__ __launch_bounds__(256) void k_pass_r(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
-                                                uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
-                                                const uint32_t* __restrict__ tw, int log2n, uint64_t nvec,
-                                                uint64_t vin, uint64_t vout) {
+__device__ __forceinline__ void pass_r_body(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
+                                            uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out,
+                                            uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
+                                            int log2n, uint64_t nvec, uint64_t vin, uint64_t vout, VB vb) {
   typedef Geo<KD> Gm;
   constexpr int R = 1 << LR;
   const int l = Gm::lane();
   const int m = Gm::digit(l);
-  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const uint64_t wave = vb.idx * (blockDim.x / 64) + (threadIdx.x >> 6);
   const uint64_t J = wave * Gm::G + Gm::group(l);
   const int log2nr = log2n - LR;  // groups per vector
   uint64_t vec = J >> log2nr;
@@ -517,6 +537,15 @@ __global__ __launch_bounds__(256) void k_pass_r(const uint64_t* __restrict__ in,
     const uint64_t d = seminorm<KD, W, U>(v[t], m);
     if (active) out[(uint64_t)m * sd_out + (j * R + t) * se_out] = d;
   });
+}
+
+template <int KD, int W, int U, bool INV, int MODE, int LR>
+__global__ __launch_bounds__(256) void k_pass_r(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
+                                                uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
+                                                const uint32_t* __restrict__ tw, int log2n, uint64_t nvec,
+                                                uint64_t vin, uint64_t vout) {
+  pass_r_body<KD, W, U, INV, MODE, LR>(in, in2, se_in, sd_in, out, se_out, sd_out, tw, log2n, nvec, vin, vout,
+                                       launch_vb());
 }
 
 // ---------------------------------------------------------------------------
@@ -826,14 +855,14 @@ __global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in
 // elementwise operations (one element per k lanes)
 // ---------------------------------------------------------------------------
 template <int KD, int W, int U, int OP>
-__global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict__ x, uint64_t xse, uint64_t xsd,
-                                                     const uint64_t* __restrict__ y, uint64_t yse, uint64_t ysd,
-                                                     uint64_t* __restrict__ z, uint64_t zse, uint64_t zsd, uint64_t n,
-                                                     int64_t s, const uint32_t* __restrict__ cst) {
+__device__ __forceinline__ void elementwise_body(const uint64_t* __restrict__ x, uint64_t xse, uint64_t xsd,
+                                                 const uint64_t* __restrict__ y, uint64_t yse, uint64_t ysd,
+                                                 uint64_t* __restrict__ z, uint64_t zse, uint64_t zsd, uint64_t n,
+                                                 int64_t s, const uint32_t* __restrict__ cst, VB vb) {
   typedef Geo<KD> Gm;
   const int l = Gm::lane();
   const int m = Gm::digit(l);
-  const uint64_t e = ((uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * Gm::G + Gm::group(l);
+  const uint64_t e = (vb.idx * (blockDim.x / 64) + (threadIdx.x >> 6)) * Gm::G + Gm::group(l);
   const bool active = e < n;
   const uint64_t ee = active ? e : 0;
   L96 t;
@@ -860,6 +889,179 @@ __global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict_
   }
   const uint64_t d = canonicalize<KD, W, U>(t, l, m);
   if (active) z[(uint64_t)m * zsd + ee * zse] = d;
+}
+
+template <int KD, int W, int U, int OP>
+__global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict__ x, uint64_t xse, uint64_t xsd,
+                                                     const uint64_t* __restrict__ y, uint64_t yse, uint64_t ysd,
+                                                     uint64_t* __restrict__ z, uint64_t zse, uint64_t zsd, uint64_t n,
+                                                     int64_t s, const uint32_t* __restrict__ cst) {
+  elementwise_body<KD, W, U, OP>(x, xse, xsd, y, yse, ysd, z, zse, zsd, n, s, cst, launch_vb());
+}
+
+// ---------------------------------------------------------------------------
+// one persistent launch for a batch of products (k <= 16)
+// ---------------------------------------------------------------------------
+// Copies with the descriptors in device memory, on one virtual block: vector
+// v = block / tiles-per-vector, 256 words of it per block.
+__device__ __forceinline__ void pad_dev_body(const CopyDesc* __restrict__ desc, uint64_t* __restrict__ work,
+                                             uint64_t n, uint32_t k, VB vb) {
+  const uint64_t per = (n * k + 255) / 256;
+  const uint64_t v = vb.idx / per;
+  const uint64_t t = (vb.idx - v * per) * 256 + threadIdx.x;
+  if (t >= n * k) return;
+  const uint64_t i = t / k;
+  const uint32_t d = (uint32_t)(t - i * k);
+  const CopyDesc cd = desc[v];
+  work[v * n * k + t] = (i < cd.len) ? cd.src[(uint64_t)d * cd.ld + i] : 0ull;
+}
+
+__device__ __forceinline__ void unpad_dev_body(const CopyDesc* __restrict__ desc, const uint64_t* __restrict__ work,
+                                               uint64_t n, uint32_t k, VB vb) {
+  const uint64_t per = (n * k + 255) / 256;
+  const uint64_t v = vb.idx / per;
+  const uint64_t t = (vb.idx - v * per) * 256 + threadIdx.x;
+  if (t >= n * k) return;
+  const uint64_t d = t / n;
+  const uint64_t i = t - d * n;
+  const CopyDesc cd = desc[v];
+  if (i >= cd.len) return;
+  cd.dst[d * cd.ld + i] = work[v * n * k + i * k + d];
+}
+
+template <int KD, int W, int U>
+__device__ __forceinline__ void run_record(const PRec& R, uint64_t tile, uint32_t* __restrict__ stg) {
+  const VB vb{tile, R.tiles};
+  const uint64_t* in = reinterpret_cast<const uint64_t*>(R.in);
+#define GFP_PBODY(INV, MODE, LAST, UNIF, T2)                                                                        \
+  pass_body<KD, W, U, INV, MODE, LAST, UNIF, T2>(in, R.in2, R.se_in, R.sd_in, R.out, R.se_out, R.sd_out, R.tw, R.tw2, \
+                                                 R.twr1, R.twr2, R.log2n, R.log2ns, R.ngroups, R.nvec, R.vin, R.vout, \
+                                                 R.staged, vb, stg)
+  switch (R.kind) {
+    case PK_PAD:
+      pad_dev_body(reinterpret_cast<const CopyDesc*>(R.in), R.out, R.ngroups, KD, vb);
+      break;
+    case PK_UNPAD:
+      unpad_dev_body(reinterpret_cast<const CopyDesc*>(R.in), R.in2, R.ngroups, KD, vb);
+      break;
+    case PK_MUL:
+      elementwise_body<KD, W, U, GFP_OP_MUL>(in, KD, 1, R.in2, KD, 1, R.out, KD, 1, R.nvec, 0, nullptr, vb);
+      break;
+    case PK_PASS_FIRST: GFP_PBODY(false, MODE_PLAIN, false, false, false); break;
+    case PK_PASS_MID: GFP_PBODY(false, MODE_PLAIN, false, true, true); break;
+    case PK_PASS_IMID: GFP_PBODY(true, MODE_PLAIN, false, true, true); break;
+    case PK_PASS_ILAST: GFP_PBODY(true, MODE_PLAIN, true, false, false); break;
+    case PK_PASS_ISCALE: GFP_PBODY(true, MODE_SCALE, false, false, false); break;
+    case PK_PASS_ISCALE_LAST: GFP_PBODY(true, MODE_SCALE, true, false, false); break;
+    case PK_PASS_R_F:
+    case PK_PASS_R_I: {
+      const bool inv = R.kind == PK_PASS_R_I;
+#define GFP_RBODY(LR)                                                                                              \
+  if (inv) pass_r_body<KD, W, U, true, MODE_SCALE, LR>(in, R.in2, R.se_in, R.sd_in, R.out, R.se_out, R.sd_out, R.tw,  \
+                                                       R.log2n, R.nvec, R.vin, R.vout, vb);                           \
+  else pass_r_body<KD, W, U, false, MODE_PLAIN, LR>(in, R.in2, R.se_in, R.sd_in, R.out, R.se_out, R.sd_out, R.tw,     \
+                                                    R.log2n, R.nvec, R.vin, R.vout, vb)
+      if (R.lr == 1) {
+        GFP_RBODY(1);
+      } else if (R.lr == 2) {
+        GFP_RBODY(2);
+      } else if (R.lr == 3) {
+        GFP_RBODY(3);
+      } else if constexpr (KD >= 16) {
+        if (R.lr == 4) {
+          GFP_RBODY(4);
+        }
+      }
+#undef GFP_RBODY
+      break;
+    }
+    default:
+      break;
+  }
+#undef GFP_PBODY
+}
+
+// Grid-wide barrier between levels.  Each workgroup adds 1 to one of
+// kSyncLines counters (one per 128-byte line, so the arrivals spread over
+// memory channels instead of queueing on one address) after an agent-scope
+// release fence; wavefront 0 then sums the counters (one per lane) until the
+// total reaches gridDim.x (level + 1), and takes an agent-scope acquire
+// fence.  The counters start at zero (written with the work list).  Measured
+// on MI355X: 2-4x cheaper per level than the cooperative-groups grid barrier
+// (768 workgroups: 27 against 53 us), the difference being the atomics on a
+// single address.  Every workgroup is resident (cooperative launch), so every
+// wait ends; the poll count is bounded all the same.
+constexpr int kSyncLines = 64;
+constexpr int kSyncStride = 32;  // uint32 words per counter line
+__device__ __forceinline__ void level_barrier(uint32_t* __restrict__ sync, uint32_t target) {
+  __syncthreads();  // every wavefront's stores are issued and complete to L2
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(&sync[(blockIdx.x % kSyncLines) * kSyncStride], 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x < 64) {
+    for (uint32_t poll = 0; poll < (1u << 26); ++poll) {
+      uint32_t v = __hip_atomic_load(&sync[threadIdx.x * kSyncStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (v >= target) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// Every workgroup walks the tiles of a level (tile = blockIdx.x,
+// blockIdx.x + gridDim.x, ...), the records of the level in tile order, then
+// meets the others at the level barrier.  The LDS staging area is per
+// wavefront, so tiles follow each other without a workgroup barrier.
+// Registers: k = 8 at most 168 (three wavefronts per SIMD: at 128 the
+// combined bodies spill), k = 16 at most 256 (two).
+template <int KD, int W, int U>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KD == 16 ? 2 : 3, KD == 16 ? 2 : 3))) void k_batch_persistent(
+    const PLevel* __restrict__ levels, uint32_t nlevels, const PRec* __restrict__ recs, uint32_t* __restrict__ sync) {
+  static_assert(KD == 8 || KD == 16, "the persistent batch is built for k = 8 and 16");
+  __shared__ uint32_t stg[4 * StageGeo<KD>::PER_WAVE];
+  for (uint32_t L = 0; L < nlevels; ++L) {
+    const uint32_t r0 = levels[L].rec0, r1 = r0 + levels[L].nrec;
+    const uint64_t tiles = levels[L].tiles;
+    uint32_t r = r0;
+    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+      while (r + 1 < r1 && recs[r + 1].tile0 <= t) ++r;
+      run_record<KD, W, U>(recs[r], t - recs[r].tile0, stg);
+    }
+    if (L + 1 < nlevels) level_barrier(sync, gridDim.x * (L + 1));
+  }
+}
+
+template <int KD, int W, int U>
+hipError_t launch_persistent_t(const PLevel* levels, uint32_t nlevels, const PRec* recs, uint32_t* sync,
+                               uint32_t grid, hipStream_t st) {
+  if constexpr (KD != 8 && KD != 16) {
+    return hipErrorInvalidValue;
+  } else {
+    void* args[] = {(void*)&levels, (void*)&nlevels, (void*)&recs, (void*)&sync};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch_persistent<KD, W, U>), dim3(grid),
+                                      dim3(256), args, 0, st);
+  }
+}
+
+template <int KD, int W, int U>
+int persistent_capacity_t(int* grid) {
+  if constexpr (KD != 8 && KD != 16) {
+    *grid = 0;
+    return 0;
+  } else {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_batch_persistent<KD, W, U>),
+                                                     256, 0) != hipSuccess)
+      return -1;
+    *grid = per_cu * cus;
+    return 0;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -8,4 +8,10 @@ hipError_t launch_elementwise_16_58_10(const EwArgs& a, hipStream_t st) {
   return launch_elementwise_t<16, 58, 10>(a, st);
 }
 
+hipError_t launch_persistent_16_58_10(const PLevel* levels, uint32_t nlevels, const PRec* recs, uint32_t* sync,
+                                     uint32_t grid, hipStream_t st) {
+  return launch_persistent_t<16, 58, 10>(levels, nlevels, recs, sync, grid, st);
+}
+int persistent_capacity_16_58_10(int* grid) { return persistent_capacity_t<16, 58, 10>(grid); }
+
 }  // namespace gfpk

@@ -8,4 +8,10 @@ hipError_t launch_elementwise_32_62_56(const EwArgs& a, hipStream_t st) {
   return launch_elementwise_t<32, 62, 56>(a, st);
 }
 
+hipError_t launch_persistent_32_62_56(const PLevel* levels, uint32_t nlevels, const PRec* recs, uint32_t* sync,
+                                     uint32_t grid, hipStream_t st) {
+  return launch_persistent_t<32, 62, 56>(levels, nlevels, recs, sync, grid, st);
+}
+int persistent_capacity_32_62_56(int* grid) { return persistent_capacity_t<32, 62, 56>(grid); }
+
 }  // namespace gfpk

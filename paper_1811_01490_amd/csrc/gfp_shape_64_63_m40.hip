@@ -8,4 +8,10 @@ hipError_t launch_elementwise_64_63_m40(const EwArgs& a, hipStream_t st) {
   return launch_elementwise_t<64, 63, -40>(a, st);
 }
 
+hipError_t launch_persistent_64_63_m40(const PLevel* levels, uint32_t nlevels, const PRec* recs, uint32_t* sync,
+                                     uint32_t grid, hipStream_t st) {
+  return launch_persistent_t<64, 63, -40>(levels, nlevels, recs, sync, grid, st);
+}
+int persistent_capacity_64_63_m40(int* grid) { return persistent_capacity_t<64, 63, -40>(grid); }
+
 }  // namespace gfpk

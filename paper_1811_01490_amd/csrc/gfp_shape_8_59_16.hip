@@ -8,4 +8,10 @@ hipError_t launch_elementwise_8_59_16(const EwArgs& a, hipStream_t st) {
   return launch_elementwise_t<8, 59, 16>(a, st);
 }
 
+hipError_t launch_persistent_8_59_16(const PLevel* levels, uint32_t nlevels, const PRec* recs, uint32_t* sync,
+                                     uint32_t grid, hipStream_t st) {
+  return launch_persistent_t<8, 59, 16>(levels, nlevels, recs, sync, grid, st);
+}
+int persistent_capacity_8_59_16(int* grid) { return persistent_capacity_t<8, 59, 16>(grid); }
+
 }  // namespace gfpk

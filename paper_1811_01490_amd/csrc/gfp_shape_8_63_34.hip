@@ -8,4 +8,10 @@ hipError_t launch_elementwise_8_63_34(const EwArgs& a, hipStream_t st) {
   return launch_elementwise_t<8, 63, 34>(a, st);
 }
 
+hipError_t launch_persistent_8_63_34(const PLevel* levels, uint32_t nlevels, const PRec* recs, uint32_t* sync,
+                                     uint32_t grid, hipStream_t st) {
+  return launch_persistent_t<8, 63, 34>(levels, nlevels, recs, sync, grid, st);
+}
+int persistent_capacity_8_63_34(int* grid) { return persistent_capacity_t<8, 63, 34>(grid); }
+
 }  // namespace gfpk

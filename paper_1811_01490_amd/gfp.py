@@ -32,6 +32,7 @@ STATIC_SCRATCH_BYTES = 32 << 20
 
 OP_ADD, OP_SUB, OP_MUL, OP_MUL_POW_R, OP_MUL_CONST, OP_MUL_SCALE, OP_MUL_NTT = range(7)
 BATCH_GRAPH = 1
+BATCH_PERSISTENT = 2
 SERVER_EAGER = 1
 LAYOUT_DIGIT_MAJOR, LAYOUT_ELEMENT_MAJOR = 0, 1
 
@@ -293,11 +294,12 @@ class Field:
                "gfp_polymul_batched_workspace_size")
         return v.value
 
-    def polymul_batched(self, descs, workspace=None, graph=False, stream=None):
+    def polymul_batched(self, descs, workspace=None, graph=False, stream=None, persistent=False):
         wp, wb = (ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()) \
             if workspace is not None else (None, 0)
-        _check(lib().gfp_polymul_batched(self._h, len(descs), descs, wp, wb, BATCH_GRAPH if graph else 0,
-                                         _stream(stream)), "gfp_polymul_batched")
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_PERSISTENT if persistent else 0)
+        _check(lib().gfp_polymul_batched(self._h, len(descs), descs, wp, wb, flags, _stream(stream)),
+               "gfp_polymul_batched")
 
     def check_canonical(self, x, n=None, stream=None) -> int:
         """Number of elements of x (a (k, ld) device tensor) that are not

@@ -87,6 +87,12 @@ def test_error_codes():
     assert L.gfp_polymul(f.handle, ctypes.c_void_p(8), 0, 1, ctypes.c_void_p(8), 1, 1, ctypes.c_void_p(8), 1, None, 0, None) == gfp.GFP_EINVAL
     assert L.gfp_elementwise(f.handle, 99, ctypes.c_void_p(8), 1, None, 0, ctypes.c_void_p(8), 1, 1, 0, None, None) == gfp.GFP_EINVAL
     assert gfp.strerror(gfp.GFP_ENOTPRIME).startswith("r^k + 1")
+    # batched flags: unknown bits, graph together with persistent, persistent for k = 32
+    d = (gfp.PolymulDesc * 1)(gfp.PolymulDesc(8, 1, 1, 8, 1, 1, 8, 1))
+    assert L.gfp_polymul_batched(f.handle, 1, d, None, 0, 4, None) == gfp.GFP_EINVAL
+    assert L.gfp_polymul_batched(f.handle, 1, d, None, 0, gfp.BATCH_GRAPH | gfp.BATCH_PERSISTENT, None) == gfp.GFP_EINVAL
+    f32 = gfp.Field(**P32)
+    assert L.gfp_polymul_batched(f32.handle, 1, d, None, 0, gfp.BATCH_PERSISTENT, None) == gfp.GFP_EUNSUPPORTED
 
 
 def test_server_argument_errors():

@@ -1,0 +1,130 @@
+"""The persistent batched product (gfp_polymul_batched with
+GFP_BATCH_PERSISTENT): one cooperative launch over a device work list must
+give, for every request, exactly gfp_polymul's result, for mixed sizes (one
+and several chunks per size class, the radix-R first pass, transforms of
+size K), on repeated calls with other work in between."""
+
+import numpy as np
+import pytest
+
+import gfp_inputs as gi
+from oracle import transform as T
+from oracle.field import GFPField, P8, P16
+from tests.helpers import canonical_mask, to_ints
+
+pytestmark = pytest.mark.gpu
+
+K8B = dict(k=8, r=2 ** 59 + 2 ** 16)
+K16B = dict(k=16, r=2 ** 58 + 2 ** 10)
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _batch(params, sizes, seed):
+    from paper_1811_01490_amd import to_device
+
+    k, r = params["k"], params["r"]
+    reqs = []
+    for i, (la, lb) in enumerate(sizes):
+        a = gi.operand(k, r, la, seed, 2 + 2 * i, edge_frac=0.05)
+        b = gi.operand(k, r, lb, seed, 3 + 2 * i, edge_frac=0.05)
+        reqs.append((a, b))
+    dev = [(to_device(a), to_device(b)) for a, b in reqs]
+    return reqs, dev
+
+
+def _outs(torch, k, dev, fill=7):
+    return [torch.full((k, a.shape[1] + b.shape[1] - 1), fill, dtype=torch.int64, device="cuda") for a, b in dev]
+
+
+# k = 8: 16 = K (one pass), 2048 = 8 16^2 (radix-8 first pass), 4096 = 16^3;
+# k = 16: 32 = K, 256 = 8 32 (radix-8), 512 = 16 32 (radix-16), 4096 = 2 32^2
+# (radix-2), 2^15 = 32^3, 2^16 = 2 32^3.
+SIZES = {
+    8: [(1, 1), (5, 3), (8, 9), (128, 128), (300, 200), (1000, 1000), (2048, 2048), (1, 2000), (513, 512),
+        (4000, 96), (30000, 30000)] + [(7 + i, 11 + 2 * i) for i in range(12)],
+    16: [(1, 1), (16, 17), (100, 157), (300, 200), (2048, 2048), (1000, 1000), (16000, 16000), (20000, 30000), (64, 64)]
+    + [(7 + i, 11 + 2 * i) for i in range(12)],
+}
+
+
+@pytest.mark.parametrize("params", [P8, P16, K8B, K16B], ids=["k8", "k16", "k8-59-16", "k16-58-10"])
+def test_persistent_mixed_sizes(torch_mod, params):
+    import torch
+
+    from paper_1811_01490_amd import Field, to_host
+
+    F = GFPField(**params)
+    f = Field(params["k"], params["r"])
+    sizes = SIZES[params["k"]]
+    print("persistent mixed sizes", params, len(sizes), flush=True)
+    reqs, dev = _batch(params, sizes, gi.BASE_SEED + 320)
+    outs = _outs(torch, F.k, dev)
+    descs = f.batch_descs([(a, b, c) for (a, b), c in zip(dev, outs)])
+    f.polymul_batched(descs, persistent=True)
+    torch.cuda.synchronize()
+    for i, ((a, b), (da, db), c) in enumerate(zip(reqs, dev, outs)):
+        ch = to_host(c)
+        assert canonical_mask(ch, F.r).all(), i
+        assert np.array_equal(ch, to_host(f.polymul(da, db))), i
+        if a.shape[1] * b.shape[1] <= 1000 * 1000:
+            assert to_ints(ch, F.r) == T.polymul(to_ints(a, F.r), to_ints(b, F.r), F.p), i
+
+
+def test_persistent_several_chunks(torch_mod):
+    """Nine products of transform size 2^20 (eight fit a 4 GiB chunk) beside
+    small ones: the size class runs two chunks, level after level, in the
+    same launch as the small class."""
+    import torch
+
+    from paper_1811_01490_amd import Field, to_host
+
+    f = Field(P8["k"], P8["r"])
+    sizes = [(2 ** 19 - 3 * i, 2 ** 19 - 5 * i) for i in range(9)] + [(100, 60), (3, 3), (2000, 1000)]
+    print("persistent several chunks", len(sizes), flush=True)
+    _, dev = _batch(P8, sizes, gi.BASE_SEED + 321)
+    outs = _outs(torch, 8, dev)
+    descs = f.batch_descs([(a, b, c) for (a, b), c in zip(dev, outs)])
+    f.polymul_batched(descs, persistent=True)
+    torch.cuda.synchronize()
+    for i, ((da, db), c) in enumerate(zip(dev, outs)):
+        assert torch.equal(c, f.polymul(da, db)), i
+    del outs, descs
+
+
+def test_persistent_repeated_calls_with_workspace(torch_mod):
+    """Repeated calls on one stream and workspace (the work list is rewritten
+    in stream order), with eager transforms in between, and against the
+    per-class batched launches."""
+    import torch
+
+    from paper_1811_01490_amd import Field, to_device, to_host
+
+    F = GFPField(**P8)
+    f = Field(P8["k"], P8["r"])
+    sizes = [(100, 60), (2000, 2000), (20, 1), (600, 700), (3, 3), (1000, 30)]
+    reqs, dev = _batch(P8, sizes, gi.BASE_SEED + 322)
+    outs = _outs(torch, F.k, dev, fill=0)
+    ref = _outs(torch, F.k, dev, fill=0)
+    f.polymul_batched(f.batch_descs([(a, b, c) for (a, b), c in zip(dev, ref)]))
+    descs = f.batch_descs([(a, b, c) for (a, b), c in zip(dev, outs)])
+    ws = torch.empty(f.polymul_batched_workspace_size(descs) // 8 + 1, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.Stream()
+    want = [T.polymul(to_ints(a, F.r), to_ints(b, F.r), F.p) for a, b in reqs[:1]]
+    with torch.cuda.stream(stream):
+        for rep in range(4):
+            for c in outs:
+                c.zero_()
+            f.polymul_batched(descs, workspace=ws, persistent=True, stream=stream)
+            junk = to_device(gi.uniform_digits(F.k, F.r, 4096, 5, rep))
+            f.fft_forward(junk, stream=stream)
+            stream.synchronize()
+            for i, c in enumerate(outs):
+                assert torch.equal(c, ref[i]), (rep, i)
+            assert to_ints(to_host(outs[0]), F.r) == want[0]
