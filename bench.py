@@ -592,7 +592,7 @@ def main():
     ap.add_argument("--served-loads", default="0.5,0.7,0.9",
                     help="comma-separated fractions of the plain saturated rate")
     ap.add_argument("--served-workspace-gib", type=int, default=16)
-    ap.add_argument("--served-slots", type=int, default=2)
+    ap.add_argument("--served-slots", type=int, default=3)
     ap.add_argument("--served-express-log2n", type=int, default=16,
                     help="the last slot serves only transform sizes up to 2^this (0: no express slot)")
     args = ap.parse_args()
