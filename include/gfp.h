@@ -194,8 +194,9 @@ int gfp_polymul_batched_workspace_size(const gfp_field* f, uint32_t n, const gfp
  * flags & GFP_BATCH_GRAPH: the launch sequence is captured into a hipGraph
  * on the first call with this exact argument list (descriptors, workspace,
  * stream) and plans, and replayed on later calls; stream must not be NULL.
- * A field keeps at most 64 such graphs; capturing another evicts the oldest
- * after synchronising the stream it was last launched on.
+ * A field keeps at most 64 such graphs; capturing another evicts the least
+ * recently used one, after waiting (outside the field's lock) for an event
+ * recorded behind its last launch.
  * flags & GFP_BATCH_PERSISTENT (k = 8 and 16 only, else GFP_EUNSUPPORTED;
  * not with GFP_BATCH_GRAPH): one cooperative launch walks a work list of
  * (launch, tile) items, grouped in levels separated by grid-wide barriers:

@@ -102,14 +102,16 @@ struct gfp_field {
   std::mutex mu;
   std::map<std::pair<int, uint64_t>, DevTables> tables;
   std::map<int, DevConsts> consts;
-  // batched products captured as graphs, keyed by a hash of the argument
-  // list and the plan generation; at most kMaxGraphs, the oldest evicted
+  // batched products captured as graphs, keyed by the whole argument list
+  // (descriptors, workspace, stream, device) and the plan generation, found
+  // by a hash of it; at most kMaxGraphs, the least recently used evicted
   struct Graph {
+    std::string key;
     hipGraphExec_t exec;
-    hipStream_t stream;
-    uint64_t seq;
+    hipEvent_t done;  // recorded after each launch of the graph
+    uint64_t seq;     // last use
   };
-  std::map<uint64_t, Graph> graphs;
+  std::multimap<uint64_t, Graph> graphs;
   uint64_t graph_seq = 0;
   uint64_t plan_gen = 0;  // bumped by every plan change
   // stage groupings: (log2 n, batch class, layout) -> launch codes (1: one
@@ -1395,7 +1397,10 @@ int gfp_field_destroy(gfp_field* f) {
     (void)hipFree(kv.second.one);
     (void)hipFree(kv.second.ntt);
   }
-  for (auto& kv : f->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  for (auto& kv : f->graphs) {
+    (void)hipGraphExecDestroy(kv.second.exec);
+    (void)hipEventDestroy(kv.second.done);
+  }
   for (auto& kv : f->side) {
     (void)hipSetDevice(kv.first);
     for (hipStream_t s2 : kv.second.streams) (void)hipStreamDestroy(s2);
@@ -1698,25 +1703,39 @@ int gfp_polymul_batched(const gfp_field* cf, uint32_t n, const gfp_polymul_desc*
   if (flags & GFP_BATCH_PERSISTENT) return enqueue_batch_persistent(f, plan, w, st);
   if (!graph) return enqueue_batch(f, plan, w, st);
 
-  uint64_t key = 1469598103934665603ull;
-  key = hash_bytes(key, &n, sizeof(n));
-  key = hash_bytes(key, d, sizeof(gfp_polymul_desc) * n);
-  key = hash_bytes(key, &w, sizeof(w));
-  key = hash_bytes(key, &ws_bytes, sizeof(ws_bytes));
-  key = hash_bytes(key, &st, sizeof(st));
   int dev = 0;
   (void)hipGetDevice(&dev);
-  key = hash_bytes(key, &dev, sizeof(dev));
+  std::string key;
+  auto put = [&key](const void* p, size_t bytes) { key.append(reinterpret_cast<const char*>(p), bytes); };
+  put(&n, sizeof(n));
+  put(d, sizeof(gfp_polymul_desc) * n);
+  put(&w, sizeof(w));
+  put(&ws_bytes, sizeof(ws_bytes));
+  put(&st, sizeof(st));
+  put(&dev, sizeof(dev));
+  uint64_t h = 0;
+  // under f->mu: the cached graph for key, or nullptr
+  auto find = [&]() -> gfp_field::Graph* {
+    auto range = f->graphs.equal_range(h);
+    for (auto it = range.first; it != range.second; ++it)
+      if (it->second.key == key) return &it->second;
+    return nullptr;
+  };
+  // under f->mu (so that an eviction cannot destroy the graph in between)
+  auto launch = [&](gfp_field::Graph& g) -> int {
+    g.seq = ++f->graph_seq;
+    hipError_t he = hipGraphLaunch(g.exec, st);
+    if (he == hipSuccess) he = hipEventRecord(g.done, st);
+    return hip_status(he);
+  };
   {
     std::lock_guard<std::mutex> lk(f->mu);
-    key = hash_bytes(key, &f->plan_gen, sizeof(f->plan_gen));  // a new plan means a new launch sequence
-    auto it = f->graphs.find(key);
-    if (it != f->graphs.end()) {
-      // launched under the lock, so an eviction cannot destroy it in between
-      return hip_status(hipGraphLaunch(it->second.exec, st));
-    }
+    put(&f->plan_gen, sizeof(f->plan_gen));  // a new plan means a new launch sequence
+    h = hash_bytes(1469598103934665603ull, key.data(), key.size());
+    if (gfp_field::Graph* g = find()) return launch(*g);
   }
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
   {
     hipError_t he = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (he != hipSuccess) return hip_status(he);
@@ -1730,25 +1749,37 @@ int gfp_polymul_batched(const gfp_field* cf, uint32_t n, const gfp_polymul_desc*
     if (he != hipSuccess) return hip_status(he);
     he = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (he != hipSuccess) return hip_status(he);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (he != hipSuccess) {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      return hip_status(he);
+    }
+  }
+  gfp_field::Graph victim{std::string(), nullptr, nullptr, 0};
+  {
     std::lock_guard<std::mutex> lk(f->mu);
-    auto it = f->graphs.find(key);
-    if (it != f->graphs.end()) {  // another thread captured the same list meanwhile
+    if (gfp_field::Graph* g = find()) {  // another thread captured the same list meanwhile
       (void)hipGraphExecDestroy(exec);
-      return hip_status(hipGraphLaunch(it->second.exec, st));
+      (void)hipEventDestroy(done);
+      return launch(*g);
     }
     if (f->graphs.size() >= kMaxGraphs) {
-      // evict the oldest; its last launch must have finished first
       auto old = f->graphs.begin();
       for (auto j = f->graphs.begin(); j != f->graphs.end(); ++j)
         if (j->second.seq < old->second.seq) old = j;
-      (void)hipStreamSynchronize(old->second.stream);
-      (void)hipGraphExecDestroy(old->second.exec);
+      victim = old->second;
       f->graphs.erase(old);
     }
-    f->graphs.emplace(key, gfp_field::Graph{exec, st, ++f->graph_seq});
-    return hip_status(hipGraphLaunch(exec, st));
+    auto it = f->graphs.emplace(h, gfp_field::Graph{key, exec, done, 0});
+    rc = launch(it->second);
   }
+  if (victim.exec) {
+    // out of the map, so no new launch; wait for its last one without the lock
+    (void)hipEventSynchronize(victim.done);
+    (void)hipGraphExecDestroy(victim.exec);
+    (void)hipEventDestroy(victim.done);
+  }
+  return rc;
 }
 
 int gfp_elementwise(const gfp_field* cf, int op, const uint64_t* x, uint64_t ld_x, const uint64_t* y, uint64_t ld_y,

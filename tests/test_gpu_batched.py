@@ -162,3 +162,47 @@ def test_graph_cache_bound_and_plan_changes(torch_mod):
         stream.synchronize()
         for i, c in enumerate(outs):
             assert np.array_equal(to_host(c.contiguous()), ref[i]), (call, i)
+
+
+def test_graph_eviction_after_stream_destroyed(torch_mod):
+    """A graph captured on a stream the caller has since destroyed is evicted
+    (waiting on the library's own event, not on that stream), and a graph in
+    steady use stays cached (least recently used eviction) and correct."""
+    import torch
+
+    from paper_1811_01490_amd import Field, to_host
+
+    f = Field(P8["k"], P8["r"])
+    _, dev = _batch(P8, [(50, 40), (300, 20)], gi.BASE_SEED + 303)
+    ref = [to_host(f.polymul(a, b)) for a, b in dev]
+    pool = torch.zeros((8, 2 * 400 + 80), dtype=torch.int64, device="cuda")
+
+    def descs_at(off):
+        outs = []
+        for a, b in dev:
+            n = a.shape[1] + b.shape[1] - 1
+            outs.append(pool[:, off:off + n])
+            off += n
+        return outs, f.batch_descs([(a, b, c) for (a, b), c in zip(dev, outs)])
+
+    outs0, d0 = descs_at(0)
+    ws = torch.empty(f.polymul_batched_workspace_size(d0) // 8 + 1, dtype=torch.int64, device="cuda")
+    s1 = torch.cuda.Stream()
+    with torch.cuda.stream(s1):
+        f.polymul_batched(d0, workspace=ws, graph=True, stream=s1)
+    s1.synchronize()
+    del s1
+    torch.cuda.synchronize()
+    s2 = torch.cuda.Stream()
+    hot_outs, hot = descs_at(1)
+    with torch.cuda.stream(s2):
+        for call in range(70):  # 70 new lists: the s1 graph is evicted, `hot` is used between them
+            outs, d = descs_at(2 + call)
+            f.polymul_batched(d, workspace=ws, graph=True, stream=s2)
+            s2.synchronize()
+            for i, c in enumerate(outs):
+                assert np.array_equal(to_host(c.contiguous()), ref[i]), (call, i)
+            f.polymul_batched(hot, workspace=ws, graph=True, stream=s2)
+            s2.synchronize()
+            for i, c in enumerate(hot_outs):
+                assert np.array_equal(to_host(c.contiguous()), ref[i]), ("hot", call, i)
