@@ -41,6 +41,11 @@
  * gfp_check_canonical does, synchronising the stream) and return GFP_EINVAL
  * if there are any.  gfp_fft_noalloc, gfp_fft_pass, the integer products and
  * the request loop do not validate.
+ * Twiddle tables: built once per (field, device, transform size) on first
+ * use; for k <= 16 on the device (the host computes 2 sqrt(N/2k) powers of
+ * the root, a kernel the rest), unless GFP_HOST_TABLES is set (to anything
+ * but "0") at gfp_field_create, which builds them on the host as for k >= 32.
+ * Both give the same tables digit for digit.
  */
 #ifndef GFP_H
 #define GFP_H

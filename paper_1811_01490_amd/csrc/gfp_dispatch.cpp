@@ -20,7 +20,9 @@ namespace gfpk {
   hipError_t launch_elementwise_##TAG(const EwArgs& a, hipStream_t st);                                      \
   hipError_t launch_persistent_##TAG(const PLevel* levels, uint32_t nlevels, const PRec* recs, uint32_t* sync, \
                                      uint32_t grid, hipStream_t st);                                           \
-  int persistent_capacity_##TAG(int* grid);
+  int persistent_capacity_##TAG(int* grid);                                                                  \
+  hipError_t launch_table_build_##TAG(const uint64_t* lo, const uint64_t* hi, int log2b, uint64_t cnt,        \
+                                      uint32_t* tab, uint64_t* raw, hipStream_t st);
 GFP_FOR_EACH_SHAPE(GFP_DECLARE)
 #undef GFP_DECLARE
 
@@ -55,6 +57,15 @@ hipError_t launch_persistent(int k, int w, int u, const PLevel* levels, uint32_t
                              uint32_t* sync, uint32_t grid, hipStream_t st) {
 #define GFP_SHAPE_CASE(K, W, U, TAG) \
   if (k == K && w == W && u == U) return launch_persistent_##TAG(levels, nlevels, recs, sync, grid, st);
+  GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
+#undef GFP_SHAPE_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_table_build(int k, int w, int u, const uint64_t* lo, const uint64_t* hi, int log2b, uint64_t cnt,
+                              uint32_t* tab, uint64_t* raw, hipStream_t st) {
+#define GFP_SHAPE_CASE(K, W, U, TAG) \
+  if (k == K && w == W && u == U) return launch_table_build_##TAG(lo, hi, log2b, cnt, tab, raw, st);
   GFP_FOR_EACH_SHAPE(GFP_SHAPE_CASE)
 #undef GFP_SHAPE_CASE
   return hipErrorInvalidValue;

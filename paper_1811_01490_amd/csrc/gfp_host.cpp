@@ -94,6 +94,7 @@ struct gfp_field {
   int w = -1, u = 0;  // r = 2^w + 2^u (or 2^w - 2^-u for u < 0); w = -1: neither form
   bool gpu_shape = false;
   bool validate = false;  // GFP_VALIDATE set at create: check inputs are canonical
+  bool host_tables = false;  // GFP_HOST_TABLES set at create: build every twiddle table on the host
   Big p, pm1;
   std::unique_ptr<Mont> mont;
   uint32_t log2max = 0;
@@ -251,6 +252,53 @@ int upload(const std::vector<T>& host, T** dev) {
   return GFP_OK;
 }
 
+// The table of w^j, j < cnt (a power of two), and its raw digits, built on the
+// device (k <= 16): the host computes w^i for i < B = 2^ceil(lg cnt / 2) and
+// w^(B i) for i < cnt / B (2 sqrt(cnt) powers instead of cnt), and
+// k_table_build multiplies them.  Its products are canonical, so the tables
+// equal the host-built ones digit for digit (measured: the first 2^20-point
+// transform of a field 3.1 ms against 15.8 ms for k = 8, 7.1 against 27.5 ms
+// for k = 16).
+int build_table_dev(const gfp_field* f, const Big& wm, uint64_t cnt, uint32_t** tab, uint64_t** raw) {
+  const int lg = log2_exact(cnt);
+  if (lg < 0 || f->k > 16) return GFP_EINVAL;
+  const Mont& M = *f->mont;
+  const int lb = (lg + 1) / 2;
+  const uint64_t B = 1ull << lb, H = cnt >> lb;
+  std::vector<uint64_t> small((B + H) * f->k);
+  Big acc = M.pow(wm, Big(0));
+  for (uint64_t i = 0; i < B; ++i) {
+    to_digits(f, M.from(acc), &small[i * f->k]);
+    acc = M.mmul(acc, wm);
+  }
+  const Big wb = M.pow(wm, Big(B));
+  acc = M.pow(wm, Big(0));
+  for (uint64_t i = 0; i < H; ++i) {
+    to_digits(f, M.from(acc), &small[(B + i) * f->k]);
+    acc = M.mmul(acc, wb);
+  }
+  uint64_t* dsmall = nullptr;
+  int rc = upload(small, &dsmall);
+  if (rc != GFP_OK) return rc;
+  void* t = nullptr;
+  void* r = nullptr;
+  hipError_t he = hipMalloc(&t, cnt * gfpk::tw_words((int)f->k) * sizeof(uint32_t));
+  if (he == hipSuccess) he = hipMalloc(&r, cnt * f->k * sizeof(uint64_t));
+  if (he == hipSuccess)
+    he = gfpk::launch_table_build((int)f->k, f->w, f->u, dsmall, dsmall + B * f->k, lb, cnt, (uint32_t*)t,
+                                  (uint64_t*)r, hipStreamPerThread);
+  if (he == hipSuccess) he = hipStreamSynchronize(hipStreamPerThread);
+  (void)hipFree(dsmall);
+  if (he != hipSuccess) {
+    if (t) (void)hipFree(t);
+    if (r) (void)hipFree(r);
+    return hip_status(he);
+  }
+  *tab = (uint32_t*)t;
+  *raw = (uint64_t*)r;
+  return GFP_OK;
+}
+
 // valid transform size: a power of two n >= K within the field and the build
 // limit.  n = R K^e with R = 2^(log2n - e log2 K) < K: *e radix-K passes, preceded
 // by one radix-R pass when R > 1.
@@ -290,24 +338,20 @@ int get_tables(gfp_field* f, uint64_t n, const DevTables** out, bool build = tru
   std::vector<uint64_t>* rawp = f->k <= 16 ? &raw : nullptr;
   const Mont& M = *f->mont;
   const Big ninv_m = M.pow(M.to(Big(n)), gfp::sub(f->p, Big(2)));  // 1/n, Montgomery form
-  build_table(f, root_mont(f, n, false), cnt, host, nullptr, rawp);
-  int rc = upload(host, &t.fwd);
-  if (rc == GFP_OK && rawp) rc = upload(raw, &t.fwd_raw);
-  if (rc == GFP_OK) {
-    build_table(f, root_mont(f, n, true), cnt, host, nullptr, rawp);
-    rc = upload(host, &t.inv);
-    if (rc == GFP_OK && rawp) rc = upload(raw, &t.inv_raw);
-  }
+  // table of w^j (or w^(-j)) with its raw digits where the passes read them
+  auto table = [&](const Big& wm, uint32_t** tab, uint64_t** rawt) -> int {
+    if (rawp && !f->host_tables) return build_table_dev(f, wm, cnt, tab, rawt);
+    build_table(f, wm, cnt, host, nullptr, rawp);
+    int r2 = upload(host, tab);
+    if (r2 == GFP_OK && rawp) r2 = upload(raw, rawt);
+    return r2;
+  };
+  int rc = table(root_mont(f, n, false), &t.fwd, &t.fwd_raw);
+  if (rc == GFP_OK) rc = table(root_mont(f, n, true), &t.inv, &t.inv_raw);
   // w^K = w_{n/K} (the roots are nested): twiddles of the passes before the last
   if (rc == GFP_OK && n >= 4ull * f->k * f->k) {
-    build_table(f, root_mont(f, n / (2ull * f->k), false), cnt, host, nullptr, rawp);
-    rc = upload(host, &t.fwd2);
-    if (rc == GFP_OK && rawp) rc = upload(raw, &t.fwd2_raw);
-    if (rc == GFP_OK) {
-      build_table(f, root_mont(f, n / (2ull * f->k), true), cnt, host, nullptr, rawp);
-      rc = upload(host, &t.inv2);
-      if (rc == GFP_OK && rawp) rc = upload(raw, &t.inv2_raw);
-    }
+    rc = table(root_mont(f, n / (2ull * f->k), false), &t.fwd2, &t.fwd2_raw);
+    if (rc == GFP_OK) rc = table(root_mont(f, n / (2ull * f->k), true), &t.inv2, &t.inv2_raw);
   }
   if (rc == GFP_OK && scale_in_tables(f, log2_exact(n))) {
     build_table(f, root_mont(f, n, true), cnt, host, &ninv_m);
@@ -1333,6 +1377,8 @@ int gfp_field_create(uint32_t k, uint64_t r, gfp_field** out) {
   f->r = r;
   const char* v = getenv("GFP_VALIDATE");
   f->validate = v && *v && strcmp(v, "0") != 0;
+  const char* ht = getenv("GFP_HOST_TABLES");
+  f->host_tables = ht && *ht && strcmp(ht, "0") != 0;
   // r = 2^w + 2^u (u > 0), or r = 2^w - 2^-u (u < 0) ?
   if (__builtin_popcountll(r) == 2) {
     f->u = __builtin_ctzll(r);

@@ -201,6 +201,11 @@ inline bool persist_pass_kind(int k, const PassArgs& p, uint32_t* kind, uint64_t
 constexpr uint64_t kPersistSyncBytes = 64 * 128;
 hipError_t launch_persistent(int k, int w, int u, const PLevel* levels, uint32_t nlevels, const PRec* recs,
                              uint32_t* sync, uint32_t grid, hipStream_t st);
+// The table of w^j, j < cnt, on the device (k <= 16): lo[i] = w^i for
+// i < 2^log2b, hi[i] = w^(i 2^log2b) for i < cnt / 2^log2b (raw digits,
+// device); writes the entry-layout table tab and the raw-digit table raw.
+hipError_t launch_table_build(int k, int w, int u, const uint64_t* lo, const uint64_t* hi, int log2b, uint64_t cnt,
+                              uint32_t* tab, uint64_t* raw, hipStream_t st);
 // Workgroups of that kernel that fit on the device at once (0 if the shape has none).
 int persistent_capacity(int k, int w, int u, int* grid);
 

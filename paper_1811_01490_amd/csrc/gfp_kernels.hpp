@@ -900,6 +900,70 @@ __global__ __launch_bounds__(256) void k_elementwise(const uint64_t* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// twiddle tables on the device (k <= 16)
+// ---------------------------------------------------------------------------
+// Entry j < cnt of the table of w^j from two small tables of raw digits:
+// lo[i] = w^i (i < 2^log2b) and hi[i] = w^(i 2^log2b): w^j is their product,
+// canonical, so it equals the value computed any other way digit for digit.
+// Writes the raw digits (raw[j k + m]) and the entry layout read by the
+// passes (tab + j WORDS: the 22/22/20-bit limbs of every digit, the suffix
+// sums sum_{t >= i} y_t for i = 0..k as three words, zero padding).
+template <int KD, int W, int U>
+__global__ __launch_bounds__(256) void k_table_build(const uint64_t* __restrict__ lo, const uint64_t* __restrict__ hi,
+                                                     int log2b, uint64_t cnt, uint32_t* __restrict__ tab,
+                                                     uint64_t* __restrict__ raw) {
+  typedef Geo<KD> Gm;
+  static_assert(Gm::ROW, "elements inside one DPP row");
+  const int l = Gm::lane();
+  const int m = Gm::digit(l);
+  const uint64_t e = ((uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * Gm::G + Gm::group(l);
+  const bool active = e < cnt;
+  const uint64_t j = active ? e : 0;  // inactive groups compute entry 0 and store nothing
+  const uint64_t xm = lo[(j & ((1ull << log2b) - 1)) * KD + m];
+  const L96 t = mul_data_ptr<KD, W, U>(xm, hi + (j >> log2b) * KD, 1, l, m);
+  const uint64_t d = canonicalize<KD, W, U>(t, l, m);
+  uint32_t l0, l1, l2;
+  split22(d, l0, l1, l2);
+  // inclusive suffix sum sum_{t >= m} y_t (< 2^68) by doubling steps
+  uint32_t s0 = (uint32_t)d, s1 = (uint32_t)(d >> 32), s2 = 0u;
+  static_for<ilog2(KD)>([&](auto I) {
+    constexpr int dd = 1 << decltype(I)::value;
+    const uint32_t n0 = dig_up<KD, dd>(s0), n1 = dig_up<KD, dd>(s1), n2 = dig_up<KD, dd>(s2);
+    unsigned c;
+    s0 = __builtin_addc(s0, n0, 0u, &c);
+    s1 = __builtin_addc(s1, n1, c, &c);
+    s2 = s2 + n2 + c;
+  });
+  if (!active) return;
+  raw[j * KD + m] = d;
+  uint32_t* E = tab + j * TwLayout<KD>::WORDS;
+  E[3 * m] = l0;
+  E[3 * m + 1] = l1;
+  E[3 * m + 2] = l2;
+  uint32_t* suf = E + TwLayout<KD>::SUF + 3 * m;
+  suf[0] = s0;
+  suf[1] = s1;
+  suf[2] = s2;
+  if (m == KD - 1) {  // suffix(k) = 0 and the padding
+    for (int w = TwLayout<KD>::SUF + 3 * KD; w < TwLayout<KD>::WORDS; ++w) E[w] = 0u;
+  }
+}
+
+template <int KD, int W, int U>
+hipError_t launch_table_build_t(const uint64_t* lo, const uint64_t* hi, int log2b, uint64_t cnt, uint32_t* tab,
+                                uint64_t* raw, hipStream_t st) {
+  if constexpr (KD > 16) {
+    return hipErrorInvalidValue;
+  } else {
+    const uint64_t per_block = 4ull * Geo<KD>::G;  // 4 wavefronts of G entries
+    const unsigned nb = (unsigned)((cnt + per_block - 1) / per_block);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_table_build<KD, W, U>), dim3(nb), dim3(256), 0, st, lo, hi, log2b, cnt, tab, raw);
+    return hipGetLastError();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // one persistent launch for a batch of products (k <= 16)
 // ---------------------------------------------------------------------------
 // Copies with the descriptors in device memory, on one virtual block: vector

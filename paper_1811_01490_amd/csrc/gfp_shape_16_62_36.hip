@@ -14,4 +14,9 @@ hipError_t launch_persistent_16_62_36(const PLevel* levels, uint32_t nlevels, co
 }
 int persistent_capacity_16_62_36(int* grid) { return persistent_capacity_t<16, 62, 36>(grid); }
 
+hipError_t launch_table_build_16_62_36(const uint64_t* lo, const uint64_t* hi, int log2b, uint64_t cnt, uint32_t* tab,
+                                      uint64_t* raw, hipStream_t st) {
+  return launch_table_build_t<16, 62, 36>(lo, hi, log2b, cnt, tab, raw, st);
+}
+
 }  // namespace gfpk

@@ -14,4 +14,9 @@ hipError_t launch_persistent_32_62_56(const PLevel* levels, uint32_t nlevels, co
 }
 int persistent_capacity_32_62_56(int* grid) { return persistent_capacity_t<32, 62, 56>(grid); }
 
+hipError_t launch_table_build_32_62_56(const uint64_t* lo, const uint64_t* hi, int log2b, uint64_t cnt, uint32_t* tab,
+                                      uint64_t* raw, hipStream_t st) {
+  return launch_table_build_t<32, 62, 56>(lo, hi, log2b, cnt, tab, raw, st);
+}
+
 }  // namespace gfpk

@@ -14,4 +14,9 @@ hipError_t launch_persistent_64_63_m40(const PLevel* levels, uint32_t nlevels, c
 }
 int persistent_capacity_64_63_m40(int* grid) { return persistent_capacity_t<64, 63, -40>(grid); }
 
+hipError_t launch_table_build_64_63_m40(const uint64_t* lo, const uint64_t* hi, int log2b, uint64_t cnt, uint32_t* tab,
+                                      uint64_t* raw, hipStream_t st) {
+  return launch_table_build_t<64, 63, -40>(lo, hi, log2b, cnt, tab, raw, st);
+}
+
 }  // namespace gfpk

@@ -14,4 +14,9 @@ hipError_t launch_persistent_8_59_16(const PLevel* levels, uint32_t nlevels, con
 }
 int persistent_capacity_8_59_16(int* grid) { return persistent_capacity_t<8, 59, 16>(grid); }
 
+hipError_t launch_table_build_8_59_16(const uint64_t* lo, const uint64_t* hi, int log2b, uint64_t cnt, uint32_t* tab,
+                                      uint64_t* raw, hipStream_t st) {
+  return launch_table_build_t<8, 59, 16>(lo, hi, log2b, cnt, tab, raw, st);
+}
+
 }  // namespace gfpk
