@@ -45,7 +45,9 @@
  * use; for k <= 16 on the device (the host computes 2 sqrt(N/2k) powers of
  * the root, a kernel the rest), unless GFP_HOST_TABLES is set (to anything
  * but "0") at gfp_field_create, which builds them on the host as for k >= 32.
- * Both give the same tables digit for digit.
+ * Both give the same tables digit for digit.  Either build uploads and
+ * waits on the calling thread (gfp_server_submit included), so it can wait
+ * behind other work on the GPU that shares its hardware queue.
  */
 #ifndef GFP_H
 #define GFP_H
@@ -186,7 +188,11 @@ typedef struct gfp_polymul_desc {
 #define GFP_BATCH_GRAPH 1      /* capture the launches into a hipGraph, cache it per argument list, replay it */
 #define GFP_BATCH_PERSISTENT 2 /* k <= 16: the whole batch as one cooperative launch over a device work list */
 
-/* Workspace bytes gfp_polymul_batched needs for this request list. */
+/* Workspace bytes gfp_polymul_batched needs for this request list, with
+ * either flag.  Without GFP_BATCH_PERSISTENT the call needs less: the sum of
+ * the size classes' chunk workspaces (8 C N k words for a chunk of C requests
+ * of transform size N), without the work-list tail (its levels, records,
+ * three 32-byte copy descriptors per request and 8 KiB of counters). */
 int gfp_polymul_batched_workspace_size(const gfp_field* f, uint32_t n, const gfp_polymul_desc* d, uint64_t* bytes);
 
 /* n independent products (section 3.3, Alg. Fast Convolution), each exactly

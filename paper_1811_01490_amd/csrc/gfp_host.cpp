@@ -1039,10 +1039,11 @@ struct BatchPlan {
     uint64_t ws_off = 0;  // its workspace region (words), used chunk after chunk
   };
   std::vector<Group> groups;  // ascending size
-  uint64_t ws_words = 0;      // the regions of all groups, which run concurrently, and the tail
-  // Tail of the workspace (words from tail_off): the work list of the
+  uint64_t ws_words = 0;      // the regions of all groups, which run concurrently
+  // Tail of the workspace, needed only by the persistent launch (tail_words
+  // words from tail_off = ws_words): the work list of the
   // persistent launch (levels, records, copy descriptors, barrier counters).
-  uint64_t tail_off = 0, nlevels = 0, nrecs = 0, ndesc = 0;
+  uint64_t tail_off = 0, tail_words = 0, nlevels = 0, nrecs = 0, ndesc = 0;
 };
 
 // Launches of one chunk in the persistent work list: pad, the forward
@@ -1088,7 +1089,7 @@ int plan_batch(gfp_field* f, uint32_t n, const gfp_polymul_desc* d, BatchPlan& p
   }
   plan.ndesc = 3ull * n;
   plan.tail_off = plan.ws_words;
-  plan.ws_words += align_words(plan.nlevels * sizeof(gfpk::PLevel)) + align_words(plan.nrecs * sizeof(gfpk::PRec)) +
+  plan.tail_words = align_words(plan.nlevels * sizeof(gfpk::PLevel)) + align_words(plan.nrecs * sizeof(gfpk::PRec)) +
                    align_words(plan.ndesc * sizeof(gfpk::CopyDesc)) + align_words(gfpk::kPersistSyncBytes);
   return GFP_OK;
 }
@@ -1715,7 +1716,7 @@ int gfp_polymul_batched_workspace_size(const gfp_field* cf, uint32_t n, const gf
   BatchPlan plan;
   int rc = plan_batch(const_cast<gfp_field*>(cf), n, d, plan);
   if (rc != GFP_OK) return rc;
-  *bytes = plan.ws_words * 8;
+  *bytes = (plan.ws_words + plan.tail_words) * 8;  // enough for either path
   return GFP_OK;
 }
 
@@ -1744,7 +1745,8 @@ int gfp_polymul_batched(const gfp_field* cf, uint32_t n, const gfp_polymul_desc*
   }
   Scratch s;
   uint64_t* w = nullptr;
-  rc = get_workspace(workspace, ws_bytes, plan.ws_words * 8, st, s, &w);
+  const bool persistent = (flags & GFP_BATCH_PERSISTENT) != 0;
+  rc = get_workspace(workspace, ws_bytes, (plan.ws_words + (persistent ? plan.tail_words : 0)) * 8, st, s, &w);
   if (rc != GFP_OK) return rc;
   if (flags & GFP_BATCH_PERSISTENT) return enqueue_batch_persistent(f, plan, w, st);
   if (!graph) return enqueue_batch(f, plan, w, st);

@@ -89,10 +89,11 @@ struct CopyDesc {
 // launch), so a captured graph holds its own copy of them.
 constexpr uint32_t kCopyBatch = 48;
 hipError_t launch_pad(int k, const CopyDesc* host_d, uint32_t nvec, uint64_t* work, uint64_t n, hipStream_t st);
+// maxlen: the largest len of the descriptors (at most n); k = 8, 16, 32, 64.
 hipError_t launch_unpad(int k, const CopyDesc* host_d, uint32_t nvec, const uint64_t* work, uint64_t n,
                         uint64_t maxlen, hipStream_t st);
-// The same with the descriptors in device memory (dev_desc[0, nvec)); unpad
-// needs n a power of two.
+// The same with the descriptors in device memory (dev_desc[0, nvec), every
+// len at most n).
 hipError_t launch_pad_dev(int k, const CopyDesc* dev_desc, uint32_t nvec, uint64_t* work, uint64_t n,
                           hipStream_t st);
 hipError_t launch_unpad_dev(int k, const CopyDesc* dev_desc, uint32_t nvec, const uint64_t* work, uint64_t n,

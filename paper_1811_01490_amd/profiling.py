@@ -30,7 +30,8 @@ import os
 import re
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["paper_1811_01490_amd/csrc/gfp_kernels.hpp", "paper_1811_01490_amd/csrc/gfp_device.hpp"]
+KERNEL_SOURCES = ["paper_1811_01490_amd/csrc/gfp_kernels.hpp", "paper_1811_01490_amd/csrc/gfp_device.hpp",
+                  "paper_1811_01490_amd/csrc/gfp_copy.hip"]
 CALIB_BYTES = 64 * 2 ** 20
 
 
@@ -153,6 +154,9 @@ def sq_table(sq, stats):
             k, row["waves"], row["valu_per_wave"], row["valu64_per_wave"], row["salu_per_wave"],
             row["lds_per_wave"], row["vmem_rd_per_wave"], row["lds_bank_conflicts_per_wave"],
             "%.2f" % busy if busy is not None else "-"))
+    if any(r["valu_busy"] is not None and r["valu_busy"] > 1.0 for r in out.values()):
+        lines += ["", "A busy share above 1 means that launches of this kernel overlapped others (the size "
+                  "classes of a batch run on forked streams), so the chip was not its alone for its duration."]
     return lines, out
 
 

@@ -57,6 +57,16 @@ def sleep_cycles(torch_mod):
     return int(2_000_000 * 60.0 / ms)
 
 
+def _tables_ready(torch, f, *ops):
+    """Build the twiddle tables of every product size a test submits while a
+    batch is held.  A table build uploads from the submitting thread, and
+    that copy can queue behind the held spin kernel when their streams share
+    a hardware queue; submit would then wait out the hold."""
+    for op in ops:
+        f.polymul(op[2], op[3])
+    torch.cuda.synchronize()
+
+
 def _held_event(torch, cycles):
     """An event that completes after a ~60 ms spin on a side stream."""
     s = torch.cuda.Stream()
@@ -128,7 +138,7 @@ def test_arrivals_during_a_batch_use_another_slot(torch_mod, fields, sleep_cycle
     small = [_operands(P8, 50 + 7 * i, 40 + 3 * i, 101 + i) for i in range(6)]
     c = _out(torch, 8, 4999)
     cs = [_out(torch, 8, x[2].shape[1] + x[3].shape[1] - 1) for x in small]
-    torch.cuda.synchronize()
+    _tables_ready(torch, f, (a, b, da, db), *small)
     with Server(workspace_bytes=1 << 30, slots=2, max_batch=64) as srv:
         ev, side = _held_event(torch, sleep_cycles)
         t_big = srv.submit(f, da, db, c, ready=ev)
@@ -188,12 +198,12 @@ def test_budget_limits_batch_and_rejects_oversize(torch_mod, fields, sleep_cycle
         # hold the only slot so the queue fills, then release it
         hold = _operands(P8, 10, 10, 201)
         ch = _out(torch, 8, 19)
+        ops = [_operands(P8, 1500 + i, 1000 + i, 210 + i) for i in range(7)]  # transform size 4096
+        outs = [_out(torch, 8, x[2].shape[1] + x[3].shape[1] - 1) for x in ops]
+        _tables_ready(torch, f, hold, ops[0])
         ev, side = _held_event(torch, sleep_cycles)
         t0 = srv.submit(f, hold[2], hold[3], ch, ready=ev)
         time.sleep(0.005)
-        ops = [_operands(P8, 1500 + i, 1000 + i, 210 + i) for i in range(7)]  # transform size 4096
-        outs = [_out(torch, 8, x[2].shape[1] + x[3].shape[1] - 1) for x in ops]
-        torch.cuda.synchronize()
         ts = [srv.submit(f, x[2], x[3], c) for x, c in zip(ops, outs)]
         rs = [srv.wait(t) for t in ts]
         srv.wait(t0)
@@ -217,7 +227,7 @@ def test_full_queue_and_shutdown(torch_mod, fields, sleep_cycles):
     ch = _out(torch, 16, 69)
     queued = [_operands(P16, 20 + i, 10 + i, 301 + i) for i in range(4)]
     outs = [_out(torch, 16, x[2].shape[1] + x[3].shape[1] - 1) for x in queued]
-    torch.cuda.synchronize()
+    _tables_ready(torch, f, hold, *queued)
     ev, side = _held_event(torch, sleep_cycles)
     t0 = srv.submit(f, hold[2], hold[3], ch, ready=ev)
     time.sleep(0.005)
@@ -248,7 +258,7 @@ def test_express_slot_serves_small_requests_past_large_ones(torch_mod, fields, s
     small = _operands(P8, 100, 100, 510)  # transform size 2^8
     cb = [_out(torch, 8, 5999) for _ in big]
     cs = _out(torch, 8, 199)
-    torch.cuda.synchronize()
+    _tables_ready(torch, f, big[0], small)
     with Server(workspace_bytes=2 * f.polymul_workspace_size(3000, 3000), slots=2, max_batch=1,
                 express_log2n=12) as srv:
         ev, side = _held_event(torch, sleep_cycles)
@@ -281,7 +291,7 @@ def test_mixed_batch_completes_small_class_first(torch_mod, fields, sleep_cycles
     large = _operands(P16, 2 ** 14, 2 ** 14, 601)  # transform size 32^3
     small = _operands(P16, 30, 20, 602)
     cl, cs = _out(torch, 16, 2 ** 15 - 1), _out(torch, 16, 49)
-    torch.cuda.synchronize()
+    _tables_ready(torch, f, hold, large, small)
     with Server(workspace_bytes=4 << 30, slots=1, max_batch=64) as srv:
         ev, side = _held_event(torch, sleep_cycles)
         t0 = srv.submit(f, hold[2], hold[3], ch, ready=ev)
@@ -289,9 +299,9 @@ def test_mixed_batch_completes_small_class_first(torch_mod, fields, sleep_cycles
         tl = srv.submit(f, large[2], large[3], cl)  # queued in arrival order, large first
         ts = srv.submit(f, small[2], small[3], cs)
         rl, rs = srv.wait(tl), srv.wait(ts)
-        srv.wait(t0)
+        r0 = srv.wait(t0)
     side.synchronize()
-    assert rl["batch_id"] == rs["batch_id"] and rl["batch_size"] == 2
+    assert rl["batch_id"] == rs["batch_id"] and rl["batch_size"] == 2, (r0, rl, rs)
     assert rs["t_done_ns"] <= rl["t_done_ns"]
     _check_alone(f, large[2], large[3], cl)
     _check_alone(f, small[2], small[3], cs)
