@@ -1240,7 +1240,8 @@ int persist_chunk(gfp_field* f, int log2n, int e, uint64_t C, uint64_t* ws, cons
   r.in2 = F;
   r.ngroups = n;
   r.nvec = C;
-  r.tiles = C * copy_tiles;
+  const uint64_t e_tile = gfpk::kUnpadTileWords / k;  // elements per unpad tile
+  r.tiles = C * ((n + e_tile - 1) / e_tile);
   seq.push_back(r);
   return GFP_OK;
 }

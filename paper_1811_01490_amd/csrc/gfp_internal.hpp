@@ -93,7 +93,9 @@ hipError_t launch_pad(int k, const CopyDesc* host_d, uint32_t nvec, uint64_t* wo
 hipError_t launch_unpad(int k, const CopyDesc* host_d, uint32_t nvec, const uint64_t* work, uint64_t n,
                         uint64_t maxlen, hipStream_t st);
 // The same with the descriptors in device memory (dev_desc[0, nvec), every
-// len at most n).
+// len at most n).  Unpad moves tiles of kUnpadTileWords words (1024 / k
+// elements) through LDS.
+constexpr uint64_t kUnpadTileWords = 1024;
 hipError_t launch_pad_dev(int k, const CopyDesc* dev_desc, uint32_t nvec, uint64_t* work, uint64_t n,
                           hipStream_t st);
 hipError_t launch_unpad_dev(int k, const CopyDesc* dev_desc, uint32_t nvec, const uint64_t* work, uint64_t n,

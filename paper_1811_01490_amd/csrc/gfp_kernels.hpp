@@ -13,6 +13,7 @@
 // j < N/K is tabulated and r^rho is a digit rotation.
 #pragma once
 
+#include "gfp_copy.hpp"
 #include "gfp_device.hpp"
 #include "gfp_internal.hpp"
 
@@ -980,21 +981,23 @@ __device__ __forceinline__ void pad_dev_body(const CopyDesc* __restrict__ desc, 
   work[v * n * k + t] = (i < cd.len) ? cd.src[(uint64_t)d * cd.ld + i] : 0ull;
 }
 
+// Unpad tile vb.idx: vector v = tile / per, per = tiles per vector; the
+// tile transposes through LDS (ulds), and the trailing barrier lets the next
+// tile reuse it.
+template <int KD>
 __device__ __forceinline__ void unpad_dev_body(const CopyDesc* __restrict__ desc, const uint64_t* __restrict__ work,
-                                               uint64_t n, uint32_t k, VB vb) {
-  const uint64_t per = (n * k + 255) / 256;
+                                               uint64_t n, VB vb, uint64_t* __restrict__ ulds) {
+  constexpr uint64_t E = kUnpadWords / KD;
+  const uint64_t per = (n + E - 1) / E;
   const uint64_t v = vb.idx / per;
-  const uint64_t t = (vb.idx - v * per) * 256 + threadIdx.x;
-  if (t >= n * k) return;
-  const uint64_t d = t / n;
-  const uint64_t i = t - d * n;
   const CopyDesc cd = desc[v];
-  if (i >= cd.len) return;
-  cd.dst[d * cd.ld + i] = work[v * n * k + i * k + d];
+  unpad_tile<KD>(cd, work + v * n * KD, vb.idx - v * per, ulds);
+  __syncthreads();
 }
 
 template <int KD, int W, int U>
-__device__ __forceinline__ void run_record(const PRec& R, uint64_t tile, uint32_t* __restrict__ stg) {
+__device__ __forceinline__ void run_record(const PRec& R, uint64_t tile, uint32_t* __restrict__ stg,
+                                           uint64_t* __restrict__ ulds) {
   const VB vb{tile, R.tiles};
   const uint64_t* in = reinterpret_cast<const uint64_t*>(R.in);
 #define GFP_PBODY(INV, MODE, LAST, UNIF, T2)                                                                        \
@@ -1006,7 +1009,7 @@ __device__ __forceinline__ void run_record(const PRec& R, uint64_t tile, uint32_
       pad_dev_body(reinterpret_cast<const CopyDesc*>(R.in), R.out, R.ngroups, KD, vb);
       break;
     case PK_UNPAD:
-      unpad_dev_body(reinterpret_cast<const CopyDesc*>(R.in), R.in2, R.ngroups, KD, vb);
+      unpad_dev_body<KD>(reinterpret_cast<const CopyDesc*>(R.in), R.in2, R.ngroups, vb, ulds);
       break;
     case PK_MUL:
       elementwise_body<KD, W, U, GFP_OP_MUL>(in, KD, 1, R.in2, KD, 1, R.out, KD, 1, R.nvec, 0, nullptr, vb);
@@ -1087,13 +1090,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KD == 16 ? 
     const PLevel* __restrict__ levels, uint32_t nlevels, const PRec* __restrict__ recs, uint32_t* __restrict__ sync) {
   static_assert(KD == 8 || KD == 16, "the persistent batch is built for k = 8 and 16");
   __shared__ uint32_t stg[4 * StageGeo<KD>::PER_WAVE];
+  __shared__ uint64_t ulds[kUnpadWords + kUnpadWords / KD];
   for (uint32_t L = 0; L < nlevels; ++L) {
     const uint32_t r0 = levels[L].rec0, r1 = r0 + levels[L].nrec;
     const uint64_t tiles = levels[L].tiles;
     uint32_t r = r0;
     for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
       while (r + 1 < r1 && recs[r + 1].tile0 <= t) ++r;
-      run_record<KD, W, U>(recs[r], t - recs[r].tile0, stg);
+      run_record<KD, W, U>(recs[r], t - recs[r].tile0, stg, ulds);
     }
     if (L + 1 < nlevels) level_barrier(sync, gridDim.x * (L + 1));
   }
