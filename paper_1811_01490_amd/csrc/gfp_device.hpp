@@ -72,10 +72,8 @@ struct Geo {
   }
   // Shorter product tail (add_carried_q, undefined-old rotations, one SGPR
   // constant per shifted add): the default of the LN template parameter
-  // below.  k = 16 keeps the longer forms by default: its uniform-twiddle
-  // passes sit at the 128-VGPR (4 wavefronts per SIMD) limit, which the
-  // shorter forms' register allocation exceeds; its per-group passes take
-  // the shorter forms (LN = true, set by the kernel).
+  // below.  k = 16 keeps the longer forms by default (its fused pairs and
+  // elementwise kernels); its single-pass kernels set LN = true themselves.
   static constexpr bool LEAN = KD != 16;
 };
 
@@ -792,7 +790,7 @@ __device__ __forceinline__ L96 mul_twiddle(uint64_t x, const uint32_t* __restric
 // Same with a wavefront-uniform twiddle entry and rotation: the limbs are
 // read with scalar loads (uniform address, read-only table) and stay in
 // SGPRs; only the per-lane correction sum is a vector load.
-template <int KD, int W, int U>
+template <int KD, int W, int U, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ L96 mul_twiddle_uniform(uint64_t x, const uint32_t* __restrict__ tw, int rot, int l,
                                                    int m) {
   const RotLane<KD> rl = rot_lane<KD>(rot, m);
@@ -811,14 +809,14 @@ __device__ __forceinline__ L96 mul_twiddle_uniform(uint64_t x, const uint32_t* _
     });
     uint32_t s0, s1, s2;
     tw_correction<KD>(tw, rl, s0, s1, s2);
-    return mul_core<KD, W, U>(x0, x1, y, s0, s1, s2, m);
+    return mul_core<KD, W, U, LN>(x0, x1, y, s0, s1, s2, m);
   }
 }
 
 // x * tw where lane m holds digit m of x (no rotation) and the table entry
 // is wavefront-uniform: limbs through scalar loads, the lane's correction sum
 // S_m = suffix(m + 1) through one vector load at a fixed per-lane offset.
-template <int KD, int W, int U>
+template <int KD, int W, int U, bool LN = Geo<KD>::LEAN>
 __device__ __forceinline__ L96 mul_entry_uniform(uint64_t x, const uint32_t* __restrict__ tw, int m) {
   slot_fence();
   if constexpr (KD == 64) {
@@ -831,7 +829,7 @@ __device__ __forceinline__ L96 mul_entry_uniform(uint64_t x, const uint32_t* __r
       y.l[i] = tw[TwLayout<KD>::LIMBS + i];
     });
     const uint32_t* suf = tw + TwLayout<KD>::SUF + 3 * (m + 1);
-    return mul_core<KD, W, U>((uint32_t)x, (uint32_t)(x >> 32), y, suf[0], suf[1], suf[2], m);
+    return mul_core<KD, W, U, LN>((uint32_t)x, (uint32_t)(x >> 32), y, suf[0], suf[1], suf[2], m);
   }
 }
 

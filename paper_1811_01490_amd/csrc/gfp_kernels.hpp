@@ -91,9 +91,12 @@ __device__ __forceinline__ L96 first_slot(uint64_t x, const uint64_t* __restrict
 // Used when every a has at least G groups (all passes but the last).
 // T2: the twiddles come from the table of w^(K i) without rotations (every
 // pass but the last); otherwise from the table of w^j with r^rho rotations.
-// k = 16 per-group passes: the shorter product tail (LN) and at most 2
-// wavefronts per SIMD expected, so the scheduler keeps their instruction-level
-// parallelism (with fewer registers it aims at 3 and runs slower).
+// k = 16 passes take the shorter product tail (LN).  Per-group passes: at
+// most 2 wavefronts per SIMD expected, so the scheduler keeps their
+// instruction-level parallelism (with fewer registers it aims at 3 and runs
+// slower).  Uniform-twiddle passes: at most 3 (145 VGPRs); with the longer
+// tail at 4 wavefronts (128 VGPRs) the N = 2^20 forward transform took
+// 538.7 us against 536.4, a 2^15 product 180.3 against 176.4 us.
 template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T2>
 __device__ __forceinline__ void pass_body(
     const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2, uint64_t se_in, uint64_t sd_in,
@@ -102,7 +105,7 @@ __device__ __forceinline__ void pass_body(
     int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout, int staged, VB vb,
     uint32_t* __restrict__ stg) {
   typedef Geo<KD> Gm;
-  constexpr bool LN = Gm::LEAN || !UNIF;
+  constexpr bool LN = Gm::LEAN || KD == 16;
   constexpr int KB = Gm::KB;
   constexpr int LOGKB = ilog2(KB);
   const int l = Gm::lane();
@@ -176,7 +179,7 @@ __device__ __forceinline__ void pass_body(
       const int sh2 = log2n - 2 * LOGKB - log2ns;
       static_for<KB - 1>([&](auto T) {
         constexpr int t = decltype(T)::value + 1;
-        v[t] = mul_entry_uniform<KD, W, U>(x[t], tw2 + ((a * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS, m);
+        v[t] = mul_entry_uniform<KD, W, U, LN>(x[t], tw2 + ((a * (uint64_t)t) << sh2) * TwLayout<KD>::WORDS, m);
       });
     } else if constexpr (UNIF) {
       const int shift = log2n - log2ns - LOGKB;  // table stride N / (Ns K)
@@ -186,7 +189,7 @@ __device__ __forceinline__ void pass_body(
         const int rho = (int)(e >> log2ns);
         const uint64_t c = e & (ns - 1);
         const int rot = INV ? ((2 * KD - rho) & (2 * KD - 1)) : rho;
-        v[t] = mul_twiddle_uniform<KD, W, U>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
+        v[t] = mul_twiddle_uniform<KD, W, U, LN>(x[t], tw + (c << shift) * TwLayout<KD>::WORDS, rot, l, m);
       });
     } else if (!staged) {
       // per-group twiddles, each lane reading the whole entry from the limb
@@ -257,7 +260,7 @@ __device__ __forceinline__ void pass_body(
 
 // stg: 4 wavefronts' LDS staging areas (StageGeo<KD>::PER_WAVE words each).
 template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T2>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16 && !UNIF ? 2 : 8))) void k_pass(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16 ? (UNIF ? 3 : 2) : 8))) void k_pass(
     const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2, uint64_t se_in, uint64_t sd_in,
     uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
     const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1, const uint64_t* __restrict__ twr2, int log2n,
