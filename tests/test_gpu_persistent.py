@@ -128,3 +128,38 @@ def test_persistent_repeated_calls_with_workspace(torch_mod):
             for i, c in enumerate(outs):
                 assert torch.equal(c, ref[i]), (rep, i)
             assert to_ints(to_host(outs[0]), F.r) == want[0]
+
+
+def test_persistent_workspace_and_flags(torch_mod):
+    """The persistent launch needs the work-list tail of the workspace; the
+    per-class path does not.  A workspace sized without the tail is rejected
+    with GFP_EINVAL for the persistent flag only, and the k = 32 prime is not
+    built for it (GFP_EUNSUPPORTED)."""
+    import torch
+
+    from oracle.field import P32
+    from paper_1811_01490_amd import Field, GFPError
+    from paper_1811_01490_amd.gfp import GFP_EINVAL, GFP_EUNSUPPORTED
+
+    f = Field(P8["k"], P8["r"])
+    _, dev = _batch(P8, [(300, 200), (40, 30)], gi.BASE_SEED + 323)
+    outs = _outs(torch, 8, dev, fill=0)
+    descs = f.batch_descs([(a, b, c) for (a, b), c in zip(dev, outs)])
+    full = f.polymul_batched_workspace_size(descs)
+    # the per-class path's need: the chunk workspaces alone (8 C N k words per class)
+    need = sum(8 * 1 * f.polymul_size(a.shape[1], b.shape[1]) * 8 * 8 for a, b in dev)
+    assert need < full
+    ws = torch.empty(need // 8, dtype=torch.int64, device="cuda")
+    f.polymul_batched(descs, workspace=ws)  # enough without the tail
+    torch.cuda.synchronize()
+    for (a, b), c in zip(dev, outs):
+        assert torch.equal(c, f.polymul(a, b))
+    with pytest.raises(GFPError) as e:
+        f.polymul_batched(descs, workspace=ws, persistent=True)
+    assert e.value.code == GFP_EINVAL
+    f32 = Field(P32["k"], P32["r"])
+    _, dev32 = _batch(P32, [(10, 10)], gi.BASE_SEED + 324)
+    o32 = _outs(torch, 32, dev32)
+    with pytest.raises(GFPError) as e:
+        f32.polymul_batched(f32.batch_descs([(a, b, c) for (a, b), c in zip(dev32, o32)]), persistent=True)
+    assert e.value.code == GFP_EUNSUPPORTED
