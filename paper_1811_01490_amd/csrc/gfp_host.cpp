@@ -1173,6 +1173,7 @@ int pass_record(const gfp_field* f, const gfpk::PassArgs& p, gfpk::PRec* r) {
   r->se_out = p.se_out;
   r->sd_out = p.sd_out;
   r->tw = p.tw;
+  r->tw1 = p.tw1;
   r->tw2 = p.tw2;
   r->twr1 = p.twr1;
   r->twr2 = p.twr2;
@@ -1183,9 +1184,28 @@ int pass_record(const gfp_field* f, const gfpk::PassArgs& p, gfpk::PRec* r) {
   return GFP_OK;
 }
 
+// Stage grouping of the persistent launch: k = 8 fuses pairs of passes (two
+// blocks per 256-thread tile) from the first one on, leaving the last pass
+// single (a fused last pair is slower, its twiddles being per group either
+// way); e = 2 is one pair.  k = 16 runs single passes (its pairs need
+// 512-thread workgroups).
+std::vector<int> persist_plan(const gfp_field* f, int log2n, int e) {
+  std::vector<int> plan;
+  if (f->k != 8 || e < 2) return std::vector<int>(e, LC_ONE);
+  if (e == 2) return std::vector<int>(1, LC_PAIR);
+  int left = e;
+  while (left >= 3) {
+    plan.push_back(LC_PAIR);
+    left -= 2;
+  }
+  while (left-- > 0) plan.push_back(LC_ONE);
+  if (!plan_valid(f, log2n, e, plan)) return std::vector<int>(e, LC_ONE);
+  return plan;
+}
+
 // The records of one chunk of C products of size 2^log2n (the launches of
-// polymul_chunk with one pass per launch and the pointwise product as a
-// launch of its own), one per level, appended to seq.  dev_desc: its 3C copy
+// polymul_chunk with the persistent stage grouping and the pointwise product
+// as a launch of its own), one per level, appended to seq.  dev_desc: its 3C copy
 // descriptors in device memory (operands a, operands b, products).
 int persist_chunk(gfp_field* f, int log2n, int e, uint64_t C, uint64_t* ws, const gfpk::CopyDesc* dev_desc,
                   std::vector<gfpk::PRec>& seq) {
@@ -1205,14 +1225,14 @@ int persist_chunk(gfp_field* f, int log2n, int e, uint64_t C, uint64_t* ws, cons
   r.nvec = 2 * C;
   r.tiles = 2 * C * copy_tiles;
   seq.push_back(r);
-  const std::vector<int> ones(e, LC_ONE);
+  const std::vector<int> plan = persist_plan(f, log2n, e);
   const VecView em{A, k, 1, vw}, fm{F, k, 1, vw};
   std::vector<gfpk::PassArgs> fwd, inv;
   t_record = &fwd;
-  int rc = run_transform_plan(f, log2n, e, ones, false, em, fm, 2 * C, false, W1, W2, nullptr);
+  int rc = run_transform_plan(f, log2n, e, plan, false, em, fm, 2 * C, false, W1, W2, nullptr);
   if (rc == GFP_OK) {
     t_record = &inv;
-    rc = run_transform_plan(f, log2n, e, ones, true, em, fm, C, true, W1, W2, nullptr);
+    rc = run_transform_plan(f, log2n, e, plan, true, em, fm, C, true, W1, W2, nullptr);
   }
   t_record = nullptr;
   if (rc != GFP_OK) return rc;

@@ -138,6 +138,13 @@ enum PersistKind : uint32_t {
   PK_PASS_ISCALE_LAST = 8,  // k_pass <inv, scale, last>
   PK_PASS_R_F = 9,     // k_pass_r <fwd, plain, radix 2^lr>
   PK_PASS_R_I = 10,    // k_pass_r <inv, scale, radix 2^lr>
+  // fused pairs (k = 8, two blocks per tile): k_pass2 <inv, mode, last, T2B>
+  PK_PAIR_F_T2 = 11,     // <fwd, plain, not last, second pass from the w^(K i) table>
+  PK_PAIR_F = 12,        // <fwd, plain, not last, second pass the final one>
+  PK_PAIR_I_T2 = 13,     // <inv, plain, not last, T2B>
+  PK_PAIR_I_LAST = 14,   // <inv, plain, last>
+  PK_PAIR_IS_T2 = 15,    // <inv, scale, not last, T2B>
+  PK_PAIR_IS_LAST = 16,  // <inv, scale, last>
 };
 
 struct PRec {
@@ -152,6 +159,7 @@ struct PRec {
   uint64_t* out;
   uint64_t se_out, sd_out;
   const uint32_t* tw;
+  const uint32_t* tw1;  // fused pairs: the w^j table of the second pass
   const uint32_t* tw2;
   const uint64_t* twr1;
   const uint64_t* twr2;
@@ -164,10 +172,32 @@ struct PLevel {
 };
 
 // Kind and tile count of a pass launch (the variant launch_pass_t would
-// pick) for k <= 16 single passes; false if the persistent launch does not
-// carry it (fused pairs, k >= 32, the fused pointwise product).
+// pick) for k <= 16 single passes and k = 8 fused pairs; false if the
+// persistent launch does not carry it (wide pairs, k = 16 pairs, k >= 32,
+// the fused pointwise product).
 inline bool persist_pass_kind(int k, const PassArgs& p, uint32_t* kind, uint64_t* tiles) {
-  if (k > 16 || p.span != 1 || p.in2 || p.ntt_mul) return false;
+  if (k > 16 || p.in2 || p.ntt_mul) return false;
+  if (p.span == 2) {
+    if (k != 8 || p.wide || p.radix_log2 != 0) return false;
+    const int lk2 = 4;
+    if (p.log2n < 2 * lk2 || p.log2ns + 2 * lk2 > p.log2n) return false;
+    const bool t2b = !p.last && p.log2n - 2 * lk2 - (p.log2ns + lk2) >= 0;
+    if (!p.inverse) {
+      if (p.last) return false;  // forward transforms of a product stay non-canonical
+      *kind = t2b ? PK_PAIR_F_T2 : PK_PAIR_F;
+    } else if (p.scale) {
+      if (p.last) *kind = PK_PAIR_IS_LAST;
+      else if (t2b) *kind = PK_PAIR_IS_T2;
+      else return false;
+    } else {
+      if (p.last) *kind = PK_PAIR_I_LAST;
+      else if (t2b) *kind = PK_PAIR_I_T2;
+      else return false;
+    }
+    *tiles = ((p.nvec << (p.log2n - 2 * lk2)) + 1) / 2;  // two K^2-element blocks per tile
+    return true;
+  }
+  if (p.span != 1) return false;
   const int lk = k == 8 ? 4 : 5;
   const int lg = k == 8 ? 3 : 2;  // log2 of the element groups per wavefront
   const uint64_t groups_per_block = 4ull << lg;

@@ -579,26 +579,28 @@ struct Span2Geo {
 
 // T2B: the second pass is not the last one and takes its twiddles from the
 // table of w^(K i); the first pass never is the last and always does.
+// lds: SG::BPW * KB * SG::ROW words (the blocks' transposes); stg: the
+// wavefronts' staging areas (SG::WAVES * StageGeo<KD>::PER_WAVE words).
 template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B>
-__global__ __launch_bounds__(Span2Geo<KD>::THREADS) void k_pass2(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
-                                               uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
-                                               const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
-                                               const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1,
-                                               const uint64_t* __restrict__ twr2, int log2n, int log2ns, uint64_t nvec,
-                                               uint64_t vin, uint64_t vout, int staged) {
+__device__ __forceinline__ void pass2_body(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
+                                           uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out,
+                                           uint64_t sd_out, const uint32_t* __restrict__ tw0,
+                                           const uint32_t* __restrict__ tw1, const uint32_t* __restrict__ tw2,
+                                           const uint64_t* __restrict__ twr1, const uint64_t* __restrict__ twr2,
+                                           int log2n, int log2ns, uint64_t nvec, uint64_t vin, uint64_t vout,
+                                           int staged, VB vb, uint64_t* __restrict__ lds, uint32_t* __restrict__ stg) {
   static_assert(KD == 8 || KD == 16, "the fused pass pair is built for k = 8 and 16");
   typedef Geo<KD> Gm;
   typedef Span2Geo<KD> SG;
   constexpr int KB = Gm::KB;
   constexpr int LOGKB = ilog2(KB);
-  __shared__ uint64_t lds[SG::BPW * KB * SG::ROW];
   const int l = Gm::lane();
   const int m = Gm::digit(l);
   const int g = Gm::group(l);
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int bw = wv / SG::WPB, h = wv % SG::WPB;
   const int log2nb = log2n - 2 * LOGKB;  // blocks per vector
-  uint64_t gq = xcd_block(se_in == 1 || se_out == 1) * SG::BPW + bw;
+  uint64_t gq = xcd_block(se_in == 1 || se_out == 1, vb) * SG::BPW + bw;
   uint64_t vec = gq >> log2nb;
   const bool active = vec < nvec;
   if (!active) {
@@ -665,7 +667,6 @@ __global__ __launch_bounds__(Span2Geo<KD>::THREADS) void k_pass2(const uint64_t*
   v[0] = l96(x[0]);
   // per-group twiddles, staged through LDS from the raw-digit tables (or, for
   // small transforms, read whole by each lane from the limb tables)
-  __shared__ uint32_t stg[SG::WAVES * StageGeo<KD>::PER_WAVE];
   uint32_t* E = stg + wv * StageGeo<KD>::PER_WAVE + g * StageGeo<KD>::WORDS;
   if (!staged) {
     if constexpr (T2B) {
@@ -723,6 +724,20 @@ __global__ __launch_bounds__(Span2Geo<KD>::THREADS) void k_pass2(const uint64_t*
     }
     if (active) out[(uint64_t)m * sd_out + (obase + (uint64_t)t * ns1) * se_out] = d;
   });
+}
+
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B>
+__global__ __launch_bounds__(Span2Geo<KD>::THREADS) void k_pass2(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
+                                               uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
+                                               const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
+                                               const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1,
+                                               const uint64_t* __restrict__ twr2, int log2n, int log2ns, uint64_t nvec,
+                                               uint64_t vin, uint64_t vout, int staged) {
+  typedef Span2Geo<KD> SG;
+  __shared__ uint64_t lds[SG::BPW * SG::KB * SG::ROW];
+  __shared__ uint32_t stg[SG::WAVES * StageGeo<KD>::PER_WAVE];
+  pass2_body<KD, W, U, INV, MODE, LAST, T2B>(in, in2, se_in, sd_in, out, se_out, sd_out, tw0, tw1, tw2, twr1, twr2,
+                                             log2n, log2ns, nvec, vin, vout, staged, launch_vb(), lds, stg);
 }
 
 // The same pass pair with uniform twiddles in both halves ("wide"): a
@@ -1000,7 +1015,7 @@ __device__ __forceinline__ void unpad_dev_body(const CopyDesc* __restrict__ desc
 
 template <int KD, int W, int U>
 __device__ __forceinline__ void run_record(const PRec& R, uint64_t tile, uint32_t* __restrict__ stg,
-                                           uint64_t* __restrict__ ulds) {
+                                           uint64_t* __restrict__ big) {
   const VB vb{tile, R.tiles};
   const uint64_t* in = reinterpret_cast<const uint64_t*>(R.in);
 #define GFP_PBODY(INV, MODE, LAST, UNIF, T2)                                                                        \
@@ -1012,7 +1027,7 @@ __device__ __forceinline__ void run_record(const PRec& R, uint64_t tile, uint32_
       pad_dev_body(reinterpret_cast<const CopyDesc*>(R.in), R.out, R.ngroups, KD, vb);
       break;
     case PK_UNPAD:
-      unpad_dev_body<KD>(reinterpret_cast<const CopyDesc*>(R.in), R.in2, R.ngroups, vb, ulds);
+      unpad_dev_body<KD>(reinterpret_cast<const CopyDesc*>(R.in), R.in2, R.ngroups, vb, big);
       break;
     case PK_MUL:
       elementwise_body<KD, W, U, GFP_OP_MUL>(in, KD, 1, R.in2, KD, 1, R.out, KD, 1, R.nvec, 0, nullptr, vb);
@@ -1045,6 +1060,20 @@ __device__ __forceinline__ void run_record(const PRec& R, uint64_t tile, uint32_
 #undef GFP_RBODY
       break;
     }
+#define GFP_P2BODY(INV, MODE, LAST, T2B)                                                                          \
+  if constexpr (KD == 8) {                                                                                         \
+    pass2_body<KD, W, U, INV, MODE, LAST, T2B>(in, R.in2, R.se_in, R.sd_in, R.out, R.se_out, R.sd_out, R.tw, R.tw1, \
+                                               R.tw2, R.twr1, R.twr2, R.log2n, R.log2ns, R.nvec, R.vin, R.vout,     \
+                                               R.staged, vb, big, stg);                                            \
+    __syncthreads(); /* the next tile rewrites the transpose area */                                               \
+  }
+    case PK_PAIR_F_T2: GFP_P2BODY(false, MODE_PLAIN, false, true); break;
+    case PK_PAIR_F: GFP_P2BODY(false, MODE_PLAIN, false, false); break;
+    case PK_PAIR_I_T2: GFP_P2BODY(true, MODE_PLAIN, false, true); break;
+    case PK_PAIR_I_LAST: GFP_P2BODY(true, MODE_PLAIN, true, false); break;
+    case PK_PAIR_IS_T2: GFP_P2BODY(true, MODE_SCALE, false, true); break;
+    case PK_PAIR_IS_LAST: GFP_P2BODY(true, MODE_SCALE, true, false); break;
+#undef GFP_P2BODY
     default:
       break;
   }
@@ -1093,14 +1122,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KD == 16 ? 
     const PLevel* __restrict__ levels, uint32_t nlevels, const PRec* __restrict__ recs, uint32_t* __restrict__ sync) {
   static_assert(KD == 8 || KD == 16, "the persistent batch is built for k = 8 and 16");
   __shared__ uint32_t stg[4 * StageGeo<KD>::PER_WAVE];
-  __shared__ uint64_t ulds[kUnpadWords + kUnpadWords / KD];
+  // the fused pairs' transposes (k = 8) or the unpad tiles
+  constexpr int PAIR_WORDS = KD == 8 ? Span2Geo<KD>::BPW * Span2Geo<KD>::KB * Span2Geo<KD>::ROW : 0;
+  constexpr int UNPAD_WORDS = kUnpadWords + kUnpadWords / KD;
+  __shared__ uint64_t big[PAIR_WORDS > UNPAD_WORDS ? PAIR_WORDS : UNPAD_WORDS];
   for (uint32_t L = 0; L < nlevels; ++L) {
     const uint32_t r0 = levels[L].rec0, r1 = r0 + levels[L].nrec;
     const uint64_t tiles = levels[L].tiles;
     uint32_t r = r0;
     for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
       while (r + 1 < r1 && recs[r + 1].tile0 <= t) ++r;
-      run_record<KD, W, U>(recs[r], t - recs[r].tile0, stg, ulds);
+      run_record<KD, W, U>(recs[r], t - recs[r].tile0, stg, big);
     }
     if (L + 1 < nlevels) level_barrier(sync, gridDim.x * (L + 1));
   }
