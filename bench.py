@@ -629,8 +629,8 @@ def main():
     y.copy_(x)
     torch.cuda.synchronize()
     # warm-up: the requested steps, then more until the GPU has been busy for
-    # at least --warmup-s seconds (the first call builds the twiddle tables on
-    # the host while the GPU idles, and the clock needs tens of ms of work to
+    # at least --warmup-s seconds (the first call builds the twiddle tables,
+    # the GPU mostly idle meanwhile, and the clock needs tens of ms of work to
     # come back up), so that a short --warmup still times the steady state
     f.fft_forward(x, y=y, workspace=ws)
     torch.cuda.synchronize()
