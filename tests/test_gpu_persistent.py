@@ -163,3 +163,29 @@ def test_persistent_workspace_and_flags(torch_mod):
     with pytest.raises(GFPError) as e:
         f32.polymul_batched(f32.batch_descs([(a, b, c) for (a, b), c in zip(dev32, o32)]), persistent=True)
     assert e.value.code == GFP_EUNSUPPORTED
+
+
+def test_persistent_matches_per_class_on_the_batched_workload_mix(torch_mod):
+    """A draw of the batched workload's shape (transform sizes log-uniform on
+    16^2..16^5, la = lb = N / 2, uniform digits), smaller in count: the
+    persistent launch and the per-class launches give identical products."""
+    import torch
+
+    from paper_1811_01490_amd import Field, to_device
+
+    f = Field(P8["k"], P8["r"])
+    g = gi.rng(gi.BASE_SEED + 325, 0)
+    sizes = [16 ** int(e) for e in g.integers(2, 6, size=24)]
+    print("persistent workload mix", sorted(sizes), flush=True)
+    dev = []
+    for i, n in enumerate(sizes):
+        a = to_device(gi.uniform_digits(8, P8["r"], n // 2, gi.BASE_SEED + 325, 2 + 2 * i))
+        b = to_device(gi.uniform_digits(8, P8["r"], n // 2, gi.BASE_SEED + 325, 3 + 2 * i))
+        dev.append((a, b))
+    ref = _outs(torch, 8, dev, fill=0)
+    got = _outs(torch, 8, dev, fill=7)
+    f.polymul_batched(f.batch_descs([(a, b, c) for (a, b), c in zip(dev, ref)]))
+    f.polymul_batched(f.batch_descs([(a, b, c) for (a, b), c in zip(dev, got)]), persistent=True)
+    torch.cuda.synchronize()
+    for i, (x, y) in enumerate(zip(ref, got)):
+        assert torch.equal(x, y), (i, sizes[i])
