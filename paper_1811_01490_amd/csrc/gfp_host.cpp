@@ -128,6 +128,15 @@ struct gfp_field {
   };
   std::mutex side_mu;
   std::map<int, Side> side;
+  // pinned staging of the persistent launch's work list, per device; `done`
+  // is recorded behind the copy that last read it (guarded by stage_mu)
+  struct Stage {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+  };
+  std::mutex stage_mu;
+  std::map<int, Stage> stage;
 };
 
 namespace {
@@ -1270,7 +1279,7 @@ int persist_chunk(gfp_field* f, int log2n, int e, uint64_t C, uint64_t* ws, cons
 // chunks of each size class run level after level, the classes side by side
 // (level j of every class in one grid-wide step).  The list and the zeroed
 // barrier counters are copied into the workspace tail ahead of the launch,
-// in stream order.
+// in stream order, from the field's pinned staging.
 int enqueue_batch_persistent(gfp_field* f, const BatchPlan& plan, uint64_t* ws, hipStream_t st) {
   if (f->k > 16) return GFP_EUNSUPPORTED;
   int cap = 0;
@@ -1330,9 +1339,40 @@ int enqueue_batch_persistent(gfp_field* f, const BatchPlan& plan, uint64_t* ws, 
   memcpy(host.data(), lv.data(), lv.size() * sizeof(gfpk::PLevel));
   memcpy(host.data() + lev_bytes, recs.data(), recs.size() * sizeof(gfpk::PRec));
   memcpy(host.data() + lev_bytes + rec_bytes, descs.data(), descs.size() * sizeof(gfpk::CopyDesc));
-  // a copy from pageable memory returns once the source has been read
-  hipError_t he = hipMemcpyAsync(tail, host.data(), host.size(), hipMemcpyHostToDevice, st);
+  // through pinned staging: wait until the previous copy from it is done,
+  // refill it, copy in stream order and mark the copy
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
   if (he != hipSuccess) return hip_status(he);
+  {
+    std::lock_guard<std::mutex> lk(f->stage_mu);
+    gfp_field::Stage& sg = f->stage[dev];
+    if (!sg.done) {
+      he = hipEventCreateWithFlags(&sg.done, hipEventDisableTiming);
+      if (he != hipSuccess) {
+        sg.done = nullptr;
+        return hip_status(he);
+      }
+    } else {
+      he = hipEventSynchronize(sg.done);
+      if (he != hipSuccess) return hip_status(he);
+    }
+    if (sg.bytes < host.size()) {
+      if (sg.host) (void)hipHostFree(sg.host);
+      sg.host = nullptr;
+      sg.bytes = 0;
+      he = hipHostMalloc(&sg.host, host.size(), hipHostMallocDefault);
+      if (he != hipSuccess) {
+        sg.host = nullptr;
+        return hip_status(he);
+      }
+      sg.bytes = host.size();
+    }
+    memcpy(sg.host, host.data(), host.size());
+    he = hipMemcpyAsync(tail, sg.host, host.size(), hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) he = hipEventRecord(sg.done, st);
+    if (he != hipSuccess) return hip_status(he);
+  }
   const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)cap, most);
   return hip_status(gfpk::launch_persistent(
       (int)f->k, f->w, f->u, reinterpret_cast<const gfpk::PLevel*>(tail), (uint32_t)lv.size(),
@@ -1475,7 +1515,15 @@ int gfp_field_destroy(gfp_field* f) {
     for (hipEvent_t e2 : kv.second.joins) (void)hipEventDestroy(e2);
     if (kv.second.fork) (void)hipEventDestroy(kv.second.fork);
   }
-  if (!f->tables.empty() || !f->consts.empty() || !f->side.empty()) (void)hipSetDevice(dev);
+  for (auto& kv : f->stage) {
+    (void)hipSetDevice(kv.first);
+    if (kv.second.done) {
+      (void)hipEventSynchronize(kv.second.done);
+      (void)hipEventDestroy(kv.second.done);
+    }
+    if (kv.second.host) (void)hipHostFree(kv.second.host);
+  }
+  if (!f->tables.empty() || !f->consts.empty() || !f->side.empty() || !f->stage.empty()) (void)hipSetDevice(dev);
   delete f;
   return GFP_OK;
 }
