@@ -9,12 +9,13 @@ struct CopyBatch {
   CopyDesc d[kCopyBatch];
 };
 
-// thread -> (element i, digit d) of work vector blockIdx.y: work[v n k + i k + d]
-__global__ __launch_bounds__(256) void k_pad(const CopyBatch desc, uint64_t* __restrict__ work, uint64_t n, uint32_t k,
-                                             uint32_t log2k) {
+// thread -> (element i, digit d) of work vector blockIdx.y: work[v n k + i k + d],
+// for the first cols elements
+__global__ __launch_bounds__(256) void k_pad(const CopyBatch desc, uint64_t* __restrict__ work, uint64_t n,
+                                             uint64_t cols, uint32_t k, uint32_t log2k) {
   const uint32_t v = blockIdx.y;
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * k) return;
+  if (t >= cols * k) return;
   const uint64_t i = t >> log2k;
   const uint32_t d = (uint32_t)(t & (k - 1));
   const CopyDesc cd = desc.d[v];
@@ -82,16 +83,17 @@ hipError_t launch_check_canonical(const uint64_t* x, uint64_t ld, uint64_t n, in
   return hipGetLastError();
 }
 
-hipError_t launch_pad(int k, const CopyDesc* d, uint32_t nvec, uint64_t* work, uint64_t n, hipStream_t st) {
-  if (nvec == 0) return hipSuccess;
-  if (nvec > kCopyBatch) return hipErrorInvalidValue;
+hipError_t launch_pad(int k, const CopyDesc* d, uint32_t nvec, uint64_t* work, uint64_t n, uint64_t cols,
+                      hipStream_t st) {
+  if (nvec == 0 || cols == 0) return hipSuccess;
+  if (nvec > kCopyBatch || cols > n) return hipErrorInvalidValue;
   CopyBatch b;
   for (uint32_t i = 0; i < nvec; ++i) b.d[i] = d[i];
-  const uint64_t tot = n * (uint64_t)k;
+  const uint64_t tot = cols * (uint64_t)k;
   dim3 grid((unsigned)((tot + 255) / 256), nvec);
   uint32_t lk = 0;
   while ((1u << lk) < (uint32_t)k) ++lk;
-  hipLaunchKernelGGL(k_pad, grid, dim3(256), 0, st, b, work, n, (uint32_t)k, lk);
+  hipLaunchKernelGGL(k_pad, grid, dim3(256), 0, st, b, work, n, cols, (uint32_t)k, lk);
   return hipGetLastError();
 }
 

@@ -784,9 +784,11 @@ thread_local std::vector<gfpk::PassArgs>* t_record = nullptr;
 
 // X2 (inverse only): the transform input is the pointwise product X X2, formed
 // in the first launch (X2 has X's strides, element-major)
+// in_len (k <= 16): elements of the input vectors at or past it are zero
+// and the first launch does not read them.
 int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& plan, bool inverse, VecView X,
                        VecView Y, uint64_t nvec, bool canonical, uint64_t* W1, uint64_t* W2, hipStream_t st,
-                       const uint64_t* X2 = nullptr, bool build_tables = true) {
+                       const uint64_t* X2 = nullptr, bool build_tables = true, uint64_t in_len = ~0ull) {
   const uint64_t n = 1ull << log2n;
   const uint64_t k = f->k;
   const DevTables* t = nullptr;
@@ -842,6 +844,7 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
     p.inverse = inverse;
     p.scale = inverse && i == 0 && !scale_tab;
     p.in2 = (i == 0) ? X2 : nullptr;
+    p.in_len = (i == 0 && f->k <= 16) ? in_len : ~0ull;
     p.tw = p.scale ? t->ninv : (inverse ? t->inv : t->fwd);
     p.tw1 = inverse ? t->inv : t->fwd;
     p.tw2 = inverse ? t->inv2 : t->fwd2;
@@ -883,9 +886,10 @@ int run_transform_plan(gfp_field* f, int log2n, int e, const std::vector<int>& p
 }
 
 int run_transform(gfp_field* f, int log2n, int e, bool inverse, VecView X, VecView Y, uint64_t nvec, bool canonical,
-                  uint64_t* W1, uint64_t* W2, hipStream_t st, const uint64_t* X2 = nullptr) {
+                  uint64_t* W1, uint64_t* W2, hipStream_t st, const uint64_t* X2 = nullptr,
+                  uint64_t in_len = ~0ull) {
   return run_transform_plan(f, log2n, e, plan_for(f, log2n, e, nvec, view_layout(X, Y)), inverse, X, Y, nvec,
-                            canonical, W1, W2, st, X2);
+                            canonical, W1, W2, st, X2, true, in_len);
 }
 
 // no_alloc: ws is the static scratch (gfp_fft_noalloc); the tables must
@@ -940,10 +944,12 @@ struct PolyReq {
 };
 
 // pad / unpad with descriptors passed by value (so graph capture keeps them)
-int copy_in(gfp_field* f, const std::vector<gfpk::CopyDesc>& d, uint64_t* work, uint64_t n, hipStream_t st) {
+// the first cols elements of each work vector (cols <= n)
+int copy_in(gfp_field* f, const std::vector<gfpk::CopyDesc>& d, uint64_t* work, uint64_t n, uint64_t cols,
+            hipStream_t st) {
   for (size_t i = 0; i < d.size(); i += gfpk::kCopyBatch) {
     const uint32_t cnt = (uint32_t)std::min<size_t>(gfpk::kCopyBatch, d.size() - i);
-    hipError_t he = gfpk::launch_pad((int)f->k, d.data() + i, cnt, work + i * n * f->k, n, st);
+    hipError_t he = gfpk::launch_pad((int)f->k, d.data() + i, cnt, work + i * n * f->k, n, cols, st);
     if (he != hipSuccess) return hip_status(he);
   }
   return GFP_OK;
@@ -979,25 +985,34 @@ int polymul_chunk(gfp_field* f, int log2n, int e, const PolyReq* r, uint64_t C, 
   uint64_t* W1 = F + 2 * C * vw;
   uint64_t* W2 = W1 + 2 * C * vw;
   std::vector<gfpk::CopyDesc> din, dout;
+  // operand elements the forward transforms read: past the longest operand
+  // everything is zero padding, which is neither written nor read (k <= 16;
+  // with device descriptors the lengths are not known here)
+  uint64_t cols = n;
   if (!dev_desc) {
     din.resize(2 * C);
     dout.resize(C);
+    uint64_t longest = 0;
     for (uint64_t i = 0; i < C; ++i) {
       din[i] = gfpk::CopyDesc{r[i].a, nullptr, r[i].la, r[i].lda};
       din[C + i] = gfpk::CopyDesc{r[i].b, nullptr, r[i].lb, r[i].ldb};
       dout[i] = gfpk::CopyDesc{nullptr, r[i].c, r[i].la + r[i].lb - 1, r[i].ldc};
+      longest = std::max(longest, std::max(r[i].la, r[i].lb));
     }
+    // from 2^16 elements on (smaller products measured 1-2% slower with the
+    // bounded first launch)
+    if (k <= 16 && n >= (1ull << 16)) cols = std::min(n, longest);
   }
   auto copy_out_any = [&](const uint64_t* src) -> int {
     if (dev_desc) return hip_status(gfpk::launch_unpad_dev((int)k, dev_desc + 2 * C, (uint32_t)C, src, n, st));
     return copy_out(f, dout, src, n, st);
   };
   int rc = dev_desc ? hip_status(gfpk::launch_pad_dev((int)k, dev_desc, (uint32_t)(2 * C), A, n, st))
-                    : copy_in(f, din, A, n, st);
+                    : copy_in(f, din, A, n, cols, st);
   // forward transforms of all 2C operands in one launch per pass; the last
   // pass leaves congruent (not canonical) digits for the pointwise product
   const VecView em{A, k, 1, vw}, fm{F, k, 1, vw};
-  if (rc == GFP_OK) rc = run_transform(f, log2n, e, false, em, fm, 2 * C, false, W1, W2, st);
+  if (rc == GFP_OK) rc = run_transform(f, log2n, e, false, em, fm, 2 * C, false, W1, W2, st, nullptr, cols);
   if (rc != GFP_OK) return rc;
   if (C * n >= kFuseProductElems && !scale_in_tables(f, log2n)) {
     // inverse of the pointwise products F[i] F[C + i], formed in its first

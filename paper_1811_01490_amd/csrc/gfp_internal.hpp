@@ -58,6 +58,9 @@ struct PassArgs {
   // in[i] in2[i] of two transforms; in2 has the strides of in and its digits
   // contiguous (sd_in 1), and the product is then multiplied by tw[0]
   const uint64_t* in2 = nullptr;
+  // k <= 16, plain or scale passes: elements at or past in_len of each input
+  // vector are zero and not read (the zero padding of a product's operands)
+  uint64_t in_len = ~0ull;
 };
 // Whether two passes can share a launch for k (plan character '2'), and
 // the wide variant over eight blocks per workgroup (plan character 'w').
@@ -86,9 +89,13 @@ struct CopyDesc {
   uint64_t ld;          // caller row stride
 };
 // Descriptors travel as kernel arguments (by value, at most kCopyBatch per
-// launch), so a captured graph holds its own copy of them.
+// launch), so a captured graph holds its own copy of them.  Pad writes the
+// first `cols` elements of each work vector (zeros past a descriptor's len);
+// the rest stays unwritten, for a transform that reads at most cols
+// elements (PassArgs::in_len).
 constexpr uint32_t kCopyBatch = 48;
-hipError_t launch_pad(int k, const CopyDesc* host_d, uint32_t nvec, uint64_t* work, uint64_t n, hipStream_t st);
+hipError_t launch_pad(int k, const CopyDesc* host_d, uint32_t nvec, uint64_t* work, uint64_t n, uint64_t cols,
+                      hipStream_t st);
 // maxlen: the largest len of the descriptors (at most n); k = 8, 16, 32, 64.
 hipError_t launch_unpad(int k, const CopyDesc* host_d, uint32_t nvec, const uint64_t* work, uint64_t n,
                         uint64_t maxlen, hipStream_t st);

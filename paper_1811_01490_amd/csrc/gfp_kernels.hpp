@@ -97,13 +97,13 @@ __device__ __forceinline__ L96 first_slot(uint64_t x, const uint64_t* __restrict
 // slower).  Uniform-twiddle passes: at most 3 (145 VGPRs); with the longer
 // tail at 4 wavefronts (128 VGPRs) the N = 2^20 forward transform took
 // 538.7 us against 536.4, a 2^15 product 180.3 against 176.4 us.
-template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T2>
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T2, bool BND = false>
 __device__ __forceinline__ void pass_body(
     const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2, uint64_t se_in, uint64_t sd_in,
     uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
     const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1, const uint64_t* __restrict__ twr2, int log2n,
     int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout, int staged, VB vb,
-    uint32_t* __restrict__ stg) {
+    uint32_t* __restrict__ stg, uint64_t in_len = ~0ull) {
   typedef Geo<KD> Gm;
   constexpr bool LN = Gm::LEAN || KD == 16;
   constexpr int KB = Gm::KB;
@@ -145,11 +145,15 @@ __device__ __forceinline__ void pass_body(
 
   // all slots loaded up front, except for the pointwise product, whose
   // second operand loads already keep enough reads in flight
+  // BND: elements at or past in_len are zero and not read (a product's
+  // zero padding, first launch of its forward transforms; a variant of its
+  // own, so that the transforms' kernels carry no bound check)
   uint64_t x[KB];
   if constexpr (MODE != MODE_PRODUCT) {
     static_for<KB>([&](auto T) {
       constexpr int t = decltype(T)::value;
-      x[t] = in[(uint64_t)m * sd_in + (jj + (uint64_t)t * nk) * se_in];
+      const uint64_t i = jj + (uint64_t)t * nk;
+      x[t] = (!BND || i < in_len) ? in[(uint64_t)m * sd_in + i * se_in] : 0ull;
     });
   }
 
@@ -259,15 +263,16 @@ __device__ __forceinline__ void pass_body(
 }
 
 // stg: 4 wavefronts' LDS staging areas (StageGeo<KD>::PER_WAVE words each).
-template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T2>
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool UNIF, bool T2, bool BND = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KD == 16 ? (UNIF ? 3 : 2) : 8))) void k_pass(
     const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2, uint64_t se_in, uint64_t sd_in,
     uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
     const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1, const uint64_t* __restrict__ twr2, int log2n,
-    int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout, int staged) {
+    int log2ns, uint64_t ngroups, uint64_t nvec, uint64_t vin, uint64_t vout, int staged, uint64_t in_len) {
   __shared__ uint32_t stg[4 * StageGeo<KD>::PER_WAVE];
-  pass_body<KD, W, U, INV, MODE, LAST, UNIF, T2>(in, in2, se_in, sd_in, out, se_out, sd_out, tw, tw2, twr1, twr2, log2n,
-                                                 log2ns, ngroups, nvec, vin, vout, staged, launch_vb(), stg);
+  pass_body<KD, W, U, INV, MODE, LAST, UNIF, T2, BND>(in, in2, se_in, sd_in, out, se_out, sd_out, tw, tw2, twr1, twr2,
+                                                      log2n, log2ns, ngroups, nvec, vin, vout, staged, launch_vb(), stg,
+                                                      in_len);
 }
 
 // ---------------------------------------------------------------------------
@@ -506,11 +511,12 @@ __global__ __launch_bounds__(256) void k_pass_k64(const uint64_t* __restrict__ i
 // The radix-K passes that follow run with Ns = R K^s (section 4.1: any
 // factorisation N = N1 N2 with the base case at powers of r).  MODE_SCALE
 // multiplies every element by the 1/N entry first (inverse transform).
-template <int KD, int W, int U, bool INV, int MODE, int LR>
+template <int KD, int W, int U, bool INV, int MODE, int LR, bool BND = false>
 __device__ __forceinline__ void pass_r_body(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
                                             uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out,
                                             uint64_t se_out, uint64_t sd_out, const uint32_t* __restrict__ tw,
-                                            int log2n, uint64_t nvec, uint64_t vin, uint64_t vout, VB vb) {
+                                            int log2n, uint64_t nvec, uint64_t vin, uint64_t vout, VB vb,
+                                            uint64_t in_len = ~0ull) {
   typedef Geo<KD> Gm;
   constexpr int R = 1 << LR;
   const int l = Gm::lane();
@@ -528,7 +534,8 @@ __device__ __forceinline__ void pass_r_body(const uint64_t* __restrict__ in, con
   L96 v[R];
   static_for<R>([&](auto T) {
     constexpr int t = decltype(T)::value;
-    const uint64_t x = in[(uint64_t)m * sd_in + (j + ((uint64_t)t << log2nr)) * se_in];
+    const uint64_t i = j + ((uint64_t)t << log2nr);
+    const uint64_t x = (!BND || i < in_len) ? in[(uint64_t)m * sd_in + i * se_in] : 0ull;
     if constexpr (MODE != MODE_PLAIN) {
       v[t] = first_slot<KD, W, U, MODE, (KD <= 16)>(x, in2 + (j + ((uint64_t)t << log2nr)) * se_in, tw, l, m);
     } else {
@@ -543,13 +550,13 @@ __device__ __forceinline__ void pass_r_body(const uint64_t* __restrict__ in, con
   });
 }
 
-template <int KD, int W, int U, bool INV, int MODE, int LR>
+template <int KD, int W, int U, bool INV, int MODE, int LR, bool BND = false>
 __global__ __launch_bounds__(256) void k_pass_r(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
                                                 uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
                                                 const uint32_t* __restrict__ tw, int log2n, uint64_t nvec,
-                                                uint64_t vin, uint64_t vout) {
-  pass_r_body<KD, W, U, INV, MODE, LR>(in, in2, se_in, sd_in, out, se_out, sd_out, tw, log2n, nvec, vin, vout,
-                                       launch_vb());
+                                                uint64_t vin, uint64_t vout, uint64_t in_len) {
+  pass_r_body<KD, W, U, INV, MODE, LR, BND>(in, in2, se_in, sd_in, out, se_out, sd_out, tw, log2n, nvec, vin, vout,
+                                            launch_vb(), in_len);
 }
 
 // ---------------------------------------------------------------------------
@@ -581,14 +588,15 @@ struct Span2Geo {
 // table of w^(K i); the first pass never is the last and always does.
 // lds: SG::BPW * KB * SG::ROW words (the blocks' transposes); stg: the
 // wavefronts' staging areas (SG::WAVES * StageGeo<KD>::PER_WAVE words).
-template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B>
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B, bool BND = false>
 __device__ __forceinline__ void pass2_body(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
                                            uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out,
                                            uint64_t sd_out, const uint32_t* __restrict__ tw0,
                                            const uint32_t* __restrict__ tw1, const uint32_t* __restrict__ tw2,
                                            const uint64_t* __restrict__ twr1, const uint64_t* __restrict__ twr2,
                                            int log2n, int log2ns, uint64_t nvec, uint64_t vin, uint64_t vout,
-                                           int staged, VB vb, uint64_t* __restrict__ lds, uint32_t* __restrict__ stg) {
+                                           int staged, VB vb, uint64_t* __restrict__ lds, uint32_t* __restrict__ stg,
+                                           uint64_t in_len = ~0ull) {
   static_assert(KD == 8 || KD == 16, "the fused pass pair is built for k = 8 and 16");
   typedef Geo<KD> Gm;
   typedef Span2Geo<KD> SG;
@@ -623,7 +631,8 @@ __device__ __forceinline__ void pass2_body(const uint64_t* __restrict__ in, cons
   uint64_t x[KB];
   static_for<KB>([&](auto T) {
     constexpr int t = decltype(T)::value;
-    x[t] = in[(uint64_t)m * sd_in + (base + (uint64_t)t * n1) * se_in];
+    const uint64_t i = base + (uint64_t)t * n1;
+    x[t] = (!BND || i < in_len) ? in[(uint64_t)m * sd_in + i * se_in] : 0ull;
   });
   L96 v[KB];
   if constexpr (MODE != MODE_PLAIN) {
@@ -726,18 +735,19 @@ __device__ __forceinline__ void pass2_body(const uint64_t* __restrict__ in, cons
   });
 }
 
-template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B>
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B, bool BND = false>
 __global__ __launch_bounds__(Span2Geo<KD>::THREADS) void k_pass2(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
                                                uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
                                                const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
                                                const uint32_t* __restrict__ tw2, const uint64_t* __restrict__ twr1,
                                                const uint64_t* __restrict__ twr2, int log2n, int log2ns, uint64_t nvec,
-                                               uint64_t vin, uint64_t vout, int staged) {
+                                               uint64_t vin, uint64_t vout, int staged, uint64_t in_len) {
   typedef Span2Geo<KD> SG;
   __shared__ uint64_t lds[SG::BPW * SG::KB * SG::ROW];
   __shared__ uint32_t stg[SG::WAVES * StageGeo<KD>::PER_WAVE];
-  pass2_body<KD, W, U, INV, MODE, LAST, T2B>(in, in2, se_in, sd_in, out, se_out, sd_out, tw0, tw1, tw2, twr1, twr2,
-                                             log2n, log2ns, nvec, vin, vout, staged, launch_vb(), lds, stg);
+  pass2_body<KD, W, U, INV, MODE, LAST, T2B, BND>(in, in2, se_in, sd_in, out, se_out, sd_out, tw0, tw1, tw2, twr1,
+                                                  twr2, log2n, log2ns, nvec, vin, vout, staged, launch_vb(), lds, stg,
+                                                  in_len);
 }
 
 // The same pass pair with uniform twiddles in both halves ("wide"): a
@@ -756,12 +766,12 @@ struct Span2UGeo {
   static constexpr int THREADS = 64 * NBLK * KB / Geo<KD>::G;
 };
 
-template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B>
+template <int KD, int W, int U, bool INV, int MODE, bool LAST, bool T2B, bool BND = false>
 __global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in, const uint64_t* __restrict__ in2,
                                                  uint64_t se_in, uint64_t sd_in, uint64_t* __restrict__ out, uint64_t se_out, uint64_t sd_out,
                                                  const uint32_t* __restrict__ tw0, const uint32_t* __restrict__ tw1,
                                                  const uint32_t* __restrict__ tw2, int log2n, int log2ns, uint64_t nvec,
-                                                 uint64_t vin, uint64_t vout) {
+                                                 uint64_t vin, uint64_t vout, uint64_t in_len) {
   static_assert(KD == 8, "the fused pass pair is built for k = 8");
   typedef Geo<KD> Gm;
   typedef Span2UGeo<KD> SG;
@@ -793,7 +803,8 @@ __global__ __launch_bounds__(1024) void k_pass2u(const uint64_t* __restrict__ in
   uint64_t x[KB];
   static_for<KB>([&](auto T) {
     constexpr int t = decltype(T)::value;
-    x[t] = in[(uint64_t)m * sd_in + (base + (uint64_t)t * n1) * se_in];
+    const uint64_t i = base + (uint64_t)t * n1;
+    x[t] = (!BND || i < in_len) ? in[(uint64_t)m * sd_in + i * se_in] : 0ull;
   });
   L96 v[KB];
   if constexpr (MODE != MODE_PLAIN) {
@@ -1191,10 +1202,11 @@ hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
       // 8 blocks per workgroup: both halves with uniform twiddles
       if (p.log2n - 2 * LOGKB - p.log2ns < 3) return hipErrorInvalidValue;
       const uint64_t wgs = p.nvec << (p.log2n - 2 * LOGKB - 3);
-#define GFP_LAUNCH2U(INV, MODE, LAST, T2B)                                                                       \
-  hipLaunchKernelGGL((k_pass2u<KD, W, U, INV, MODE, LAST, T2B>), dim3((unsigned)wgs), dim3(Span2UGeo<KD>::THREADS), 0, \
-                     st, p.in, p.in2, p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.log2n,     \
-                     p.log2ns, p.nvec, p.vin, p.vout)
+#define GFP_LAUNCH2UB(INV, MODE, LAST, T2B, BND)                                                                  \
+  hipLaunchKernelGGL((k_pass2u<KD, W, U, INV, MODE, LAST, T2B, BND>), dim3((unsigned)wgs),                          \
+                     dim3(Span2UGeo<KD>::THREADS), 0, st, p.in, p.in2, p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, \
+                     p.tw, p.tw1, p.tw2, p.log2n, p.log2ns, p.nvec, p.vin, p.vout, p.in_len)
+#define GFP_LAUNCH2U(INV, MODE, LAST, T2B) GFP_LAUNCH2UB(INV, MODE, LAST, T2B, false)
 #define GFP_LAUNCH2U_T(INV, MODE)                   \
   if (p.last) GFP_LAUNCH2U(INV, MODE, true, false); \
   else if (t2b) GFP_LAUNCH2U(INV, MODE, false, true); \
@@ -1205,22 +1217,26 @@ hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
         GFP_LAUNCH2U_T(true, MODE_SCALE)
       } else if (p.inverse) {
         GFP_LAUNCH2U_T(true, MODE_PLAIN)
+      } else if (p.in_len != ~0ull) {  // a product's first forward launch: the bounded variant
+        if (p.last || !t2b) return hipErrorInvalidValue;
+        GFP_LAUNCH2UB(false, MODE_PLAIN, false, true, true);
       } else {
         GFP_LAUNCH2U_T(false, MODE_PLAIN)
       }
 #undef GFP_LAUNCH2U_T
 #undef GFP_LAUNCH2U
+#undef GFP_LAUNCH2UB
       return hipGetLastError();
       }
     }
     const uint64_t blocks = (p.nvec << (p.log2n - 2 * LOGKB));
     const unsigned nb = (unsigned)((blocks + Span2Geo<KD>::BPW - 1) / Span2Geo<KD>::BPW);
     if (nb == 0) return hipSuccess;
-#define GFP_LAUNCH2(INV, MODE, LAST, T2B)                                                                         \
-  hipLaunchKernelGGL((k_pass2<KD, W, U, INV, MODE, LAST, T2B>), dim3(nb), dim3(Span2Geo<KD>::THREADS), 0, st, p.in, \
-                     p.in2, p.se_in,                                                                                  \
-                     p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.twr1, p.twr2, p.log2n, p.log2ns, p.nvec, \
-                     p.vin, p.vout, (int)p.staged)
+#define GFP_LAUNCH2B(INV, MODE, LAST, T2B, BND)                                                                    \
+  hipLaunchKernelGGL((k_pass2<KD, W, U, INV, MODE, LAST, T2B, BND>), dim3(nb), dim3(Span2Geo<KD>::THREADS), 0, st,   \
+                     p.in, p.in2, p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw1, p.tw2, p.twr1, p.twr2,    \
+                     p.log2n, p.log2ns, p.nvec, p.vin, p.vout, (int)p.staged, p.in_len)
+#define GFP_LAUNCH2(INV, MODE, LAST, T2B) GFP_LAUNCH2B(INV, MODE, LAST, T2B, false)
 #define GFP_LAUNCH2_T(INV, MODE)                   \
   if (p.last) GFP_LAUNCH2(INV, MODE, true, false); \
   else if (t2b) GFP_LAUNCH2(INV, MODE, false, true); \
@@ -1231,11 +1247,16 @@ hipError_t launch_pass2_t(const PassArgs& p, hipStream_t st) {
       GFP_LAUNCH2_T(true, MODE_SCALE)
     } else if (p.inverse) {
       GFP_LAUNCH2_T(true, MODE_PLAIN)
+    } else if (p.in_len != ~0ull) {  // a product's first forward launch: the bounded variant
+      if (p.last) return hipErrorInvalidValue;
+      if (t2b) GFP_LAUNCH2B(false, MODE_PLAIN, false, true, true);
+      else GFP_LAUNCH2B(false, MODE_PLAIN, false, false, true);
     } else {
       GFP_LAUNCH2_T(false, MODE_PLAIN)
     }
 #undef GFP_LAUNCH2_T
 #undef GFP_LAUNCH2
+#undef GFP_LAUNCH2B
     return hipGetLastError();
   }
 }
@@ -1244,14 +1265,17 @@ template <int KD, int W, int U, int LR>
 hipError_t launch_pass_r_lr(const PassArgs& p, hipStream_t st) {
   const unsigned nb = blocks_for(p.nvec << (p.log2n - LR), Geo<KD>::G);
   if (nb == 0) return hipSuccess;
-#define GFP_LAUNCH_R(INV, MODE)                                                                                 \
-  hipLaunchKernelGGL((k_pass_r<KD, W, U, INV, MODE, LR>), dim3(nb), dim3(256), 0, st, p.in, p.in2, p.se_in, p.sd_in, \
-                     p.out, p.se_out, p.sd_out, p.tw, p.log2n, p.nvec, p.vin, p.vout)
+#define GFP_LAUNCH_RB(INV, MODE, BND)                                                                          \
+  hipLaunchKernelGGL((k_pass_r<KD, W, U, INV, MODE, LR, BND>), dim3(nb), dim3(256), 0, st, p.in, p.in2, p.se_in,   \
+                     p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.log2n, p.nvec, p.vin, p.vout, p.in_len)
+#define GFP_LAUNCH_R(INV, MODE) GFP_LAUNCH_RB(INV, MODE, false)
   if (p.in2) GFP_LAUNCH_R(true, MODE_PRODUCT);
   else if (p.scale) GFP_LAUNCH_R(true, MODE_SCALE);
   else if (p.inverse) GFP_LAUNCH_R(true, MODE_PLAIN);
+  else if (p.in_len != ~0ull) GFP_LAUNCH_RB(false, MODE_PLAIN, true);  // a product's first forward launch
   else GFP_LAUNCH_R(false, MODE_PLAIN);
 #undef GFP_LAUNCH_R
+#undef GFP_LAUNCH_RB
   return hipGetLastError();
 }
 
@@ -1371,10 +1395,11 @@ hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
   } else {
   const unsigned nb = blocks_for(p.ngroups * p.nvec, Geo<KD>::G);
   if (nb == 0) return hipSuccess;
-#define GFP_LAUNCH(INV, MODE, LAST, UNIF, T2)                                                                       \
-  hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST, UNIF, T2>), dim3(nb), dim3(256), 0, st, p.in, p.in2, p.se_in,   \
-                     p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.twr1, p.twr2, p.log2n, p.log2ns, p.ngroups,     \
-                     p.nvec, p.vin, p.vout, (int)p.staged)
+#define GFP_LAUNCHB(INV, MODE, LAST, UNIF, T2, BND)                                                                 \
+  hipLaunchKernelGGL((k_pass<KD, W, U, INV, MODE, LAST, UNIF, T2, BND>), dim3(nb), dim3(256), 0, st, p.in, p.in2,      \
+                     p.se_in, p.sd_in, p.out, p.se_out, p.sd_out, p.tw, p.tw2, p.twr1, p.twr2, p.log2n, p.log2ns,      \
+                     p.ngroups, p.nvec, p.vin, p.vout, (int)p.staged, p.in_len)
+#define GFP_LAUNCH(INV, MODE, LAST, UNIF, T2) GFP_LAUNCHB(INV, MODE, LAST, UNIF, T2, false)
   // uniform twiddles when every base a has at least one wavefront of groups;
   // the w^(K i) table for every pass but the last
   const int lk = ilog2(2 * KD);
@@ -1393,11 +1418,16 @@ hipError_t launch_pass_t(const PassArgs& p, hipStream_t st) {
     if (p.last) GFP_LAUNCH(true, MODE_SCALE, true, false, false); else GFP_LAUNCH(true, MODE_SCALE, false, false, false);
   } else if (p.inverse) {
     GFP_LAUNCH_T(true)
+  } else if (p.in_len != ~0ull) {  // a product's first forward launch (Ns = 1): the bounded variant
+    if (p.last || unif) return hipErrorInvalidValue;
+    if (t2) GFP_LAUNCHB(false, MODE_PLAIN, false, false, true, true);
+    else GFP_LAUNCHB(false, MODE_PLAIN, false, false, false, true);
   } else {
     GFP_LAUNCH_T(false)
   }
 #undef GFP_LAUNCH_T
 #undef GFP_LAUNCH
+#undef GFP_LAUNCHB
   return hipGetLastError();
   }
 }
