@@ -44,26 +44,29 @@ def source_hash() -> str:
 
 
 def kernel_key(name: str) -> str:
-    """'void gfpk::k_pass<8, 63, 34, false, 0, true, false>(...)' ->
+    """'void gfpk::k_pass<8, 63, 34, false, 0, true, false, false, false>(...)' ->
     'k_pass<8,63,34,fwd,last>' (',unif' for the uniform-twiddle variant,
-    'inv' and 'scale' for the inverse); the fused pairs likewise as
-    'k_pass2<...>' and 'k_pass2u<...>' (the wide variant)."""
-    m = re.search(r"(k_pass2u?)<(\d+), (\d+), (\d+), (true|false), (\d), (true|false), (true|false)>", name)
+    'inv', 'scale' and 'product' for the inverse, ',bnd' for a product's
+    bounded first forward launch); the fused pairs likewise as 'k_pass2<...>'
+    and 'k_pass2u<...>' (the wide variant)."""
+    def tail(mode, bnd):
+        t = ",scale" if mode == "1" else (",product" if mode == "2" else "")
+        return t + (",bnd" if bnd == "true" else "")
+
+    m = re.search(r"(k_pass2u?)<(\d+), (\d+), (\d+), (true|false), (\d), (true|false), (true|false)"
+                  r"(?:, (true|false))?>", name)
     if m:
-        kern, k, w, u, inv, mode, last, t2 = m.groups()
+        kern, k, w, u, inv, mode, last, t2, bnd = m.groups()
         key = "%s<%s,%s,%s,%s,%s" % (kern, k, w, u, "inv" if inv == "true" else "fwd", "last" if last == "true" else "mid")
-        if mode == "1":
-            key += ",scale"
-        return key + ">"
-    m = re.search(r"k_pass<(\d+), (\d+), (\d+), (true|false), (\d), (true|false), (true|false), (true|false)>", name)
+        return key + tail(mode, bnd) + ">"
+    m = re.search(r"k_pass<(\d+), (\d+), (\d+), (true|false), (\d), (true|false), (true|false), (true|false)"
+                  r"(?:, (true|false))?>", name)
     if m:
-        k, w, u, inv, mode, last, unif, t2 = m.groups()
+        k, w, u, inv, mode, last, unif, t2, bnd = m.groups()
         key = "k_pass<%s,%s,%s,%s,%s" % (k, w, u, "inv" if inv == "true" else "fwd", "last" if last == "true" else "mid")
-        if mode == "1":
-            key += ",scale"
         if unif == "true":
             key += ",unif"
-        return key + ">"
+        return key + tail(mode, bnd) + ">"
     m = re.search(r"(k_\w+)<([^>]*)>", name)
     if m:
         return "%s<%s>" % (m.group(1), m.group(2).replace(" ", ""))
