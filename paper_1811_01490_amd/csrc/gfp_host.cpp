@@ -175,12 +175,6 @@ void to_digits(const gfp_field* f, const Big& v, uint64_t* out) {
   }
 }
 
-Big from_digits(const gfp_field* f, const uint64_t* dg) {
-  Big v;
-  for (uint32_t d = f->k; d-- > 0;) v = gfp::add(gfp::mul_small(v, f->r), Big(dg[d]));
-  return gfp::mod(v, f->p);
-}
-
 // Twiddle-entry layout of the kernels: limbs (22, 22, 20 bits) of every
 // digit, then the suffix sums sum_{t >= i} y_t, i = 0..k (the last is 0), as
 // three 32-bit words each; padded to gfpk::tw_words(k) words.
