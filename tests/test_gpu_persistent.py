@@ -189,3 +189,27 @@ def test_persistent_matches_per_class_on_the_batched_workload_mix(torch_mod):
     torch.cuda.synchronize()
     for i, (x, y) in enumerate(zip(ref, got)):
         assert torch.equal(x, y), (i, sizes[i])
+
+
+@pytest.mark.parametrize("params,sizes", [
+    (P8, [(2 ** 15, 2 ** 15), (40000, 30000), (2 ** 19 - 7, 1000), (70000, 3)]),
+    (P16, [(2 ** 15, 2 ** 15), (100000, 30000), (2 ** 19, 2 ** 19 - 9)]),
+], ids=["k8", "k16"])
+def test_bounded_first_launch_matches_full_padding(torch_mod, params, sizes):
+    """From transform size 2^16 on, a product pads its operands only up to the
+    longest one and its first forward launch (a pair, the wide pair, a single
+    pass or the radix-R pass, by size) reads nothing past it; the persistent
+    launch pads in full.  Both must give the same products, with operands of
+    very different lengths."""
+    import torch
+
+    from paper_1811_01490_amd import Field
+
+    f = Field(params["k"], params["r"])
+    print("bounded first launch", params["k"], sizes, flush=True)
+    _, dev = _batch(params, sizes, gi.BASE_SEED + 326)
+    got = _outs(torch, params["k"], dev, fill=7)
+    f.polymul_batched(f.batch_descs([(a, b, c) for (a, b), c in zip(dev, got)]), persistent=True)
+    torch.cuda.synchronize()
+    for i, ((a, b), c) in enumerate(zip(dev, got)):
+        assert torch.equal(f.polymul(a, b), c), (i, sizes[i])
